@@ -1,0 +1,6 @@
+"""CPU oracle of the rasterizer path (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product path (the HIP library and its binding)
+never imports or calls it, and shares no code with it.
+"""
