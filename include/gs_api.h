@@ -1,0 +1,232 @@
+/*
+ * gs_api.h -- C ABI of the MI355X (gfx950) differentiable Gaussian-splatting
+ * rasterizer that every joint camera-pose / Gaussian optimisation step runs
+ * forward and backward (paper section 4.3: 30 such iterations per keyframe,
+ * sparse Adam on the Gaussians, poses optimised jointly and receiving
+ * gradient through Gaussian position and rotation but not through the
+ * spherical harmonics), plus the primitive-spawning step of section 4.2.
+ *
+ * The rasterizer is the EWA splatting model of the 3DGS codebase the paper
+ * builds on (section 5): Gaussians with mean, log-scales, rotation
+ * quaternion, opacity logit and SH colour are projected to 2D Gaussians, and
+ * every pixel composites them front to back in depth order until its
+ * transmittance would fall below a cutoff.
+ *
+ * Conventions that hold for every entry point:
+ *   * Memory.  Every array argument is caller-owned DEVICE memory unless it is
+ *     marked "host".  The library never allocates device memory; scratch
+ *     comes in through workspace arguments whose sizes the *_workspace
+ *     queries return.  Arrays are float32 structure-of-arrays planes: a
+ *     parameter with k components over n Gaussians is k contiguous planes of
+ *     n values ("[k][n]").
+ *   * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Every
+ *     call is asynchronous on it, except where a call says it synchronises.
+ *   * Errors.  Arguments are checked on the host before anything is
+ *     launched; a failed check launches nothing and returns
+ *     GS_ERR_INVALID_ARG.  A failed HIP call returns GS_ERR_HIP.
+ *     gs_last_error() returns a thread-local text for the last non-OK status.
+ *     No C++ exception crosses the ABI.
+ *   * Gradients accumulate (+=) into caller buffers, so several views can
+ *     be summed; the caller zeroes them.
+ *   * Camera.  World->camera pose [R | t] with R row-major; the camera looks
+ *     down +z; pixel (u, v) is sampled at the continuous point (u, v); the
+ *     projected mean is (fx x/z + cx, fy y/z + cy).
+ *   * Thread safety.  Entry points may be called from several host threads
+ *     on different streams, except the profiling switches.
+ */
+#ifndef GS_API_H
+#define GS_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARG = 1, /* bad pointer, size, degree, ...; nothing launched */
+  GS_ERR_CAPACITY = 2,    /* an output is too small; the required size is returned */
+  GS_ERR_HIP = 3,         /* a HIP runtime call failed */
+  GS_ERR_WORKSPACE = 4    /* the workspace is smaller than the query returned */
+} gs_status;
+
+/* Tile edge in pixels; the render kernels map one 16x16 tile to one
+ * 256-lane workgroup (four wave64). */
+#define GS_TILE 16
+
+/* Render record written by gs_project, one per Gaussian, 12 floats (48 B):
+ *   [0] mean_x integer part   [1] mean_y integer part   (exact integers)
+ *   [2] mean_x - [0]          [3] mean_y - [1]          (in [-0.5, 0.5])
+ *   [4] A  [5] B  [6] C       conic: inverse 2D covariance [[A, B], [B, C]]
+ *   [7] opacity o = sigmoid(logit)
+ *   [8] [9] [10] colour (r, g, b) from SH, clamped below at 0
+ *   [11] depth z of the camera-space mean (positive)
+ * The split mean keeps the offset to a pixel exact to ~1e-7 px at any image
+ * size.  The FP32 mean used for binning is the sum of the two parts rounded
+ * once: mean_x = fl(rec[0] + rec[2]), mean_y = fl(rec[1] + rec[3]). */
+#define GS_REC_FLOATS 12
+
+typedef struct {
+  int32_t width, height;    /* image size in pixels, 1 .. 16384 */
+  float fx, fy, cx, cy;     /* pinhole intrinsics in pixels, fx, fy > 0 */
+  float near_plane;         /* Gaussians with camera depth <= near are culled */
+  float bg[3];              /* background colour composited behind everything */
+  const float *pose;        /* DEVICE [12]: R (row-major 3x3) then t (3), world->camera */
+} gs_camera;                /* passed by pointer to HOST memory */
+
+typedef struct {
+  float eps2d;     /* dilation added to the 2D covariance's diagonal (0.3) */
+  float alpha_max; /* opacity clamp of a single Gaussian at a pixel (0.99) */
+  float alpha_min; /* smaller alphas are skipped (1/255) */
+  float t_min;     /* a pixel stops before transmittance would drop below this (1e-4) */
+  float guard;     /* guard band of the perspective Jacobian, in half-FOVs (1.3) */
+} gs_raster_params;  /* HOST memory */
+
+typedef struct {
+  int64_t n;          /* number of Gaussians, 0 .. 2^31 - 1 */
+  int32_t sh_degree;  /* 0 .. 3 */
+  float *means;          /* [3][n] world-space mean */
+  float *log_scales;     /* [3][n] log of the per-axis standard deviation */
+  float *quats;          /* [4][n] rotation (w, x, y, z), normalised inside */
+  float *opacity_logits; /* [n]    opacity = sigmoid(logit) */
+  float *sh;             /* [(deg+1)^2][3][n] SH coefficients per colour channel */
+} gs_gaussians;          /* HOST struct of DEVICE pointers */
+
+typedef struct {
+  float *rec;             /* [n][GS_REC_FLOATS] render records (layout above) */
+  int32_t *radius;        /* [n] pixel radius of the support square, 0 = culled */
+  int32_t *tiles_touched; /* [n] number of 16x16 tiles the support square meets */
+} gs_projected;           /* HOST struct of DEVICE pointers */
+
+/* Fills *p with the constants above (0.3, 0.99, 1/255, 1e-4, 1.3). */
+void gs_default_params(gs_raster_params *p);
+
+const char *gs_last_error(void);
+
+/* ---- gs_project ---------------------------------------------------------
+ * Per-Gaussian EWA projection (the rasterizer of section 5 / 3DGS):
+ *   p = R mean + t; culled if p_z <= near;
+ *   J = perspective Jacobian at p, with x/z and y/z clamped to +-guard
+ *       half-FOVs (guard band);
+ *   Sigma = Rq diag(exp(2 log_scales)) Rq^T, Rq from the normalised quaternion;
+ *   Sigma2 = J R Sigma R^T J^T + eps2d I; conic = Sigma2^-1;
+ *   colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = unit(mean - camera
+ *   centre), real SH up to degree 3;
+ *   o = sigmoid(logit); culled if o < alpha_min;
+ *   radius = ceil(r (1 + 1e-4) + 1e-3), r = sqrt(2 ln(o / alpha_min)
+ *   lambda_max(Sigma2)), the extent of the region where o exp(-d^T conic d / 2)
+ *   >= alpha_min; tiles_touched counts the tiles holding an integer pixel of
+ *   the clipped square [mean - radius, mean + radius]^2.
+ * Geometry is evaluated in FP64 and stored in FP32.  Culled Gaussians get
+ * radius = tiles_touched = 0 and zeroed records.
+ * Errors: GS_ERR_INVALID_ARG for NULL pointers (n > 0), n < 0, degree out of
+ * range, non-positive sizes or focal lengths. */
+gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g, gs_projected *out,
+                     void *stream);
+
+/* ---- gs_bin_sort --------------------------------------------------------
+ * Builds the per-tile depth-ordered lists: every (Gaussian, tile) pair of
+ * gs_project's support squares, ordered by tile id (row-major tiles,
+ * tiles_x = ceil(W/16)), then by the FP32 depth, then by Gaussian index.
+ * That is the order of a stable sort of the key (tile << 32 | bits(depth))
+ * over pairs emitted in Gaussian-index order.  Implemented as a stable LSD
+ * radix sort of the visible Gaussians by depth followed by a stable LSD
+ * radix sort of the emitted pairs by tile.
+ *   tile_ids [capacity]  out: tile id of each sorted pair
+ *   values   [capacity]  out: Gaussian index of each sorted pair
+ *   ranges   [T][2]      out: [start, end) of each tile's run (0,0 if empty)
+ *   n_instances (HOST)   out: the number M of pairs
+ * Synchronises the stream once (8-byte read of M).  If M > capacity it
+ * returns GS_ERR_CAPACITY with *n_instances = M and writes no list output.
+ * ws must be at least gs_bin_sort_workspace(n, capacity) bytes. */
+gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t *bytes);
+gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
+                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *ranges, int64_t *n_instances,
+                      void *stream);
+
+/* ---- gs_render_fwd ------------------------------------------------------
+ * Front-to-back compositing per pixel over its tile's list: with
+ * d = pixel - mean, alpha = min(alpha_max, o exp(-d^T conic d / 2));
+ * alpha < alpha_min is skipped; if T (1 - alpha) < t_min the pixel stops
+ * without this Gaussian; otherwise C += colour alpha T, D += z alpha T,
+ * T *= 1 - alpha.  Outputs, all [H][W] planes (image [3][H][W]):
+ *   image = C + T bg, depth = D (not normalised), alpha = 1 - T,
+ *   final_t = T, n_contrib = list entries up to and including the last one
+ *   composited (counted from the tile's start; state for the backward),
+ *   n_examined = entries tested before the stop (NULL = not written).
+ * values / ranges from gs_bin_sort. */
+gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                        const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,
+                        float *final_t, int32_t *n_contrib, int32_t *n_examined, void *stream);
+
+/* ---- gs_render_bwd ------------------------------------------------------
+ * Adjoint of gs_project + gs_render_fwd for upstream gradients of image
+ * [3][H][W], depth [H][W] and alpha [H][W] (dL_ddepth / dL_dalpha may be
+ * NULL = zero).  image, depth, final_t and n_contrib must be the forward's
+ * outputs for the same inputs.  Accumulates into grads (same layout as g;
+ * grads->n and sh_degree must match g) and, if not NULL, into
+ *   dL_dpose  [12] (double) gradient w.r.t. R (row-major) and t,
+ *   dL_dtwist [6]  (double) gradient w.r.t. a left twist (rho, phi):
+ *                  T <- exp(xi^) T, rho the translation part.
+ * The pose gradient flows through the projected mean, depth and covariance
+ * only, not through the SH view direction (section 4.3).  The Gaussian
+ * gradients include the view-direction path.  Decisions (skip, stop, alpha
+ * clamp, colour clamp, guard band) are held fixed: the clamp's derivative
+ * is zero.  ws: gs_render_bwd_workspace(n) bytes. */
+gs_status gs_render_bwd_workspace(int64_t n, size_t *bytes);
+gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
+                        const gs_projected *proj, const uint32_t *values, const uint32_t *ranges, const float *image,
+                        const float *depth, const float *final_t, const int32_t *n_contrib, const float *dL_dimage,
+                        const float *dL_ddepth, const float *dL_dalpha, gs_gaussians *grads, double *dL_dpose,
+                        double *dL_dtwist, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- loss, metrics and optimiser (helpers of the joint optimisation) ----
+ * gs_loss_l1: over count values, sums[0] = sum |image - target|,
+ * sums[1] = sum (image - target)^2 (double, DEVICE, overwritten), and if
+ * dL_dimage is not NULL, dL_dimage = grad_scale * sign(image - target)
+ * (sign(0) = 0).  ws: gs_loss_workspace(count) bytes. */
+gs_status gs_loss_workspace(int64_t count, size_t *bytes);
+gs_status gs_loss_l1(const float *image, const float *target, int64_t count, float grad_scale, float *dL_dimage,
+                     double *sums, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on count floats:
+ *   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * Sparse form (section 4.3, sparse Adam): if visible is not NULL, element e
+ * belongs to Gaussian e % n_stride and is left untouched (p, m, v) unless
+ * visible[e % n_stride] != 0. */
+gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,
+                       float beta2, float eps, int32_t step, const int32_t *visible, int64_t n_stride,
+                       void *stream);
+
+/* Pose from the continuous 6D rotation representation used for the camera
+ * poses (section 4.3): x [V][9] = (a1, a2, t); R's columns are
+ * b1 = a1/|a1|, b2 = unit(a2 - (b1.a2) b1), b3 = b1 x b2; pose [V][12] =
+ * (R row-major, t).  gs_pose_6d_bwd maps dL/dpose [V][12] (double) to
+ * dL/dx [V][9] (float, accumulated). */
+gs_status gs_pose_from_6d(const float *x, float *pose, int32_t n_views, void *stream);
+gs_status gs_pose_6d_bwd(const float *x, const double *dL_dpose, float *dL_dx, int32_t n_views, void *stream);
+
+/* Zero `bytes` bytes of device memory with a kernel (no memset node, so the
+ * call can sit inside a captured graph). */
+gs_status gs_zero(void *ptr, size_t bytes, void *stream);
+
+/* mask[i] |= (tiles_touched[i] > 0) over n Gaussians: the set a step
+ * processed, which the sparse Adam step of section 4.3 updates. */
+gs_status gs_mark_visible(const int32_t *tiles_touched, int64_t n, int32_t *mask, void *stream);
+
+/* ---- profiling ----------------------------------------------------------
+ * When enabled, every kernel launch is bracketed with HIP events on its
+ * stream; gs_profile_read sums the elapsed milliseconds of all launches of
+ * the named kernel since the last reset (synchronising on its events).
+ * Not thread-safe. */
+void gs_profile_enable(int on);
+void gs_profile_reset(void);
+gs_status gs_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_API_H */

@@ -362,13 +362,6 @@ typedef struct {
 
 static int cmp_depth_index(const void *pa, const void *pb, void *ctx);
 
-/* ulp of a positive double rounded to binary32 */
-static double f32_ulp(double z) {
-  int e;
-  frexp(z, &e); /* z = m 2^e, m in [0.5, 1) */
-  return ldexp(1.0, e - 24);
-}
-
 /* Evaluate Gaussian k of the list at pixel (u, v). */
 static inline void eval_pair(const orc_proj *pr, int64_t n, int64_t i, double u, double v, double *dx, double *dy,
                              double *sexp, double *raw) {
@@ -395,7 +388,7 @@ static void *render_fwd_worker(void *arg) {
       const double u = jb->x0 + rx, v = jb->y0 + ry;
       double T = 1.0, col[3] = {0, 0, 0}, D = 0.0;
       int ncomp = 0, nsup = 0, flag = 0;
-      double last_z = -1.0;
+      int64_t prev = -1; /* previous entry with alpha >= alpha_min */
       for (int64_t k = 0; k < jb->n_order; ++k) {
         const int64_t i = jb->order[k];
         const double rb = pr->radius[i] + 1.0;
@@ -407,12 +400,15 @@ static void *render_fwd_worker(void *arg) {
         const double alpha = raw < cam->alpha_max ? raw : cam->alpha_max;
         if (alpha < cam->alpha_min) continue;
         ++nsup;
+        /* An implementation that orders by the binary32 rounding of the depth
+           (ties by index) differs from (depth, index) order only where two
+           roundings tie and the index order runs against the depth order. */
+        if (prev >= 0 && (float)pr->depth[prev] == (float)pr->depth[i] && prev > i) flag |= 8;
+        prev = i;
         const double Tn = T * (1.0 - alpha);
         if (fabs(Tn - cam->t_min) <= fr * cam->t_min) flag |= 4;
         if (Tn < cam->t_min) break;
         const double z = pr->depth[i];
-        if (last_z >= 0.0 && fabs(z - last_z) <= 4.0 * f32_ulp(z)) flag |= 8;
-        last_z = z;
         const double w = alpha * T;
         for (int c = 0; c < 3; ++c) col[c] += pr->rgb[c * n + i] * w;
         D += z * w;

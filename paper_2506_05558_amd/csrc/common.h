@@ -1,0 +1,127 @@
+// Internal helpers shared by the HIP translation units of libgsmi.
+// gfx950 only: wave64, DPP cross-lane ops, hardware float atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gs_api.h"
+
+namespace gsmi {
+
+// ---------------------------------------------------------------- host side
+void set_error(const char *fmt, ...);
+gs_status hip_fail(hipError_t e, const char *what);
+
+// Launch bracket: records profiling events around a kernel when enabled.
+struct ProfScope {
+  const char *name;
+  hipStream_t stream;
+  int slot;
+  ProfScope(const char *name, hipStream_t s);
+  ~ProfScope();
+};
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Launch helper that checks the launch and returns a status.
+#define GS_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                   \
+  do {                                                                            \
+    ::gsmi::ProfScope _ps(name, stream);                                          \
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__); \
+    hipError_t _e = hipGetLastError();                                            \
+    if (_e != hipSuccess) return ::gsmi::hip_fail(_e, name);                      \
+  } while (0)
+
+#define GS_CHECK_HIP(call, what)                        \
+  do {                                                  \
+    hipError_t _e = (call);                             \
+    if (_e != hipSuccess) return ::gsmi::hip_fail(_e, what); \
+  } while (0)
+
+#define GS_REQUIRE(cond, ...)              \
+  do {                                     \
+    if (!(cond)) {                         \
+      ::gsmi::set_error(__VA_ARGS__);      \
+      return GS_ERR_INVALID_ARG;           \
+    }                                      \
+  } while (0)
+
+inline int tiles_x_of(int w) { return (w + GS_TILE - 1) / GS_TILE; }
+inline int tiles_y_of(int h) { return (h + GS_TILE - 1) / GS_TILE; }
+
+// Workspace carving: bump allocator over a caller buffer.
+struct Carve {
+  char *base;
+  size_t off;
+  explicit Carve(void *p) : base((char *)p), off(0) {}
+  template <class T>
+  T *take(size_t count) {
+    T *p = (T *)(base ? base + off : nullptr);
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+// Scan / radix sort building blocks (binning.hip).
+size_t scan_workspace(int64_t count);
+gs_status scan_exclusive(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total, void *ws,
+                         hipStream_t s);
+
+// -------------------------------------------------------------- device side
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
+                                                               0xf, false));
+}
+
+// Sum over the 64 lanes of a wave; the full sum is valid in lane 63.  Every
+// lane must be active.  Row (16-lane) rotations first, then the two
+// cross-row broadcasts.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_mov<0x128, 0xf>(v);  // row_ror:8
+  v += dpp_mov<0x124, 0xf>(v);  // row_ror:4
+  v += dpp_mov<0x122, 0xf>(v);  // row_ror:2
+  v += dpp_mov<0x121, 0xf>(v);  // row_ror:1
+  v += dpp_mov<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Inclusive tile rect of a support square, in FP32 with one rounding per
+// bound (mean -/+ radius), then ceil/floor, clipping and integer division.
+// Returns false when the square holds no pixel of the image.
+__device__ __forceinline__ bool tile_rect(float mx, float my, int radius, int W, int H, int &tx0, int &ty0,
+                                          int &tx1, int &ty1) {
+  if (radius <= 0) return false;
+  const float r = (float)radius;
+  const float fu0 = fmaxf(ceilf(__fsub_rn(mx, r)), 0.0f);
+  const float fu1 = fminf(floorf(__fadd_rn(mx, r)), (float)(W - 1));
+  const float fv0 = fmaxf(ceilf(__fsub_rn(my, r)), 0.0f);
+  const float fv1 = fminf(floorf(__fadd_rn(my, r)), (float)(H - 1));
+  if (!(fu0 <= fu1) || !(fv0 <= fv1)) return false;
+  tx0 = (int)fu0 / GS_TILE;
+  tx1 = (int)fu1 / GS_TILE;
+  ty0 = (int)fv0 / GS_TILE;
+  ty1 = (int)fv1 / GS_TILE;
+  return true;
+}
+
+// Map workgroup b of a grid of nb to a logical tile so that each of the 8
+// XCDs (workgroups are dealt round-robin) walks one contiguous band of tiles
+// and neighbouring tiles, which share Gaussians, hit the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int per = nb / 8;  // nb is padded to a multiple of 8
+  return (b % 8) * per + b / 8;
+}
+
+}  // namespace gsmi

@@ -1,0 +1,245 @@
+// Photometric loss, Adam and the 6D pose parametrisation used by the joint
+// pose + Gaussian optimisation (section 4.3).
+#include "common.h"
+
+namespace gsmi {
+namespace {
+
+constexpr int kLossBlock = 256;
+constexpr int kLossMaxBlocks = 1024;
+
+__global__ __launch_bounds__(kLossBlock) void k_loss_l1(const float *img, const float *tgt, int64_t count,
+                                                        float scale, float *grad, double *partials) {
+  double s1 = 0.0, s2 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kLossBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kLossBlock + threadIdx.x; i < count; i += stride) {
+    const float d = img[i] - tgt[i];
+    s1 += fabs((double)d);
+    s2 += (double)d * (double)d;
+    if (grad) grad[i] = d > 0.f ? scale : (d < 0.f ? -scale : 0.f);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s1 += __shfl_down(s1, off, 64);
+    s2 += __shfl_down(s2, off, 64);
+  }
+  __shared__ double red[kLossBlock / 64][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[w][0] = s1;
+    red[w][1] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < kLossBlock / 64; ++k) {
+      a += red[k][0];
+      b += red[k][1];
+    }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_loss_final(const double *partials, int nparts, double *sums) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 64) {
+    a += partials[2 * k];
+    b += partials[2 * k + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    sums[0] = a;
+    sums[1] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
+                                              float b1, float b2, float eps, float c1, float c2,
+                                              const int32_t *visible, int64_t n_stride) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  if (visible && !visible[i % n_stride]) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// R's columns from the two 3-vectors of the 6D representation.
+__device__ void gram_schmidt(const float *x, double b1[3], double b2[3], double b3[3], double &n1, double &n2,
+                             double u2[3]) {
+  const double a1[3] = {x[0], x[1], x[2]}, a2[3] = {x[3], x[4], x[5]};
+  n1 = sqrt(a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2]);
+  for (int k = 0; k < 3; ++k) b1[k] = a1[k] / n1;
+  const double d = b1[0] * a2[0] + b1[1] * a2[1] + b1[2] * a2[2];
+  for (int k = 0; k < 3; ++k) u2[k] = a2[k] - d * b1[k];
+  n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  for (int k = 0; k < 3; ++k) b2[k] = u2[k] / n2;
+  b3[0] = b1[1] * b2[2] - b1[2] * b2[1];
+  b3[1] = b1[2] * b2[0] - b1[0] * b2[2];
+  b3[2] = b1[0] * b2[1] - b1[1] * b2[0];
+}
+
+__global__ void k_pose_from_6d(const float *x, float *pose, int nv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const float *xi = x + 9 * i;
+  double b1[3], b2[3], b3[3], n1, n2, u2[3];
+  gram_schmidt(xi, b1, b2, b3, n1, n2, u2);
+  float *P = pose + 12 * i;
+  for (int r = 0; r < 3; ++r) {
+    P[3 * r] = (float)b1[r];
+    P[3 * r + 1] = (float)b2[r];
+    P[3 * r + 2] = (float)b3[r];
+  }
+  for (int k = 0; k < 3; ++k) P[9 + k] = xi[6 + k];
+}
+
+// Adjoint of the Gram-Schmidt map: from dL/dR (columns g1, g2, g3) to dL/da1, dL/da2.
+__global__ void k_pose_6d_bwd(const float *x, const double *dpose, float *dx, int nv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const float *xi = x + 9 * i;
+  const double *G = dpose + 12 * i;
+  double b1[3], b2[3], b3[3], n1, n2, u2[3];
+  gram_schmidt(xi, b1, b2, b3, n1, n2, u2);
+  double g1[3], g2[3], g3[3];
+  for (int r = 0; r < 3; ++r) {
+    g1[r] = G[3 * r];
+    g2[r] = G[3 * r + 1];
+    g3[r] = G[3 * r + 2];
+  }
+  // b3 = b1 x b2: dL/db1 += b2 x g3, dL/db2 += g3 x b1
+  g1[0] += b2[1] * g3[2] - b2[2] * g3[1];
+  g1[1] += b2[2] * g3[0] - b2[0] * g3[2];
+  g1[2] += b2[0] * g3[1] - b2[1] * g3[0];
+  g2[0] += g3[1] * b1[2] - g3[2] * b1[1];
+  g2[1] += g3[2] * b1[0] - g3[0] * b1[2];
+  g2[2] += g3[0] * b1[1] - g3[1] * b1[0];
+  // b2 = u2 / |u2|: dL/du2 = (g2 - b2 (b2.g2)) / |u2|
+  const double p2 = b2[0] * g2[0] + b2[1] * g2[1] + b2[2] * g2[2];
+  double gu[3];
+  for (int k = 0; k < 3; ++k) gu[k] = (g2[k] - b2[k] * p2) / n2;
+  // u2 = a2 - (b1.a2) b1: dL/da2 = gu - b1 (b1.gu); dL/db1 += -(b1.a2) gu - (b1.gu) a2
+  const double a2[3] = {xi[3], xi[4], xi[5]};
+  const double bgu = b1[0] * gu[0] + b1[1] * gu[1] + b1[2] * gu[2];
+  const double ba2 = b1[0] * a2[0] + b1[1] * a2[1] + b1[2] * a2[2];
+  for (int k = 0; k < 3; ++k) {
+    dx[9 * i + 3 + k] += (float)(gu[k] - b1[k] * bgu);
+    g1[k] += -ba2 * gu[k] - bgu * a2[k];
+  }
+  // b1 = a1 / |a1|
+  const double p1 = b1[0] * g1[0] + b1[1] * g1[1] + b1[2] * g1[2];
+  for (int k = 0; k < 3; ++k) dx[9 * i + k] += (float)((g1[k] - b1[k] * p1) / n1);
+  for (int k = 0; k < 3; ++k) dx[9 * i + 6 + k] += (float)G[9 + k];
+}
+
+__global__ void k_zero_words(uint32_t *p, int64_t words) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) p[i] = 0u;
+}
+
+__global__ void k_zero_bytes(uint8_t *p, int64_t bytes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < bytes) p[i] = 0u;
+}
+
+__global__ void k_mark_visible(const int32_t *tiles, int64_t n, int32_t *mask) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && tiles[i] > 0) mask[i] = 1;
+}
+
+}  // namespace
+}  // namespace gsmi
+
+using namespace gsmi;
+
+extern "C" {
+
+gs_status gs_loss_workspace(int64_t count, size_t *bytes) {
+  GS_REQUIRE(bytes && count >= 0, "gs_loss_workspace: bad argument");
+  *bytes = align_up(sizeof(double) * 2 * kLossMaxBlocks);
+  return GS_OK;
+}
+
+gs_status gs_loss_l1(const float *image, const float *target, int64_t count, float grad_scale, float *dL_dimage,
+                     double *sums, void *ws, size_t ws_bytes, void *stream) {
+  GS_REQUIRE(count >= 0 && sums, "gs_loss_l1: bad argument");
+  if (count > 0) GS_REQUIRE(image && target, "gs_loss_l1: NULL image or target");
+  size_t need = 0;
+  gs_loss_workspace(count, &need);
+  if (ws_bytes < need || !ws) {
+    set_error("gs_loss_l1: workspace %zu bytes < %zu", ws_bytes, need);
+    return GS_ERR_WORKSPACE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int64_t blocks = (count + kLossBlock - 1) / kLossBlock;
+  if (blocks > kLossMaxBlocks) blocks = kLossMaxBlocks;
+  if (blocks < 1) blocks = 1;
+  GS_LAUNCH("loss_l1", k_loss_l1, blocks, kLossBlock, 0, s, image, target, count, grad_scale, dL_dimage,
+            (double *)ws);
+  GS_LAUNCH("loss_final", k_loss_final, 1, 64, 0, s, (const double *)ws, (int)blocks, sums);
+  return GS_OK;
+}
+
+gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,
+                       float beta2, float eps, int32_t step, const int32_t *visible, int64_t n_stride,
+                       void *stream) {
+  GS_REQUIRE(count >= 0 && step >= 1, "gs_adam_step: bad count or step");
+  GS_REQUIRE(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f, "gs_adam_step: bad betas");
+  if (count == 0) return GS_OK;
+  GS_REQUIRE(param && grad && m && v, "gs_adam_step: NULL argument");
+  if (visible) GS_REQUIRE(n_stride > 0, "gs_adam_step: n_stride must be positive with a visibility mask");
+  const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+  const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+  GS_LAUNCH("adam", k_adam, (count + 255) / 256, 256, 0, (hipStream_t)stream, param, grad, m, v, count, lr, beta1,
+            beta2, eps, c1, c2, visible, n_stride);
+  return GS_OK;
+}
+
+gs_status gs_zero(void *ptr, size_t bytes, void *stream) {
+  if (bytes == 0) return GS_OK;
+  GS_REQUIRE(ptr, "gs_zero: NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  if (((uintptr_t)ptr % 4) == 0 && bytes % 4 == 0) {
+    const int64_t words = (int64_t)(bytes / 4);
+    GS_LAUNCH("zero", k_zero_words, (words + 255) / 256, 256, 0, s, (uint32_t *)ptr, words);
+  } else {
+    GS_LAUNCH("zero", k_zero_bytes, ((int64_t)bytes + 255) / 256, 256, 0, s, (uint8_t *)ptr, (int64_t)bytes);
+  }
+  return GS_OK;
+}
+
+gs_status gs_mark_visible(const int32_t *tiles_touched, int64_t n, int32_t *mask, void *stream) {
+  GS_REQUIRE(n >= 0, "gs_mark_visible: n < 0");
+  if (n == 0) return GS_OK;
+  GS_REQUIRE(tiles_touched && mask, "gs_mark_visible: NULL argument");
+  GS_LAUNCH("mark_visible", k_mark_visible, (n + 255) / 256, 256, 0, (hipStream_t)stream, tiles_touched, n, mask);
+  return GS_OK;
+}
+
+gs_status gs_pose_from_6d(const float *x, float *pose, int32_t n_views, void *stream) {
+  GS_REQUIRE(n_views >= 0, "gs_pose_from_6d: n_views < 0");
+  if (n_views == 0) return GS_OK;
+  GS_REQUIRE(x && pose, "gs_pose_from_6d: NULL argument");
+  GS_LAUNCH("pose_6d", k_pose_from_6d, (n_views + 63) / 64, 64, 0, (hipStream_t)stream, x, pose, n_views);
+  return GS_OK;
+}
+
+gs_status gs_pose_6d_bwd(const float *x, const double *dL_dpose, float *dL_dx, int32_t n_views, void *stream) {
+  GS_REQUIRE(n_views >= 0, "gs_pose_6d_bwd: n_views < 0");
+  if (n_views == 0) return GS_OK;
+  GS_REQUIRE(x && dL_dpose && dL_dx, "gs_pose_6d_bwd: NULL argument");
+  GS_LAUNCH("pose_6d_bwd", k_pose_6d_bwd, (n_views + 63) / 64, 64, 0, (hipStream_t)stream, x, dL_dpose, dL_dx,
+            n_views);
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,417 @@
+"""Python binding of libgsmi (the HIP rasterizer).  Argument marshalling only.
+
+Every step runs in the library's HIP kernels; torch provides device memory
+and the current stream.  Importing this module raises if the library has not
+been built: there is no CPU or PyTorch fallback.
+
+Names follow the C ABI in include/gs_api.h: project, bin_sort, render_fwd,
+render_bwd, loss_l1, adam_step, pose_from_6d, pose_6d_bwd; ``rasterize`` is
+the differentiable composition of the first four as a torch.autograd.Function
+returning Gaussian and camera-pose gradients.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsmi.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(python paper_2506_05558_amd/build.py); there is no fallback")
+_lib = C.CDLL(LIB_PATH)
+
+GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_WORKSPACE = range(5)
+TILE = 16
+REC_FLOATS = 12
+
+
+class GsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gsmi status {status}: {msg}")
+        self.status = status
+
+
+class _Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("near_plane", C.c_float), ("bg", C.c_float * 3),
+                ("pose", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("eps2d", C.c_float), ("alpha_max", C.c_float), ("alpha_min", C.c_float), ("t_min", C.c_float),
+                ("guard", C.c_float)]
+
+
+class _Gauss(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p), ("log_scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class _Proj(C.Structure):
+    _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles_touched", C.c_void_p)]
+
+
+_vp, _i64, _i32, _f, _sz = C.c_void_p, C.c_int64, C.c_int32, C.c_float, C.c_size_t
+_P = C.POINTER
+_sig = {
+    "gs_default_params": (None, [_P(_Params)]),
+    "gs_last_error": (C.c_char_p, []),
+    "gs_project": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp]),
+    "gs_bin_sort_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
+    "gs_bin_sort": (C.c_int, [_P(_Camera), _P(_Proj), _i64, _i64, _vp, _sz, _vp, _vp, _vp, _P(_i64), _vp]),
+    "gs_render_fwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp]),
+    "gs_render_bwd_workspace": (C.c_int, [_i64, _P(_sz)]),
+    "gs_render_bwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _vp, _P(_Gauss), _vp, _vp, _vp, _sz, _vp]),
+    "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
+    "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
+    "gs_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _i64, _vp]),
+    "gs_pose_from_6d": (C.c_int, [_vp, _vp, _i32, _vp]),
+    "gs_pose_6d_bwd": (C.c_int, [_vp, _vp, _vp, _i32, _vp]),
+    "gs_zero": (C.c_int, [_vp, _sz, _vp]),
+    "gs_mark_visible": (C.c_int, [_vp, _i64, _vp, _vp]),
+    "gs_profile_enable": (None, [C.c_int]),
+    "gs_profile_reset": (None, []),
+    "gs_profile_read": (C.c_int, [C.c_char_p, _P(C.c_double), _P(_i64)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def exported_symbols():
+    return sorted(_sig)
+
+
+def _check(status):
+    if status != GS_OK:
+        raise GsError(status, _lib.gs_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _require(t: torch.Tensor, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name}: expected contiguous CUDA {dtype} {tuple(shape)}, got {t.dtype} "
+                         f"{tuple(t.shape)} contiguous={t.is_contiguous()} device={t.device}")
+
+
+@dataclass
+class Params:
+    eps2d: float = 0.3
+    alpha_max: float = 0.99
+    alpha_min: float = 1.0 / 255.0
+    t_min: float = 1e-4
+    guard: float = 1.3
+
+    def c(self):
+        return _Params(self.eps2d, self.alpha_max, self.alpha_min, self.t_min, self.guard)
+
+
+@dataclass
+class Camera:
+    """Pinhole intrinsics (host) and a world->camera pose [12] on the device."""
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    pose: torch.Tensor  # float32 [12] = R row-major (9), t (3)
+    near_plane: float = 0.2
+    bg: tuple = (0.0, 0.0, 0.0)
+
+    @property
+    def tiles_x(self):
+        return (self.width + TILE - 1) // TILE
+
+    @property
+    def tiles_y(self):
+        return (self.height + TILE - 1) // TILE
+
+    def c(self):
+        _require(self.pose, torch.float32, (12,), "camera pose")
+        return _Camera(self.width, self.height, self.fx, self.fy, self.cx, self.cy, self.near_plane,
+                       (C.c_float * 3)(*self.bg), self.pose.data_ptr())
+
+
+@dataclass
+class Gaussians:
+    """SoA parameter planes on the device (float32)."""
+    means: torch.Tensor  # (3, N)
+    log_scales: torch.Tensor  # (3, N)
+    quats: torch.Tensor  # (4, N)
+    opacity_logits: torch.Tensor  # (N,)
+    sh: torch.Tensor  # ((d+1)^2, 3, N)
+
+    @property
+    def n(self):
+        return int(self.means.shape[1])
+
+    @property
+    def sh_degree(self):
+        return int(round(self.sh.shape[0] ** 0.5)) - 1
+
+    def tensors(self):
+        return [self.means, self.log_scales, self.quats, self.opacity_logits, self.sh]
+
+    def c(self):
+        n, d = self.n, self.sh_degree
+        _require(self.means, torch.float32, (3, n), "means")
+        _require(self.log_scales, torch.float32, (3, n), "log_scales")
+        _require(self.quats, torch.float32, (4, n), "quats")
+        _require(self.opacity_logits, torch.float32, (n,), "opacity_logits")
+        _require(self.sh, torch.float32, ((d + 1) ** 2, 3, n), "sh")
+        return _Gauss(n, d, *[t.data_ptr() for t in self.tensors()])
+
+    def zeros_like(self):
+        return Gaussians(*[torch.zeros_like(t) for t in self.tensors()])
+
+    @staticmethod
+    def from_arrays(d: dict, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).contiguous().to(device)
+        return Gaussians(f(d["means"]), f(d["log_scales"]), f(d["quats"]), f(d["opacity_logits"]), f(d["sh"]))
+
+
+@dataclass
+class Projected:
+    rec: torch.Tensor  # (N, 12)
+    radius: torch.Tensor  # (N,) int32
+    tiles_touched: torch.Tensor  # (N,) int32
+
+    def c(self):
+        return _Proj(self.rec.data_ptr(), self.radius.data_ptr(), self.tiles_touched.data_ptr())
+
+
+def default_params() -> Params:
+    p = _Params()
+    _lib.gs_default_params(C.byref(p))
+    return Params(p.eps2d, p.alpha_max, p.alpha_min, p.t_min, p.guard)
+
+
+def project(cam: Camera, g: Gaussians, params: Params = Params(), out: Optional[Projected] = None) -> Projected:
+    n = g.n
+    dev = g.means.device
+    if out is None:
+        out = Projected(torch.empty((n, REC_FLOATS), dtype=torch.float32, device=dev),
+                        torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    _check(_lib.gs_project(C.byref(cam.c()), C.byref(params.c()), C.byref(g.c()), C.byref(out.c()), _stream()))
+    return out
+
+
+@dataclass
+class Binned:
+    tile_ids: torch.Tensor  # (capacity,) uint32 as int32
+    values: torch.Tensor  # (capacity,) uint32 as int32
+    ranges: torch.Tensor  # (T, 2) uint32 as int32
+    n_instances: int
+
+
+class BinSorter:
+    """Holds the list buffers and workspace between calls; grows them on
+    GS_ERR_CAPACITY (the library reports the required size)."""
+
+    def __init__(self, capacity: int = 0, growth: float = 1.25):
+        self.capacity = int(capacity)
+        self.growth = growth
+        self._bufs = None
+        self._key = None
+
+    def _alloc(self, n, T, dev):
+        need = C.c_size_t()
+        _check(_lib.gs_bin_sort_workspace(n, self.capacity, C.byref(need)))
+        self._bufs = dict(ws=torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev),
+                          tile_ids=torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev),
+                          values=torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev),
+                          ranges=torch.empty((T, 2), dtype=torch.int32, device=dev))
+        self._key = (n, T, self.capacity)
+
+    def __call__(self, cam: Camera, proj: Projected) -> Binned:
+        n = int(proj.radius.shape[0])
+        T = cam.tiles_x * cam.tiles_y
+        dev = proj.rec.device
+        for _ in range(2):
+            if self._key != (n, T, self.capacity) or self._bufs is None:
+                self._alloc(n, T, dev)
+            b = self._bufs
+            m = C.c_int64()
+            st = _lib.gs_bin_sort(C.byref(cam.c()), C.byref(proj.c()), n, self.capacity, b["ws"].data_ptr(),
+                                  b["ws"].numel(), b["tile_ids"].data_ptr(), b["values"].data_ptr(),
+                                  b["ranges"].data_ptr(), C.byref(m), _stream())
+            if st == GS_ERR_CAPACITY:
+                self.capacity = int(m.value * self.growth) + 1024
+                continue
+            _check(st)
+            return Binned(b["tile_ids"], b["values"], b["ranges"], int(m.value))
+        raise GsError(GS_ERR_CAPACITY, "bin_sort: capacity did not converge")
+
+
+def bin_sort(cam: Camera, proj: Projected, sorter: Optional[BinSorter] = None) -> Binned:
+    return (sorter or BinSorter())(cam, proj)
+
+
+@dataclass
+class Frame:
+    image: torch.Tensor  # (3, H, W)
+    depth: torch.Tensor  # (H, W)
+    alpha: torch.Tensor  # (H, W)
+    final_t: torch.Tensor  # (H, W)
+    n_contrib: torch.Tensor  # (H, W) int32
+    n_examined: Optional[torch.Tensor] = None
+
+
+def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Params(),
+               count_examined: bool = False, out: Optional[Frame] = None) -> Frame:
+    H, W = cam.height, cam.width
+    dev = proj.rec.device
+    if out is None:
+        out = Frame(torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.int32, device=dev),
+                    torch.empty((H, W), dtype=torch.int32, device=dev) if count_examined else None)
+    _check(_lib.gs_render_fwd(C.byref(cam.c()), C.byref(params.c()), C.byref(proj.c()), binned.values.data_ptr(),
+                              binned.ranges.data_ptr(), out.image.data_ptr(), out.depth.data_ptr(),
+                              out.alpha.data_ptr(), out.final_t.data_ptr(), out.n_contrib.data_ptr(),
+                              _ptr(out.n_examined), _stream()))
+    return out
+
+
+def render_bwd_workspace(n: int) -> int:
+    need = C.c_size_t()
+    _check(_lib.gs_render_bwd_workspace(n, C.byref(need)))
+    return int(need.value)
+
+
+def render_bwd(cam: Camera, g: Gaussians, proj: Projected, binned: Binned, frame: Frame,
+               dL_dimage: torch.Tensor, dL_ddepth: Optional[torch.Tensor] = None,
+               dL_dalpha: Optional[torch.Tensor] = None, grads: Optional[Gaussians] = None,
+               dL_dpose: Optional[torch.Tensor] = None, dL_dtwist: Optional[torch.Tensor] = None,
+               params: Params = Params(), ws: Optional[torch.Tensor] = None):
+    """Accumulates into grads (new zeros if None) and the optional float64
+    dL_dpose [12] / dL_dtwist [6]; returns grads."""
+    H, W = cam.height, cam.width
+    _require(dL_dimage, torch.float32, (3, H, W), "dL_dimage")
+    if dL_ddepth is not None:
+        _require(dL_ddepth, torch.float32, (H, W), "dL_ddepth")
+    if dL_dalpha is not None:
+        _require(dL_dalpha, torch.float32, (H, W), "dL_dalpha")
+    if grads is None:
+        grads = g.zeros_like()
+    need = render_bwd_workspace(g.n)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.means.device)
+    for t, nm, k in ((dL_dpose, "dL_dpose", 12), (dL_dtwist, "dL_dtwist", 6)):
+        if t is not None:
+            _require(t, torch.float64, (k,), nm)
+    _check(_lib.gs_render_bwd(C.byref(cam.c()), C.byref(params.c()), C.byref(g.c()), C.byref(proj.c()),
+                              binned.values.data_ptr(), binned.ranges.data_ptr(), frame.image.data_ptr(),
+                              frame.depth.data_ptr(), frame.final_t.data_ptr(), frame.n_contrib.data_ptr(),
+                              dL_dimage.data_ptr(), _ptr(dL_ddepth), _ptr(dL_dalpha), C.byref(grads.c()),
+                              _ptr(dL_dpose), _ptr(dL_dtwist), ws.data_ptr(), ws.numel(), _stream()))
+    return grads
+
+
+def loss_l1(image: torch.Tensor, target: torch.Tensor, grad_scale: Optional[float] = None,
+            dL_dimage: Optional[torch.Tensor] = None, sums: Optional[torch.Tensor] = None,
+            ws: Optional[torch.Tensor] = None):
+    """sums[0] = sum |image - target|, sums[1] = sum of squares (float64,
+    device); dL_dimage = grad_scale * sign(image - target)."""
+    count = image.numel()
+    if grad_scale is None:
+        grad_scale = 1.0 / max(count, 1)
+    if sums is None:
+        sums = torch.empty(2, dtype=torch.float64, device=image.device)
+    need = C.c_size_t()
+    _check(_lib.gs_loss_workspace(count, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=image.device)
+    _check(_lib.gs_loss_l1(image.data_ptr(), target.data_ptr(), count, grad_scale, _ptr(dL_dimage),
+                           sums.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return sums
+
+
+def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=0):
+    _check(_lib.gs_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), param.numel(), lr,
+                             beta1, beta2, eps, step, _ptr(visible), n_stride, _stream()))
+
+
+def pose_from_6d(x: torch.Tensor, pose: torch.Tensor):
+    _check(_lib.gs_pose_from_6d(x.data_ptr(), pose.data_ptr(), x.shape[0], _stream()))
+
+
+def pose_6d_bwd(x: torch.Tensor, dL_dpose: torch.Tensor, dL_dx: torch.Tensor):
+    _check(_lib.gs_pose_6d_bwd(x.data_ptr(), dL_dpose.data_ptr(), dL_dx.data_ptr(), x.shape[0], _stream()))
+
+
+def zero_(t: torch.Tensor):
+    """Zero a contiguous device tensor with the library's fill kernel."""
+    _check(_lib.gs_zero(t.data_ptr(), t.numel() * t.element_size(), _stream()))
+    return t
+
+
+def mark_visible(proj: Projected, mask: torch.Tensor):
+    _check(_lib.gs_mark_visible(proj.tiles_touched.data_ptr(), proj.tiles_touched.numel(), mask.data_ptr(),
+                                _stream()))
+
+
+def profile_enable(on: bool = True):
+    _lib.gs_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib.gs_profile_reset()
+
+
+def profile_read(kernel: str):
+    ms, cnt = C.c_double(), C.c_int64()
+    _check(_lib.gs_profile_read(kernel.encode(), C.byref(ms), C.byref(cnt)))
+    return ms.value, cnt.value
+
+
+# ------------------------------------------------------------------ autograd
+class _Rasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose, cam_static, params, sorter):
+        g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
+                      sh.contiguous())
+        cam = Camera(cam_static.width, cam_static.height, cam_static.fx, cam_static.fy, cam_static.cx,
+                     cam_static.cy, pose.detach().contiguous(), cam_static.near_plane, cam_static.bg)
+        proj = project(cam, g, params)
+        binned = sorter(cam, proj)
+        frame = render_fwd(cam, proj, binned, params)
+        ctx.state = (g, cam, proj, binned, frame, params)
+        ctx.mark_non_differentiable(frame.n_contrib)
+        return frame.image, frame.depth, frame.alpha
+
+    @staticmethod
+    def backward(ctx, g_image, g_depth, g_alpha):
+        g, cam, proj, binned, frame, params = ctx.state
+        f = lambda t: None if t is None else t.contiguous()
+        g_image = f(g_image) if g_image is not None else torch.zeros_like(frame.image)
+        d_pose = torch.zeros(12, dtype=torch.float64, device=g.means.device)
+        grads = render_bwd(cam, g, proj, binned, frame, g_image, f(g_depth), f(g_alpha), dL_dpose=d_pose,
+                           params=params)
+        return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh,
+                d_pose.to(torch.float32), None, None, None)
+
+
+def rasterize(g: Gaussians, cam: Camera, params: Params = Params(), sorter: Optional[BinSorter] = None):
+    """Differentiable render: returns (image (3,H,W), depth (H,W), alpha (H,W)).
+    Gradients flow to every Gaussian plane and to cam.pose (float32 [12])."""
+    return _Rasterize.apply(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, cam.pose, cam, params,
+                            sorter or BinSorter())

@@ -1,0 +1,279 @@
+"""Parity of the HIP rasterizer (through the C ABI) with the FP64 oracle.
+
+* gs_project   vs the oracle's projection (FP64 geometry rounded to FP32).
+* gs_bin_sort  bit-exact vs the binning oracle applied to gs_project's FP32
+  outputs (pair count, tile ids, Gaussian order, ranges).
+* gs_render_fwd image / depth / alpha / final T to 1e-4 (pixels the oracle
+  flags as within 1e-5 of a decision threshold are excluded and counted).
+* gs_render_bwd every Gaussian gradient and the pose gradient to 1e-3
+  relative, with upstream gradients that are zero at flagged pixels.
+Workloads: the 128x128 / 2,000-Gaussian scene, a ragged 150x100 image,
+64x64 crops of the 1296x840 / 500k SH-3 view, and a crop of a 1920x1080 /
+2M-Gaussian window view (the benchmark's shape, sampled).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import binning
+from oracle import raster as orc
+from paper_2506_05558_amd import synth
+from tests import gpu_common as gc
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+FLAG_REL = 1e-5
+MAX_FLAGGED = 5e-4
+
+
+def _proj_parts(proj):
+    rec = proj.rec.cpu().numpy()
+    mx = (rec[:, 0] + rec[:, 2]).astype(np.float32)  # fl(hi + lo), as the library bins
+    my = (rec[:, 1] + rec[:, 3]).astype(np.float32)
+    return rec, mx, my, proj.radius.cpu().numpy(), proj.tiles_touched.cpu().numpy()
+
+
+def _check_projection(view, scene, proj):
+    ocam, og = gc.oracle_inputs(view, scene)
+    op = orc.project(ocam, og)
+    rec, _, _, radius, _ = _proj_parts(proj)
+    vis_o = op["visible"] > 0
+    vis_g = radius > 0
+    # images are tiny relative to 2^23 px, so visibility must agree exactly
+    assert np.array_equal(vis_o, vis_g), f"visibility differs at {np.nonzero(vis_o != vis_g)[0][:10]}"
+    v = vis_o
+    mean = rec[:, 0:2].astype(np.float64) + rec[:, 2:4]
+    assert np.abs(mean[v] - op["mean2d"].T[v]).max() <= 1e-6 * (1 + np.abs(op["mean2d"]).max())
+    assert np.abs(rec[v, 11] - op["depth"][v]).max() <= 1e-6 * np.abs(op["depth"][v]).max()
+    conic = rec[:, 4:7].astype(np.float64)
+    ref = op["conic"].T
+    assert (np.abs(conic[v] - ref[v]) <= 1e-6 * np.abs(ref[v]).max(axis=1, keepdims=True) + 1e-30).all()
+    assert np.abs(rec[v, 7] - op["opacity"][v]).max() <= 1e-6
+    assert np.abs(rec[v, 8:11] - op["rgb"].T[v]).max() <= 1e-6
+    # radius = ceil(r (1 + 1e-4) + 1e-3) exactly unless the argument is within 1e-9 of an integer
+    arg = op["radius"][v] * (1 + 1e-4) + 1e-3
+    near_int = np.abs(arg - np.round(arg)) < 1e-9 * np.maximum(arg, 1)
+    assert np.array_equal(radius[v][~near_int], np.ceil(arg[~near_int]).astype(np.int32))
+    return ocam, og, op
+
+
+def _check_binning(view, proj, binned):
+    _, mx, my, radius, tiles = _proj_parts(proj)
+    depth = proj.rec[:, 11].cpu().numpy()
+    ref = binning.bin_and_sort(mx, my, radius, depth, view.width, view.height, 16)
+    assert np.array_equal(tiles, ref["tiles_touched"]), "tiles_touched differs"
+    M = binned.n_instances
+    assert M == len(ref["values"]), (M, len(ref["values"]))
+    vals = binned.values[:M].cpu().numpy().view(np.uint32)
+    tids = binned.tile_ids[:M].cpu().numpy().view(np.uint32)
+    assert np.array_equal(tids.astype(np.uint64), ref["keys"] >> np.uint64(32)), "tile ids differ"
+    assert np.array_equal(vals, ref["values"]), "Gaussian order differs"
+    assert np.array_equal(binned.ranges.cpu().numpy().view(np.uint32), ref["ranges"]), "ranges differ"
+    return M
+
+
+def _check_image(name, gpu_frame, ref, crop=None):
+    sl = (slice(None), slice(None)) if crop is None else (slice(crop[1], crop[1] + crop[3]),
+                                                            slice(crop[0], crop[0] + crop[2]))
+    ok = ref["flags"] == 0
+    frac = 1 - ok.mean()
+    img = gpu_frame.image.cpu().numpy()[(slice(None),) + sl]
+    dep = gpu_frame.depth.cpu().numpy()[sl]
+    alp = gpu_frame.alpha.cpu().numpy()[sl]
+    ft = gpu_frame.final_t.cpu().numpy()[sl]
+    e_img = np.abs(img - ref["image"])[:, ok].max(initial=0)
+    zs = max(1.0, float(np.abs(ref["depth"]).max()))
+    e_dep = np.abs(dep - ref["depth"])[ok].max(initial=0) / zs
+    e_alp = np.abs(alp - ref["alpha"])[ok].max(initial=0)
+    e_t = np.abs(ft - ref["final_t"])[ok].max(initial=0)
+    print(f"{name}: flagged {frac:.2e}, max err image {e_img:.2e} depth/zmax {e_dep:.2e} alpha {e_alp:.2e} "
+          f"T {e_t:.2e}")
+    assert frac <= MAX_FLAGGED
+    assert e_img <= IMG_TOL and e_dep <= IMG_TOL and e_alp <= IMG_TOL and e_t <= IMG_TOL
+
+
+def _check_grads(name, grads, d_pose, d_twist, ref, n_checked=None):
+    sel = slice(None) if n_checked is None else n_checked
+    gc.assert_grad_close(f"{name} means", grads.means.cpu().numpy()[:, sel], ref["means"][:, sel])
+    gc.assert_grad_close(f"{name} log_scales", grads.log_scales.cpu().numpy()[:, sel], ref["log_scales"][:, sel])
+    gc.assert_grad_close(f"{name} quats", grads.quats.cpu().numpy()[:, sel], ref["quats"][:, sel])
+    gc.assert_grad_close(f"{name} opacity", grads.opacity_logits.cpu().numpy()[sel], ref["opacity_logits"][sel])
+    gc.assert_grad_close(f"{name} sh", grads.sh.cpu().numpy()[..., sel], ref["sh"][..., sel])
+    dp = d_pose.cpu().numpy()
+    gc.assert_grad_close(f"{name} dR", dp[:9], ref["R"].reshape(9))
+    gc.assert_grad_close(f"{name} dt", dp[9:], ref["t"])
+    gc.assert_grad_close(f"{name} twist", d_twist.cpu().numpy(), ref["twist"])
+
+
+def _full_case(name, view, scene, seed, bg=(0.0, 0.0, 0.0)):
+    gs = gc.gpu()
+    cam = gc.gpu_camera(view, bg)
+    g = gc.gpu_gauss(scene)
+    proj, binned, frame = gc.run_forward(cam, g)
+    ocam, og, op = _check_projection(view, scene, proj)
+    ocam.bg = bg
+    _check_binning(view, proj, binned)
+    ref = orc.render(ocam, op, flag_rel=FLAG_REL)
+    _check_image(name, frame, ref)
+    gi, gd, ga = gc.flagged_upstream((view.height, view.width), ref["flags"], seed)
+    d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
+    d_twist = torch.zeros(6, dtype=torch.float64, device="cuda")
+    grads = gs.render_bwd(cam, g, proj, binned, frame, torch.tensor(gi, device="cuda"),
+                          torch.tensor(gd, device="cuda"), torch.tensor(ga, device="cuda"), dL_dpose=d_pose,
+                          dL_dtwist=d_twist)
+    torch.cuda.synchronize()
+    rg = orc.backward(ocam, og, op, gi, gd, ga)
+    _check_grads(name, grads, d_pose, d_twist, rg)
+
+
+def test_tiny_scene_full_parity():
+    view, scene, _ = synth.tiny_scene(0)
+    _full_case("tiny", view, scene, seed=1)
+
+
+def test_tiny_scene_posed_background():
+    view, scene, _ = synth.tiny_scene(3)
+    view.R, view.t = synth.random_pose(np.random.default_rng(3), 5.0, 0.1)
+    _full_case("tiny-posed", view, scene, seed=2, bg=(0.2, 0.5, 0.1))
+
+
+def test_ragged_image_sh3():
+    rng = np.random.default_rng(4)
+    view = synth.View(150, 100, 105.0, 110.0, 74.3, 51.7)
+    view.R, view.t = synth.random_pose(rng, 4.0, 0.05)
+    scene = synth.ray_scene(4, view, 3000, sh_degree=3)
+    _full_case("ragged-sh3", view, scene, seed=3)
+
+
+@pytest.mark.parametrize("crop", [(616, 388, 64, 64), (0, 0, 64, 64)])
+def test_single_view_crops(crop):
+    gs = gc.gpu()
+    view, scene = synth.single_view(7)
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj, binned, frame = gc.run_forward(cam, g)
+    ocam, og, op = _check_projection(view, scene, proj)
+    _check_binning(view, proj, binned)
+    ref = orc.render(ocam, op, crop=crop, flag_rel=FLAG_REL)
+    _check_image(f"single-view {crop[:2]}", frame, ref, crop)
+    gi, gd, ga = gc.flagged_upstream(crop[2:][::-1], ref["flags"], 5)
+    full = (view.height, view.width)
+    d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
+    d_twist = torch.zeros(6, dtype=torch.float64, device="cuda")
+    t = lambda a: torch.tensor(gc.embed(a, full, crop), device="cuda")
+    grads = gs.render_bwd(cam, g, proj, binned, frame, t(gi), t(gd), t(ga), dL_dpose=d_pose, dL_dtwist=d_twist)
+    torch.cuda.synchronize()
+    rg = orc.backward(ocam, og, op, gi, gd, ga, crop=crop)
+    _check_grads(f"single-view {crop[:2]}", grads, d_pose, d_twist, rg)
+
+
+def test_window_view_sampled_crop():
+    """The benchmark's shape: 1920x1080, 2M Gaussians (8 x 250k), SH 3."""
+    views = synth.trajectory(11, 8, 1920, 1080)
+    scene = synth.window_scene(11, views, 250_000)
+    view = views[3]
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj, binned, frame = gc.run_forward(cam, g)
+    _check_binning(view, proj, binned)
+    ocam, og = gc.oracle_inputs(view, scene)
+    op = orc.project(ocam, og)
+    for crop in [(928, 508, 48, 48), (1888, 1048, 32, 32)]:
+        ref = orc.render(ocam, op, crop=crop, flag_rel=FLAG_REL)
+        _check_image(f"window {crop[:2]}", frame, ref, crop)
+
+
+def test_empty_and_culled():
+    gs = gc.gpu()
+    view, scene, _ = synth.tiny_scene(5)
+    cam = gc.gpu_camera(view, bg=(0.3, 0.2, 0.1))
+    behind = synth.Scene(scene.means * np.array([[1], [1], [-1]], np.float32), scene.log_scales, scene.quats,
+                         scene.opacity_logits, scene.sh, 0)
+    g = gc.gpu_gauss(behind)
+    proj, binned, frame = gc.run_forward(cam, g)
+    assert binned.n_instances == 0
+    assert int(proj.radius.abs().sum()) == 0
+    img = frame.image.cpu().numpy()
+    assert np.array_equal(img, np.broadcast_to(np.array([0.3, 0.2, 0.1], np.float32)[:, None, None], img.shape))
+    empty = gs.Gaussians(*[t[..., :0].contiguous() for t in g.tensors()])
+    proj, binned, frame = gc.run_forward(cam, empty)
+    assert binned.n_instances == 0 and float(frame.alpha.abs().max()) == 0.0
+
+
+def test_capacity_growth_gives_same_lists():
+    gs = gc.gpu()
+    view, scene, _ = synth.tiny_scene(6)
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj = gs.project(cam, g)
+    small = gs.BinSorter(capacity=16)
+    b1 = small(cam, proj)
+    assert small.capacity >= b1.n_instances > 16
+    b2 = gs.BinSorter(capacity=10 * b1.n_instances)(cam, proj)
+    M = b1.n_instances
+    assert torch.equal(b1.values[:M], b2.values[:M]) and torch.equal(b1.ranges, b2.ranges)
+
+
+def test_autograd_matches_abi_and_pose_grad():
+    gs = gc.gpu()
+    view, scene, target = synth.tiny_scene(8)
+    view.R, view.t = synth.random_pose(np.random.default_rng(8), 3.0, 0.05)
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    leaves = [t.clone().requires_grad_(True) for t in g.tensors()]
+    pose = cam.pose.clone().requires_grad_(True)
+    gl = gs.Gaussians(*leaves)
+    cam2 = gs.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, pose)
+    img, dep, alp = gs.rasterize(gl, cam2)
+    tgt = torch.tensor(target, device="cuda")
+    loss = (img - tgt).abs().mean() + 0.01 * dep.mean()
+    loss.backward()
+    proj, binned, frame = gc.run_forward(cam, g)
+    gimg = (torch.sign(frame.image - tgt) / frame.image.numel()).contiguous()
+    gdep = torch.full_like(frame.depth, 0.01 / frame.depth.numel())
+    d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
+    ref = gs.render_bwd(cam, g, proj, binned, frame, gimg, gdep, dL_dpose=d_pose)
+    for a, b in zip(leaves, ref.tensors()):
+        assert torch.allclose(a.grad, b, rtol=1e-5, atol=1e-9)
+    assert torch.allclose(pose.grad.double(), d_pose, rtol=1e-5, atol=1e-9)
+
+
+def test_forward_finite_difference_pose():
+    """FP32 finite differences of the GPU forward along the six camera-twist
+    directions agree with the analytic twist gradient.  Small scene, step
+    1e-5 and upstream weights that are zero wherever any decision (skip, stop,
+    clamp, order) lies within 1% of its threshold, so no decision flips."""
+    gs = gc.gpu()
+    view, scene = synth.small_scene(21, n=12, size=32)
+    view.R, view.t = synth.random_pose(np.random.default_rng(21), 3.0, 0.05)
+    ocam, og = gc.oracle_inputs(view, scene)
+    _, ref = orc.forward(ocam, og, flag_rel=1e-2)
+    rng = np.random.default_rng(9)
+    Wn = rng.standard_normal((3, view.height, view.width)) * (ref["flags"] == 0)[None]
+    W = torch.tensor(Wn, dtype=torch.float64, device="cuda")
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+
+    def L(R, t):
+        cam.pose = torch.tensor(np.concatenate([R.reshape(9), t]).astype(np.float32), device="cuda")
+        _, _, fr = gc.run_forward(cam, g)
+        return float((fr.image.double() * W).sum())
+
+    R0, t0 = np.asarray(view.R, np.float64), np.asarray(view.t, np.float64)
+    cam.pose = torch.tensor(np.concatenate([R0.reshape(9), t0]).astype(np.float32), device="cuda")
+    proj, binned, frame = gc.run_forward(cam, g)
+    d_tw = torch.zeros(6, dtype=torch.float64, device="cuda")
+    gs.render_bwd(cam, g, proj, binned, frame, W.float().contiguous(), dL_dtwist=d_tw)
+    an = d_tw.cpu().numpy()
+    h = 1e-5
+    fd = np.zeros(6)
+    for j in range(6):
+        xi = np.zeros(6)
+        xi[j] = h
+        E = synth._rotation(xi[3:], h) if j >= 3 else np.eye(3)
+        Lp = L(E @ R0, E @ t0 + xi[:3])
+        Lm = L(E.T @ R0, E.T @ t0 - xi[:3])
+        fd[j] = (Lp - Lm) / (2 * h)
+    print("twist analytic", an, "fd", fd)
+    assert np.linalg.norm(fd - an) <= 2e-2 * np.linalg.norm(an)

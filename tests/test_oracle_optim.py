@@ -1,0 +1,72 @@
+"""Pins of the optimiser oracle: closed forms of the first Adam step, the
+sparse mask, known loss values, the 6D map's orthonormality and fixed points,
+and finite differences of its adjoint."""
+import math
+
+import numpy as np
+
+from oracle import optim
+
+
+def test_l1_known_values():
+    img = np.array([0.5, 0.25, 1.0, 0.0])
+    tgt = np.array([0.0, 0.25, 0.5, 1.0])
+    s1, s2, g = optim.l1_loss(img, tgt, 0.5)
+    assert s1 == 2.0 and s2 == 0.25 + 0.25 + 1.0
+    assert g.tolist() == [0.5, 0.0, 0.5, -0.5]
+    assert abs(optim.psnr(0.01) - 20.0) < 1e-12
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    p1, m1, v1 = optim.adam(p, g, np.zeros(50), np.zeros(50), lr=0.1, step=1, eps=0.0)
+    # bias-corrected first moments are g and g^2: the step is lr * sign(g)
+    assert np.allclose(p1, p - 0.1 * np.sign(g), atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+
+
+def test_adam_sparse_leaves_hidden_gaussians():
+    rng = np.random.default_rng(1)
+    n = 10
+    p = rng.standard_normal((3, n))
+    g = rng.standard_normal((3, n))
+    m = rng.standard_normal((3, n)) * 0.1
+    v = rng.random((3, n)) * 0.1
+    vis = (np.arange(n) % 3 == 0).astype(np.int32)
+    p1, m1, v1 = optim.adam(p, g, m, v, 0.01, 5, visible=vis, n_stride=n)
+    pd, md, vd = optim.adam(p, g, m, v, 0.01, 5)
+    hidden = vis == 0
+    assert np.array_equal(p1[:, hidden], p[:, hidden]) and np.array_equal(m1[:, hidden], m[:, hidden])
+    assert np.array_equal(p1[:, ~hidden], pd[:, ~hidden]) and np.array_equal(v1[:, ~hidden], vd[:, ~hidden])
+
+
+def test_pose_6d_orthonormal_and_identity():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((5, 9))
+    P = optim.pose_from_6d(x)
+    for i in range(5):
+        R = P[i, :9].reshape(3, 3)
+        assert np.allclose(R.T @ R, np.eye(3), atol=1e-14) and abs(np.linalg.det(R) - 1) < 1e-14
+        # first column is a1's direction
+        assert np.allclose(R[:, 0], x[i, :3] / np.linalg.norm(x[i, :3]))
+    ident = optim.pose_from_6d(np.array([[2.0, 0, 0, 0.3, 5.0, 0, 1, 2, 3]]))
+    assert np.allclose(ident[0, :9], np.eye(3).reshape(9)) and np.allclose(ident[0, 9:], [1, 2, 3])
+
+
+def test_pose_6d_vjp_finite_differences():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((2, 9))
+    G = rng.standard_normal((2, 12))
+    an = optim.pose_6d_vjp(x, G)
+    h = 1e-6
+    fd = np.zeros_like(x)
+    for idx in np.ndindex(*x.shape):
+        xp = x.copy()
+        xp[idx] += h
+        xm = x.copy()
+        xm[idx] -= h
+        fd[idx] = ((optim.pose_from_6d(xp) - optim.pose_from_6d(xm)) * G).sum() / (2 * h)
+    assert np.abs(fd - an).max() < 1e-8 * max(1.0, np.abs(an).max())
+    assert math.isfinite(an.sum())

@@ -351,3 +351,18 @@ def test_pose_gauge_identity(oracle_lib):
     phi = np.cross(p.T, Rg.T).sum(0) + (Rm @ d_omega).sum(1)
     ref = np.concatenate([rho, phi])
     assert np.linalg.norm(ref - gr["twist"]) < 1e-9 * np.linalg.norm(ref)
+
+
+def test_depth_tie_flag(oracle_lib):
+    """The tie flag fires exactly when binary32 depths tie and the index order
+    runs against the FP64 depth order."""
+    orc = oracle_lib
+    view = synth.View(8, 8, 10.0, 10.0, 4.0, 4.0)
+    z0 = 3.0
+    z1 = float(np.nextafter(np.float64(z0), 4.0))  # same binary32 rounding, larger in FP64
+    for zs, expect in [((z1, z0), True), ((z0, z1), False), ((z0, z0 + 1e-3), False)]:
+        means = np.array([[0.0, 0.0], [0.0, 0.0], list(zs)])
+        g = orc.Gaussians(means, np.full((3, 2), -2.0), np.tile([[1.0], [0], [0], [0]], (1, 2)),
+                          np.full(2, 0.0), np.zeros((1, 3, 2)), 0)
+        _, out = orc.forward(orc.Camera.from_view(view), g)
+        assert bool(out["flags"][4, 4] & 8) == expect, zs
