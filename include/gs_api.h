@@ -155,11 +155,14 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
  *   image = C + T bg, depth = D (not normalised), alpha = 1 - T,
  *   final_t = T, n_contrib = list entries up to and including the last one
  *   composited (counted from the tile's start; state for the backward),
- *   n_examined = entries tested before the stop (NULL = not written).
+ *   stats [2][H][W] (NULL = not written): plane 0 the list entries tested
+ *   (up to and including the one that stopped the pixel), plane 1 the
+ *   entries composited -- the pair counts the work of the method is
+ *   measured in.
  * values / ranges from gs_bin_sort. */
 gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                         const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,
-                        float *final_t, int32_t *n_contrib, int32_t *n_examined, void *stream);
+                        float *final_t, int32_t *n_contrib, int32_t *stats, void *stream);
 
 /* ---- gs_render_bwd ------------------------------------------------------
  * Adjoint of gs_project + gs_render_fwd for upstream gradients of image

@@ -62,7 +62,7 @@ __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_ex
 // ------------------------------------------------------------------ forward
 struct FwdOut {
   float *image, *depth, *alpha, *final_t;
-  int32_t *n_contrib, *n_examined;
+  int32_t *n_contrib, *stats;
 };
 
 __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   __shared__ float4 sA[kBatch], sB[kBatch], sC[kBatch];
 
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
-  int last = 0;
+  int last = 0, ncomp = 0;
   int examined = (int)(e - s);
   bool done = !inside;
 
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
         D = __fmaf_rn(B.z, w, D);
         T = Tn;
         last = (int)(base - s) + k + 1;
+        ++ncomp;
       }
     }
   }
@@ -124,7 +125,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   o.alpha[pix] = 1.0f - T;
   o.final_t[pix] = T;
   o.n_contrib[pix] = last;
-  if (o.n_examined) o.n_examined[pix] = examined;
+  if (o.stats) {
+    o.stats[pix] = examined;
+    o.stats[np + pix] = ncomp;
+  }
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -298,7 +302,7 @@ extern "C" {
 
 gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                         const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,
-                        float *final_t, int32_t *n_contrib, int32_t *n_examined, void *stream) {
+                        float *final_t, int32_t *n_contrib, int32_t *stats, void *stream) {
   gs_status st = validate_camera(cam, "gs_render_fwd");
   if (st != GS_OK) return st;
   GS_REQUIRE(rp && proj && ranges && image && depth && alpha && final_t && n_contrib,
@@ -306,7 +310,7 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
   GS_REQUIRE(rp->alpha_max > 0.f && rp->alpha_max < 1.f && rp->t_min > 0.f && rp->t_min < 1.f,
              "gs_render_fwd: raster params out of range");
   RenderArgs a = render_args(cam, rp, proj, values, ranges);
-  FwdOut o{image, depth, alpha, final_t, n_contrib, n_examined};
+  FwdOut o{image, depth, alpha, final_t, n_contrib, stats};
   GS_LAUNCH("render_fwd", k_render_fwd, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
   return GS_OK;
 }

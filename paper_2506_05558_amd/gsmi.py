@@ -270,11 +270,11 @@ class Frame:
     alpha: torch.Tensor  # (H, W)
     final_t: torch.Tensor  # (H, W)
     n_contrib: torch.Tensor  # (H, W) int32
-    n_examined: Optional[torch.Tensor] = None
+    stats: Optional[torch.Tensor] = None  # (2, H, W) int32: entries tested, entries composited
 
 
 def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Params(),
-               count_examined: bool = False, out: Optional[Frame] = None) -> Frame:
+               count_pairs: bool = False, out: Optional[Frame] = None) -> Frame:
     H, W = cam.height, cam.width
     dev = proj.rec.device
     if out is None:
@@ -283,11 +283,11 @@ def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Pa
                     torch.empty((H, W), dtype=torch.float32, device=dev),
                     torch.empty((H, W), dtype=torch.float32, device=dev),
                     torch.empty((H, W), dtype=torch.int32, device=dev),
-                    torch.empty((H, W), dtype=torch.int32, device=dev) if count_examined else None)
+                    torch.empty((2, H, W), dtype=torch.int32, device=dev) if count_pairs else None)
     _check(_lib.gs_render_fwd(C.byref(cam.c()), C.byref(params.c()), C.byref(proj.c()), binned.values.data_ptr(),
                               binned.ranges.data_ptr(), out.image.data_ptr(), out.depth.data_ptr(),
                               out.alpha.data_ptr(), out.final_t.data_ptr(), out.n_contrib.data_ptr(),
-                              _ptr(out.n_examined), _stream()))
+                              _ptr(out.stats), _stream()))
     return out
 
 

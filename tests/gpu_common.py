@@ -29,12 +29,12 @@ def oracle_inputs(view, scene, bg=(0.0, 0.0, 0.0)):
     return orc.Camera.from_view(view, bg=bg), orc.Gaussians.from_scene(scene)
 
 
-def run_forward(cam, g, capacity=0, count_examined=False):
+def run_forward(cam, g, capacity=0, count_pairs=False):
     gs = gpu()
     proj = gs.project(cam, g)
     sorter = gs.BinSorter(capacity)
     binned = sorter(cam, proj)
-    frame = gs.render_fwd(cam, proj, binned, count_examined=count_examined)
+    frame = gs.render_fwd(cam, proj, binned, count_pairs=count_pairs)
     torch.cuda.synchronize()
     return proj, binned, frame
 

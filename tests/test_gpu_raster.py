@@ -110,12 +110,17 @@ def _full_case(name, view, scene, seed, bg=(0.0, 0.0, 0.0)):
     gs = gc.gpu()
     cam = gc.gpu_camera(view, bg)
     g = gc.gpu_gauss(scene)
-    proj, binned, frame = gc.run_forward(cam, g)
+    proj, binned, frame = gc.run_forward(cam, g, count_pairs=True)
     ocam, og, op = _check_projection(view, scene, proj)
     ocam.bg = bg
     _check_binning(view, proj, binned)
     ref = orc.render(ocam, op, flag_rel=FLAG_REL)
     _check_image(name, frame, ref)
+    # pair counters: composited entries match the definition's count exactly
+    ok = ref["flags"] == 0
+    stats = frame.stats.cpu().numpy()
+    assert np.array_equal(stats[1][ok], ref["n_contrib"][ok])
+    assert (stats[0] >= stats[1]).all() and (stats[0][ok] >= ref["n_support"][ok]).all()
     gi, gd, ga = gc.flagged_upstream((view.height, view.width), ref["flags"], seed)
     d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
     d_twist = torch.zeros(6, dtype=torch.float64, device="cuda")
