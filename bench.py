@@ -35,15 +35,18 @@ W_IMG, H_IMG, N_VIEWS, PER_VIEW, SH_DEG, SEED = 1920, 1080, 8, 250_000, 3, 2506
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic work (lane-operations) per pair, from the definition:
-#  forward, every tested entry: dx, dy, 5 ops for the quadratic form, exp,
-#  opacity scale, clamp, threshold test = 11; a composited entry adds
-#  1 - alpha, T (1 - alpha), cutoff test, w = alpha T, 3 colour + 1 depth
-#  accumulations = 8.
-#  backward, every entry walked: the same 11; a composited entry adds the
-#  adjoint: 55 (prefix sums 4, suffix 4, 1/(1-alpha) 2, d alpha 17,
+# Algorithmic work (lane-operations) per (pixel, Gaussian) pair, from the
+# definition.  Only pairs inside the Gaussian's support (alpha >= alpha_min)
+# are work every correct implementation must do; pairs a tile list adds
+# outside the support are acceleration overhead and are not counted.
+#  forward, per support pair up to the stop: dx, dy, 5 ops for the quadratic
+#  form, exp, opacity scale, clamp, threshold test = 11; a composited pair
+#  adds 1 - alpha, T (1 - alpha), cutoff test, w = alpha T, 3 colour and
+#  1 depth accumulations = 8.
+#  backward, per composited pair: the same 11 to recompute alpha, plus the
+#  adjoint 55 (prefix sums 4, suffix 4, 1/(1-alpha) 2, d alpha 17,
 #  colour/depth grads 4, opacity/conic/mean grads 21, T update 2, w 1).
-FWD_TEST, FWD_COMP, BWD_TEST, BWD_COMP = 11, 8, 11, 55
+FWD_PAIR, FWD_COMP, BWD_COMP = 11, 8, 66
 
 
 def parse():
@@ -109,8 +112,7 @@ def main():
     d_pose = torch.zeros((N_VIEWS, 12), dtype=torch.float64, device=dev)
     visible = torch.zeros(n, dtype=torch.int32, device=dev)
     sums = torch.zeros((N_VIEWS, 2), dtype=torch.float64, device=dev)
-    proj = gsmi.Projected(torch.empty((n, 12), dtype=torch.float32, device=dev),
-                          torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    proj = gsmi.alloc_projected(n, dev)
     f = lambda *s, dt=torch.float32: torch.empty(s, dtype=dt, device=dev)
     frame = gsmi.Frame(f(3, H, W), f(H, W), f(H, W), f(H, W), f(H, W, dt=torch.int32))
     g_img = f(3, H, W)
@@ -137,14 +139,15 @@ def main():
             fr = frame
             if count_pairs:
                 fr = gsmi.Frame(frame.image, frame.depth, frame.alpha, frame.final_t, frame.n_contrib,
-                                torch.empty((2, H, W), dtype=torch.int32, device=dev))
+                                torch.empty((4, H, W), dtype=torch.int32, device=dev))
             gsmi.render_fwd(cam, proj, b, params, out=fr)
             gsmi.loss_l1(fr.image, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i], loss_ws)
             gsmi.render_bwd(cam, g, proj, b, fr, g_img, grads=grads, dL_dpose=d_pose[i], params=params, ws=bwd_ws)
             gsmi.mark_visible(proj, visible)
             if count_pairs:
-                st = fr.stats.view(2, -1).to(torch.int64).sum(1).cpu().numpy()
-                pairs.append((int(st[0]), int(st[1]), int(fr.n_contrib.to(torch.int64).sum()), b.n_instances))
+                st = fr.stats.view(4, -1).to(torch.int64).sum(1).cpu().numpy()
+                pairs.append((int(st[0]), int(st[1]), int(st[2]), int(st[3]),
+                              int(fr.n_contrib.to(torch.int64).sum()), b.n_instances))
         gsmi.pose_6d_bwd(x6, d_pose, dx6)
         for name in ["means", "log_scales", "quats", "opacity_logits"]:
             gsmi.adam_step(getattr(g, name), getattr(grads, name), getattr(m1, name), getattr(m2, name), lr[name],
@@ -180,10 +183,12 @@ def main():
     # one extra step (not timed) with pair counters for the algorithmic work
     step(count_pairs=True)
     torch.cuda.synchronize()
-    tested = sum(p[0] for p in pairs) / N_VIEWS
-    comp = sum(p[1] for p in pairs) / N_VIEWS
-    walked = sum(p[2] for p in pairs) / N_VIEWS
-    M = sum(p[3] for p in pairs) / N_VIEWS
+    tile_pairs = sum(p[0] for p in pairs) / N_VIEWS
+    evaluated = sum(p[1] for p in pairs) / N_VIEWS
+    support = sum(p[2] for p in pairs) / N_VIEWS
+    comp = sum(p[3] for p in pairs) / N_VIEWS
+    walked = sum(p[4] for p in pairs) / N_VIEWS
+    M = sum(p[5] for p in pairs) / N_VIEWS
 
     ms_step = elapsed * 1e3 / args.steps
     mpix = N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
@@ -192,12 +197,12 @@ def main():
         k = kernels[name]
         t = k["ms_per_launch"] * 1e-3
         if name == "render_fwd":
-            ops = tested * FWD_TEST + comp * FWD_COMP
+            ops = support * FWD_PAIR + comp * FWD_COMP
             a = ops / t / 1e12
             return dict(bound="alu", achieved=a, peak=PEAK_VALU_TOPS, unit="Tlane-op/s", frac=a / PEAK_VALU_TOPS,
                         traffic=None)
         if name == "render_bwd":
-            ops = walked * BWD_TEST + comp * BWD_COMP
+            ops = comp * BWD_COMP
             a = ops / t / 1e12
             return dict(bound="alu", achieved=a, peak=PEAK_VALU_TOPS, unit="Tlane-op/s", frac=a / PEAK_VALU_TOPS,
                         traffic=None)
@@ -237,7 +242,8 @@ def main():
         "roofline": roofline,
         "kernel_rooflines": others,
         "kernels_ms_per_step": {k: round(v["ms_total"] / args.steps, 4) for k, v in kernels.items()},
-        "pairs_per_view": {"tested": tested, "composited": comp, "walked_bwd": walked, "instances": M},
+        "pairs_per_view": {"tile_list_to_stop": tile_pairs, "evaluated": evaluated, "support": support,
+                           "composited": comp, "tile_list_walked_bwd": walked, "instances": M},
         "psnr_start_end": [round(sum(psnr0) / N_VIEWS, 3), round(sum(psnr1) / N_VIEWS, 3)],
     }
     if not args.no_cpu_baseline:

@@ -56,17 +56,21 @@ typedef enum {
  * 256-lane workgroup (four wave64). */
 #define GS_TILE 16
 
-/* Render record written by gs_project, one per Gaussian, 12 floats (48 B):
+/* Render record written by gs_project, one per Gaussian, 16 floats (64 B,
+ * half a 128-byte cache line, so a gather touches one line):
  *   [0] mean_x integer part   [1] mean_y integer part   (exact integers)
  *   [2] mean_x - [0]          [3] mean_y - [1]          (in [-0.5, 0.5])
  *   [4] A  [5] B  [6] C       conic: inverse 2D covariance [[A, B], [B, C]]
  *   [7] opacity o = sigmoid(logit)
  *   [8] [9] [10] colour (r, g, b) from SH, clamped below at 0
  *   [11] depth z of the camera-space mean (positive)
+ *   [12] [13] half-extents (hx, hy) in pixels of the bounding box of the
+ *        support ellipse d^T conic d <= 2 ln(o / alpha_min)
+ *   [14] [15] zero
  * The split mean keeps the offset to a pixel exact to ~1e-7 px at any image
  * size.  The FP32 mean used for binning is the sum of the two parts rounded
  * once: mean_x = fl(rec[0] + rec[2]), mean_y = fl(rec[1] + rec[3]). */
-#define GS_REC_FLOATS 12
+#define GS_REC_FLOATS 16
 
 typedef struct {
   int32_t width, height;    /* image size in pixels, 1 .. 16384 */
@@ -96,7 +100,7 @@ typedef struct {
 
 typedef struct {
   float *rec;             /* [n][GS_REC_FLOATS] render records (layout above) */
-  int32_t *radius;        /* [n] pixel radius of the support square, 0 = culled */
+  int32_t *radius;        /* [2][n] integer half-widths (rx, ry) of the support rect, rx = 0: culled */
   int32_t *tiles_touched; /* [n] number of 16x16 tiles the support square meets */
 } gs_projected;           /* HOST struct of DEVICE pointers */
 
@@ -115,10 +119,12 @@ const char *gs_last_error(void);
  *   colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = unit(mean - camera
  *   centre), real SH up to degree 3;
  *   o = sigmoid(logit); culled if o < alpha_min;
- *   radius = ceil(r (1 + 1e-4) + 1e-3), r = sqrt(2 ln(o / alpha_min)
- *   lambda_max(Sigma2)), the extent of the region where o exp(-d^T conic d / 2)
- *   >= alpha_min; tiles_touched counts the tiles holding an integer pixel of
- *   the clipped square [mean - radius, mean + radius]^2.
+ *   support: the ellipse where o exp(-d^T conic d / 2) >= alpha_min, i.e.
+ *   d^T conic d <= qmax = 2 ln(o / alpha_min); its bounding box has
+ *   half-extents hx = sqrt(qmax Sigma2_xx), hy = sqrt(qmax Sigma2_yy) and
+ *   rx = ceil(hx (1 + 1e-4) + 1e-3), ry likewise; tiles_touched counts the
+ *   tiles holding an integer pixel of the clipped rect
+ *   [mean_x - rx, mean_x + rx] x [mean_y - ry, mean_y + ry].
  * Geometry is evaluated in FP64 and stored in FP32.  Culled Gaussians get
  * radius = tiles_touched = 0 and zeroed records.
  * Errors: GS_ERR_INVALID_ARG for NULL pointers (n > 0), n < 0, degree out of
@@ -128,7 +134,7 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
 
 /* ---- gs_bin_sort --------------------------------------------------------
  * Builds the per-tile depth-ordered lists: every (Gaussian, tile) pair of
- * gs_project's support squares, ordered by tile id (row-major tiles,
+ * gs_project's support rects, ordered by tile id (row-major tiles,
  * tiles_x = ceil(W/16)), then by the FP32 depth, then by Gaussian index.
  * That is the order of a stable sort of the key (tile << 32 | bits(depth))
  * over pairs emitted in Gaussian-index order.  Implemented as a stable LSD
@@ -155,10 +161,13 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
  *   image = C + T bg, depth = D (not normalised), alpha = 1 - T,
  *   final_t = T, n_contrib = list entries up to and including the last one
  *   composited (counted from the tile's start; state for the backward),
- *   stats [2][H][W] (NULL = not written): plane 0 the list entries tested
- *   (up to and including the one that stopped the pixel), plane 1 the
- *   entries composited -- the pair counts the work of the method is
- *   measured in.
+ *   stats [4][H][W] (NULL = not written), per pixel: plane 0 the tile-list
+ *   entries up to and including the one that stopped the pixel (the whole
+ *   list if it did not stop), plane 1 the entries evaluated (after culling
+ *   entries whose support box misses the pixel's 8x8 quadrant), plane 2 the
+ *   entries with alpha >= alpha_min up to and including the stopping one,
+ *   plane 3 the entries composited -- the pair counts the work is measured
+ *   in.
  * values / ranges from gs_bin_sort. */
 gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                         const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,

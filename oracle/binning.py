@@ -2,17 +2,17 @@
 
 Binning is acceleration, not part of what the rasterizer computes: a
 Gaussian is listed in every tile that holds an integer pixel inside the
-square [mx - r, mx + r] x [my - r, my + r] clipped to the image, and each tile
-list is ordered by (depth, index).  With the integer radius r at least the
-extent of the Gaussian's support (alpha >= alpha_min), the lists contain every
-Gaussian that can touch a pixel of the tile, so the image does not depend on
-the tile size.
+rect [mx - rx, mx + rx] x [my - ry, my + ry] clipped to the image, and each
+tile list is ordered by (depth, index).  With the integer half-widths at
+least the extent of the Gaussian's support (alpha >= alpha_min), the lists
+contain every Gaussian that can touch a pixel of the tile, so the image does
+not depend on the tile size.
 
 The oracle works from the FP32 projection outputs of the path under test
-(mean, integer radius, depth) because the lists are a discrete function of
-those values: the rect is formed with one IEEE binary32 rounding per bound
-(mx - r, mx + r), then ceil / floor, clipping and integer division by the
-tile size.  Emission is Gaussian-index order with tiles row-major inside the
+(mean, integer half-widths, depth) because the lists are a discrete function
+of those values: the rect is formed with one IEEE binary32 rounding per
+bound (mx - rx, mx + rx, ...), then ceil / floor, clipping and integer
+division by the tile size.  Emission is Gaussian-index order with tiles row-major inside the
 rect; a stable sort on the 64-bit key (tile << 32 | binary32 bits of depth)
 then gives the per-tile (depth, index) order.  Depths are positive, so their
 bit patterns order like their values.
@@ -22,17 +22,18 @@ from __future__ import annotations
 import numpy as np
 
 
-def tile_rects(mx, my, radius, width: int, height: int, tile: int):
+def tile_rects(mx, my, rx, ry, width: int, height: int, tile: int):
     """Per-Gaussian inclusive tile rect (tx0, ty0, tx1, ty1) and tile count."""
     mx = np.asarray(mx, np.float32)
     my = np.asarray(my, np.float32)
-    r = np.asarray(radius).astype(np.float32)
+    fx = np.asarray(rx).astype(np.float32)
+    fy = np.asarray(ry).astype(np.float32)
     with np.errstate(invalid="ignore", over="ignore"):
-        fu0 = np.maximum(np.ceil(mx - r), np.float32(0))
-        fu1 = np.minimum(np.floor(mx + r), np.float32(width - 1))
-        fv0 = np.maximum(np.ceil(my - r), np.float32(0))
-        fv1 = np.minimum(np.floor(my + r), np.float32(height - 1))
-    ok = (np.asarray(radius) > 0) & (fu0 <= fu1) & (fv0 <= fv1)
+        fu0 = np.maximum(np.ceil(mx - fx), np.float32(0))
+        fu1 = np.minimum(np.floor(mx + fx), np.float32(width - 1))
+        fv0 = np.maximum(np.ceil(my - fy), np.float32(0))
+        fv1 = np.minimum(np.floor(my + fy), np.float32(height - 1))
+    ok = (np.asarray(rx) > 0) & (np.asarray(ry) > 0) & (fu0 <= fu1) & (fv0 <= fv1)
     u0 = np.where(ok, fu0, 0).astype(np.int64)
     u1 = np.where(ok, fu1, 0).astype(np.int64)
     v0 = np.where(ok, fv0, 0).astype(np.int64)
@@ -42,12 +43,12 @@ def tile_rects(mx, my, radius, width: int, height: int, tile: int):
     return tx0, ty0, tx1, ty1, count
 
 
-def bin_and_sort(mx, my, radius, depth, width: int, height: int, tile: int = 16):
+def bin_and_sort(mx, my, rx, ry, depth, width: int, height: int, tile: int = 16):
     """Returns dict(tiles_touched, keys u64[M], values u32[M], ranges u32[T,2])."""
     tiles_x = (width + tile - 1) // tile
     tiles_y = (height + tile - 1) // tile
     T = tiles_x * tiles_y
-    tx0, ty0, tx1, ty1, count = tile_rects(mx, my, radius, width, height, tile)
+    tx0, ty0, tx1, ty1, count = tile_rects(mx, my, rx, ry, width, height, tile)
     M = int(count.sum())
     gid = np.repeat(np.arange(len(count), dtype=np.int64), count)
     start = np.concatenate([[0], np.cumsum(count)[:-1]]) if len(count) else np.zeros(0, np.int64)

@@ -71,6 +71,7 @@ typedef struct {
   double *opacity;  /* [n] */
   double *rgb;      /* [3][n] */
   double *radius;   /* [n]  sqrt(2 ln(o / alpha_min) lambda_max), unrounded */
+  double *half;     /* [2][n] half-extents of the support ellipse's bounding box */
   int32_t *visible; /* [n]  1 if the Gaussian can contribute anywhere */
   int32_t *clamped; /* [n]  bit c set if colour channel c was clamped at 0 */
 } orc_proj;
@@ -193,7 +194,7 @@ typedef struct {
   int clx, cly; /* Jacobian clamp active on x / y */
   double qn[4], qnorm, Rq[9], s[3], M[9], Sig[9], V[9], J[6];
   double a, b, c, det, A, B, C;
-  double mx, my, o, lmax, rarg;
+  double mx, my, o, lmax, rarg, hx, hy;
   double dir[3], dnorm, dhat[3], val[3], rgb[3];
   int clamped;
 } gfwd;
@@ -284,6 +285,10 @@ static void project_one(const orc_cam *cam, const orc_gauss *g, int64_t i, gfwd 
   const double h = 0.5 * (f->a - f->c);
   f->lmax = 0.5 * (f->a + f->c) + sqrt(h * h + f->b * f->b);
   f->rarg = sqrt(2.0 * log(f->o / cam->alpha_min) * f->lmax);
+  /* alpha >= alpha_min  <=>  d^T Sigma2^-1 d <= qmax; that ellipse's
+     axis-aligned bounding box has half-extents sqrt(qmax Sigma2_xx), ... */
+  f->hx = sqrt(2.0 * log(f->o / cam->alpha_min) * f->a);
+  f->hy = sqrt(2.0 * log(f->o / cam->alpha_min) * f->c);
 
   /* view-dependent colour from SH, view direction from the camera centre */
   const double Cw[3] = {-(R[0] * cam->t[0] + R[3] * cam->t[1] + R[6] * cam->t[2]),
@@ -330,6 +335,8 @@ void orc_project(const orc_cam *cam, const orc_gauss *g, orc_proj *out) {
     out->opacity[i] = f.o;
     for (int ch = 0; ch < 3; ++ch) out->rgb[ch * n + i] = f.rgb[ch];
     out->radius[i] = f.rarg;
+    out->half[i] = f.hx;
+    out->half[n + i] = f.hy;
     out->clamped[i] = f.clamped;
   }
 }

@@ -52,7 +52,7 @@ class _Gauss(C.Structure):
 
 class _Proj(C.Structure):
     _fields_ = [("mean2d", _dp), ("depth", _dp), ("conic", _dp), ("cov2d", _dp), ("opacity", _dp),
-                ("rgb", _dp), ("radius", _dp), ("visible", _ip), ("clamped", _ip)]
+                ("rgb", _dp), ("radius", _dp), ("half", _dp), ("visible", _ip), ("clamped", _ip)]
 
 
 _lib = None
@@ -139,10 +139,10 @@ def project(cam: Camera, g: Gaussians) -> dict:
     """Per-Gaussian EWA projection (FP64)."""
     n = g.n
     out = dict(mean2d=np.zeros((2, n)), depth=np.zeros(n), conic=np.zeros((3, n)), cov2d=np.zeros((3, n)),
-               opacity=np.zeros(n), rgb=np.zeros((3, n)), radius=np.zeros(n),
+               opacity=np.zeros(n), rgb=np.zeros((3, n)), radius=np.zeros(n), half=np.zeros((2, n)),
                visible=np.zeros(n, np.int32), clamped=np.zeros(n, np.int32))
     p = _Proj(_d(out["mean2d"]), _d(out["depth"]), _d(out["conic"]), _d(out["cov2d"]), _d(out["opacity"]),
-              _d(out["rgb"]), _d(out["radius"]), _i(out["visible"]), _i(out["clamped"]))
+              _d(out["rgb"]), _d(out["radius"]), _d(out["half"]), _i(out["visible"]), _i(out["clamped"]))
     gc = g.c()
     lib().orc_project(C.byref(cam.c()), C.byref(gc), C.byref(p))
     out["_c"] = p

@@ -205,14 +205,16 @@ __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev
 }
 
 __global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const float *rec,
-                            const int32_t *radius, int W, int H, int tiles_x, uint32_t capacity,
+                            const int32_t *radius, int64_t n, int W, int H, int tiles_x, uint32_t capacity,
                             uint32_t *tile_keys, uint32_t *vals) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= (int64_t)*count_dev) return;
   const uint32_t g = order[j];
   const float4 r0 = *(const float4 *)(rec + (size_t)g * GS_REC_FLOATS);
   int tx0, ty0, tx1, ty1;
-  if (!tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[g], W, H, tx0, ty0, tx1, ty1)) return;
+  if (!tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[g], radius[n + g], W, H, tx0, ty0, tx1,
+                 ty1))
+    return;
   uint32_t o = offs[j];
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
@@ -416,7 +418,7 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
     kk[0] = L.ktmp; vv[0] = L.vtmp; kk[1] = tile_ids; vv[1] = values;
   }
   const uint32_t *order = order_buf ? L.vB : L.vA;
-  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, proj->rec, proj->radius, W, H, tx,
+  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, proj->rec, proj->radius, n, W, H, tx,
             (uint32_t)capacity, kk[0], vv[0]);
   int res = 0;
   if ((st = radix_sort(kk, vv, nullptr, M, np, shifts, widths, rw, s, &res)) != GS_OK) return st;

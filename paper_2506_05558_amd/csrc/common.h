@@ -97,17 +97,17 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v) {
   return v;
 }
 
-// Inclusive tile rect of a support square, in FP32 with one rounding per
-// bound (mean -/+ radius), then ceil/floor, clipping and integer division.
-// Returns false when the square holds no pixel of the image.
-__device__ __forceinline__ bool tile_rect(float mx, float my, int radius, int W, int H, int &tx0, int &ty0,
+// Inclusive tile rect of a support rect, in FP32 with one rounding per
+// bound (mean -/+ half-width), then ceil/floor, clipping and integer
+// division.  Returns false when the rect holds no pixel of the image.
+__device__ __forceinline__ bool tile_rect(float mx, float my, int rx, int ry, int W, int H, int &tx0, int &ty0,
                                           int &tx1, int &ty1) {
-  if (radius <= 0) return false;
-  const float r = (float)radius;
-  const float fu0 = fmaxf(ceilf(__fsub_rn(mx, r)), 0.0f);
-  const float fu1 = fminf(floorf(__fadd_rn(mx, r)), (float)(W - 1));
-  const float fv0 = fmaxf(ceilf(__fsub_rn(my, r)), 0.0f);
-  const float fv1 = fminf(floorf(__fadd_rn(my, r)), (float)(H - 1));
+  if (rx <= 0 || ry <= 0) return false;
+  const float fx = (float)rx, fy = (float)ry;
+  const float fu0 = fmaxf(ceilf(__fsub_rn(mx, fx)), 0.0f);
+  const float fu1 = fminf(floorf(__fadd_rn(mx, fx)), (float)(W - 1));
+  const float fv0 = fmaxf(ceilf(__fsub_rn(my, fy)), 0.0f);
+  const float fv1 = fminf(floorf(__fadd_rn(my, fy)), (float)(H - 1));
   if (!(fu0 <= fu1) || !(fv0 <= fv1)) return false;
   tx0 = (int)fu0 / GS_TILE;
   tx1 = (int)fu1 / GS_TILE;

@@ -3,9 +3,11 @@
 //
 // One lane per Gaussian; parameters are read as SoA planes (every load of a
 // wave is one contiguous 256-byte segment per plane), the pose is a uniform
-// 48-byte read.  The geometry runs in FP64: on gfx950 the FP64 vector rate
-// equals the unpacked FP32 rate, so the extra precision is free in a kernel
-// bounded by HBM traffic (236 B in + 56 B out per SH-degree-3 Gaussian).
+// 48-byte read.  Geometry runs in FP64: on gfx950 the FP64 vector rate
+// equals the unpacked FP32 rate, so the extra precision costs nothing in a
+// kernel bounded by HBM traffic (236 B in + 72 B out per SH-degree-3
+// Gaussian).  The SH colour terms of the adjoint stream one coefficient at
+// a time in FP32 to keep the register footprint, and with it occupancy, up.
 #include "common.h"
 
 namespace gsmi {
@@ -28,78 +30,47 @@ constexpr double kY3c = 0.4570457994644658;
 constexpr double kY3d = 0.3731763325901154;
 constexpr double kY3e = 1.445305721320277;
 
-template <int DEG>
-__device__ __forceinline__ void sh_basis(double x, double y, double z, double *Y) {
-  Y[0] = kY0;
-  if (DEG >= 1) {
-    Y[1] = -kY1 * y;
-    Y[2] = kY1 * z;
-    Y[3] = -kY1 * x;
-  }
-  if (DEG >= 2) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = kY2a * x * y;
-    Y[5] = -kY2a * y * z;
-    Y[6] = kY2b * (2.0 * zz - xx - yy);
-    Y[7] = -kY2a * x * z;
-    Y[8] = kY2c * (xx - yy);
-    if (DEG >= 3) {
-      Y[9] = -kY3a * y * (3.0 * xx - yy);
-      Y[10] = kY3b * x * y * z;
-      Y[11] = -kY3c * y * (4.0 * zz - xx - yy);
-      Y[12] = kY3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-      Y[13] = -kY3c * x * (4.0 * zz - xx - yy);
-      Y[14] = kY3e * z * (xx - yy);
-      Y[15] = -kY3a * x * (xx - 3.0 * yy);
-    }
-  }
-}
-
-// Gradient of sum_k w[k] Y_k(x, y, z) with respect to (x, y, z), the basis
-// polynomials differentiated as functions on R^3.
-template <int DEG>
-__device__ __forceinline__ void sh_basis_vjp(double x, double y, double z, const double *w, double &gx, double &gy,
-                                             double &gz) {
-  gx = gy = gz = 0.0;
-  if (DEG >= 1) {
-    gy -= kY1 * w[1];
-    gz += kY1 * w[2];
-    gx -= kY1 * w[3];
-  }
-  if (DEG >= 2) {
-    gx += kY2a * y * w[4];
-    gy += kY2a * x * w[4];
-    gy -= kY2a * z * w[5];
-    gz -= kY2a * y * w[5];
-    gx -= 2.0 * kY2b * x * w[6];
-    gy -= 2.0 * kY2b * y * w[6];
-    gz += 4.0 * kY2b * z * w[6];
-    gx -= kY2a * z * w[7];
-    gz -= kY2a * x * w[7];
-    gx += 2.0 * kY2c * x * w[8];
-    gy -= 2.0 * kY2c * y * w[8];
-  }
-  if (DEG >= 3) {
-    const double xx = x * x, yy = y * y, zz = z * z;
-    gx -= 6.0 * kY3a * x * y * w[9];
-    gy -= kY3a * (3.0 * xx - 3.0 * yy) * w[9];
-    gx += kY3b * y * z * w[10];
-    gy += kY3b * x * z * w[10];
-    gz += kY3b * x * y * w[10];
-    gx += 2.0 * kY3c * x * y * w[11];
-    gy -= kY3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
-    gz -= 8.0 * kY3c * y * z * w[11];
-    gx -= 6.0 * kY3d * x * z * w[12];
-    gy -= 6.0 * kY3d * y * z * w[12];
-    gz += kY3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
-    gx -= kY3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
-    gy += 2.0 * kY3c * x * y * w[13];
-    gz -= 8.0 * kY3c * x * z * w[13];
-    gx += 2.0 * kY3e * x * z * w[14];
-    gy -= 2.0 * kY3e * y * z * w[14];
-    gz += kY3e * (xx - yy) * w[14];
-    gx -= kY3a * (3.0 * xx - 3.0 * yy) * w[15];
-    gy += 6.0 * kY3a * x * y * w[15];
+// Basis function k at the unit direction (x, y, z) and its gradient with
+// respect to (x, y, z) as a polynomial on R^3.  T is float or double.
+template <class T>
+__device__ __forceinline__ void sh_term(int k, T x, T y, T z, T &Y, T &gx, T &gy, T &gz) {
+  const T xx = x * x, yy = y * y, zz = z * z;
+  switch (k) {
+    case 0: Y = (T)kY0; gx = gy = gz = 0; break;
+    case 1: Y = -(T)kY1 * y; gx = 0; gy = -(T)kY1; gz = 0; break;
+    case 2: Y = (T)kY1 * z; gx = 0; gy = 0; gz = (T)kY1; break;
+    case 3: Y = -(T)kY1 * x; gx = -(T)kY1; gy = 0; gz = 0; break;
+    case 4: Y = (T)kY2a * x * y; gx = (T)kY2a * y; gy = (T)kY2a * x; gz = 0; break;
+    case 5: Y = -(T)kY2a * y * z; gx = 0; gy = -(T)kY2a * z; gz = -(T)kY2a * y; break;
+    case 6:
+      Y = (T)kY2b * (2 * zz - xx - yy); gx = -2 * (T)kY2b * x; gy = -2 * (T)kY2b * y; gz = 4 * (T)kY2b * z;
+      break;
+    case 7: Y = -(T)kY2a * x * z; gx = -(T)kY2a * z; gy = 0; gz = -(T)kY2a * x; break;
+    case 8: Y = (T)kY2c * (xx - yy); gx = 2 * (T)kY2c * x; gy = -2 * (T)kY2c * y; gz = 0; break;
+    case 9:
+      Y = -(T)kY3a * y * (3 * xx - yy); gx = -6 * (T)kY3a * x * y; gy = -(T)kY3a * (3 * xx - 3 * yy); gz = 0;
+      break;
+    case 10:
+      Y = (T)kY3b * x * y * z; gx = (T)kY3b * y * z; gy = (T)kY3b * x * z; gz = (T)kY3b * x * y;
+      break;
+    case 11:
+      Y = -(T)kY3c * y * (4 * zz - xx - yy);
+      gx = 2 * (T)kY3c * x * y; gy = -(T)kY3c * (4 * zz - xx - 3 * yy); gz = -8 * (T)kY3c * y * z;
+      break;
+    case 12:
+      Y = (T)kY3d * z * (2 * zz - 3 * xx - 3 * yy);
+      gx = -6 * (T)kY3d * x * z; gy = -6 * (T)kY3d * y * z; gz = (T)kY3d * (6 * zz - 3 * xx - 3 * yy);
+      break;
+    case 13:
+      Y = -(T)kY3c * x * (4 * zz - xx - yy);
+      gx = -(T)kY3c * (4 * zz - 3 * xx - yy); gy = 2 * (T)kY3c * x * y; gz = -8 * (T)kY3c * x * z;
+      break;
+    case 14:
+      Y = (T)kY3e * z * (xx - yy); gx = 2 * (T)kY3e * x * z; gy = -2 * (T)kY3e * y * z; gz = (T)kY3e * (xx - yy);
+      break;
+    default:
+      Y = -(T)kY3a * x * (xx - 3 * yy); gx = -(T)kY3a * (3 * xx - 3 * yy); gy = 6 * (T)kY3a * x * y; gz = 0;
+      break;
   }
 }
 
@@ -110,23 +81,19 @@ struct ProjArgs {
   const float *pose;
   const float *means, *log_scales, *quats, *opac, *sh;
   float *rec;
-  int32_t *radius, *tiles;
+  int32_t *radius, *tiles;  // radius: [2][n] (rx, ry)
 };
 
-// Everything one Gaussian's forward produces, in FP64.
-struct Fwd {
-  double R[9], t[3];
-  double mu[3], p[3], z, iz;
+// Geometry of one Gaussian's forward, in FP64.
+struct Geo {
+  double R[9];
+  double p[3], iz;
   bool clx, cly;
   double J00, J02, J11, J12;
-  double qn[4], qinv;  // normalised quaternion, 1/|q|
+  double qn[4], qinv;
   double Rq[9], s[3], M[9];
-  double T[6], TM[6];  // T = J R (2x3), TM = T M
+  double T[6], TM[6];
   double a, b, c, A, B, C;
-  double mx, my, o;
-  double dhat[3], dinv;
-  double val[3];
-  int radius;
 };
 
 __device__ __forceinline__ void load_pose(const float *pose, double R[9], double t[3]) {
@@ -136,33 +103,26 @@ __device__ __forceinline__ void load_pose(const float *pose, double R[9], double
   for (int k = 0; k < 3; ++k) t[k] = (double)pose[9 + k];
 }
 
-// Returns false for culled Gaussians (then only R, t, mu, p are valid).
-template <int DEG>
-__device__ __forceinline__ bool forward_one(const ProjArgs &a, int64_t i, Fwd &f) {
+// Camera-space point and the 2D covariance.  Returns false if culled by
+// the near plane or a non-positive determinant.
+__device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const double mu[3], const double t[3],
+                                         Geo &f) {
   const int64_t n = a.n;
-  load_pose(a.pose, f.R, f.t);
-  f.mu[0] = a.means[i];
-  f.mu[1] = a.means[n + i];
-  f.mu[2] = a.means[2 * n + i];
 #pragma unroll
-  for (int r = 0; r < 3; ++r) f.p[r] = f.R[3 * r] * f.mu[0] + f.R[3 * r + 1] * f.mu[1] + f.R[3 * r + 2] * f.mu[2] + f.t[r];
-  f.z = f.p[2];
-  if (!(f.z > a.near_plane)) return false;
-  f.iz = 1.0 / f.z;
-
-  // perspective Jacobian, guard band on x/z and y/z
+  for (int r = 0; r < 3; ++r) f.p[r] = f.R[3 * r] * mu[0] + f.R[3 * r + 1] * mu[1] + f.R[3 * r + 2] * mu[2] + t[r];
+  if (!(f.p[2] > a.near_plane)) return false;
+  f.iz = 1.0 / f.p[2];
   const double limx = a.guard * 0.5 * a.W / a.fx, limy = a.guard * 0.5 * a.H / a.fy;
   const double tx = f.p[0] * f.iz, ty = f.p[1] * f.iz;
   f.clx = tx < -limx || tx > limx;
   f.cly = ty < -limy || ty > limy;
-  const double xc = f.clx ? (tx < 0.0 ? -limx : limx) * f.z : f.p[0];
-  const double yc = f.cly ? (ty < 0.0 ? -limy : limy) * f.z : f.p[1];
+  const double xc = f.clx ? (tx < 0.0 ? -limx : limx) * f.p[2] : f.p[0];
+  const double yc = f.cly ? (ty < 0.0 ? -limy : limy) * f.p[2] : f.p[1];
   f.J00 = a.fx * f.iz;
   f.J11 = a.fy * f.iz;
   f.J02 = -a.fx * xc * f.iz * f.iz;
   f.J12 = -a.fy * yc * f.iz * f.iz;
 
-  // rotation of the Gaussian
   const double q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
   f.qinv = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
   const double w = q0 * f.qinv, x = q1 * f.qinv, y = q2 * f.qinv, z = q3 * f.qinv;
@@ -182,7 +142,6 @@ __device__ __forceinline__ bool forward_one(const ProjArgs &a, int64_t i, Fwd &f
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) f.M[3 * r + c] = f.Rq[3 * r + c] * f.s[c];
-
   // Sigma2 = (J R M)(J R M)^T + eps I, with J R formed first (2x3)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -203,63 +162,78 @@ __device__ __forceinline__ bool forward_one(const ProjArgs &a, int64_t i, Fwd &f
   f.A = f.c * idet;
   f.B = -f.b * idet;
   f.C = f.a * idet;
-
-  f.mx = a.fx * f.p[0] * f.iz + a.cx;
-  f.my = a.fy * f.p[1] * f.iz + a.cy;
-  if (!(fabs(f.mx) < 8388608.0 && fabs(f.my) < 8388608.0)) return false;  // |mean| < 2^23 px
-
-  f.o = 1.0 / (1.0 + exp(-(double)a.opac[i]));
-  if (!(f.o >= a.alpha_min)) return false;
-  const double hd = 0.5 * (f.a - f.c);
-  const double lmax = 0.5 * (f.a + f.c) + sqrt(hd * hd + f.b * f.b);
-  const double rr = sqrt(2.0 * log(f.o / a.alpha_min) * lmax);
-  f.radius = (int)ceil(fmin(rr * (1.0 + 1e-4) + 1e-3, 4194304.0));
-
-  // colour: view direction from the camera centre C = -R^T t
-  const double Cx = -(f.R[0] * f.t[0] + f.R[3] * f.t[1] + f.R[6] * f.t[2]);
-  const double Cy = -(f.R[1] * f.t[0] + f.R[4] * f.t[1] + f.R[7] * f.t[2]);
-  const double Cz = -(f.R[2] * f.t[0] + f.R[5] * f.t[1] + f.R[8] * f.t[2]);
-  const double dx = f.mu[0] - Cx, dy = f.mu[1] - Cy, dz = f.mu[2] - Cz;
-  f.dinv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-  f.dhat[0] = dx * f.dinv;
-  f.dhat[1] = dy * f.dinv;
-  f.dhat[2] = dz * f.dinv;
-  constexpr int NB = (DEG + 1) * (DEG + 1);
-  double Y[16];
-  sh_basis<DEG>(f.dhat[0], f.dhat[1], f.dhat[2], Y);
-#pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    double v = 0.5;
-#pragma unroll
-    for (int k = 0; k < NB; ++k) v += (double)a.sh[(int64_t)(k * 3 + ch) * n + i] * Y[k];
-    f.val[ch] = v;
-  }
   return true;
+}
+
+// Unit view direction from the camera centre C = -R^T t and 1/|mu - C|.
+__device__ __forceinline__ void view_dir(const double R[9], const double t[3], const double mu[3], double d[3],
+                                         double &dinv) {
+  const double Cx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
+  const double Cy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
+  const double Cz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
+  const double dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
+  dinv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+  d[0] = dx * dinv;
+  d[1] = dy * dinv;
+  d[2] = dz * dinv;
 }
 
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project(ProjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
-  Fwd f;
-  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-  int radius = 0, tiles = 0;
-  if (forward_one<DEG>(a, i, f)) {
-    const double hx = rint(f.mx), hy = rint(f.my);
-    r0 = make_float4((float)hx, (float)hy, (float)(f.mx - hx), (float)(f.my - hy));
-    r1 = make_float4((float)f.A, (float)f.B, (float)f.C, (float)f.o);
-    r2 = make_float4((float)fmax(f.val[0], 0.0), (float)fmax(f.val[1], 0.0), (float)fmax(f.val[2], 0.0),
-                     (float)f.z);
-    radius = f.radius;
+  const int64_t n = a.n;
+  Geo f;
+  double t[3];
+  load_pose(a.pose, f.R, t);
+  const double mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, r3 = r0;
+  int rx = 0, ry = 0, tiles = 0;
+  bool ok = geometry(a, i, mu, t, f);
+  double mx = 0, my = 0, o = 0;
+  if (ok) {
+    mx = a.fx * f.p[0] * f.iz + a.cx;
+    my = a.fy * f.p[1] * f.iz + a.cy;
+    ok = fabs(mx) < 8388608.0 && fabs(my) < 8388608.0;  // |mean| < 2^23 px
+  }
+  if (ok) {
+    o = 1.0 / (1.0 + exp(-(double)a.opac[i]));
+    ok = o >= a.alpha_min;
+  }
+  if (ok) {
+    // support: o exp(-q/2) >= alpha_min  <=>  q = d^T Sigma2^-1 d <= qmax;
+    // its bounding box has half-extents sqrt(qmax a), sqrt(qmax c)
+    const double qmax = 2.0 * log(o / a.alpha_min);
+    const double hx = sqrt(qmax * f.a), hy = sqrt(qmax * f.c);
+    rx = (int)ceil(fmin(hx * (1.0 + 1e-4) + 1e-3, 4194304.0));
+    ry = (int)ceil(fmin(hy * (1.0 + 1e-4) + 1e-3, 4194304.0));
+    double d[3], dinv;
+    view_dir(f.R, t, mu, d, dinv);
+    double val[3] = {0.5, 0.5, 0.5};
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double Y, gx, gy, gz;
+      sh_term<double>(k, d[0], d[1], d[2], Y, gx, gy, gz);
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) val[ch] += (double)a.sh[(int64_t)(k * 3 + ch) * n + i] * Y;
+    }
+    const double hxm = rint(mx), hym = rint(my);
+    r0 = make_float4((float)hxm, (float)hym, (float)(mx - hxm), (float)(my - hym));
+    r1 = make_float4((float)f.A, (float)f.B, (float)f.C, (float)o);
+    r2 = make_float4((float)fmax(val[0], 0.0), (float)fmax(val[1], 0.0), (float)fmax(val[2], 0.0), (float)f.p[2]);
+    r3 = make_float4((float)hx, (float)hy, 0.f, 0.f);
     int tx0, ty0, tx1, ty1;
-    if (tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius, a.W, a.H, tx0, ty0, tx1, ty1))
+    if (tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), rx, ry, a.W, a.H, tx0, ty0, tx1, ty1))
       tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
   }
   float4 *dst = (float4 *)(a.rec + i * GS_REC_FLOATS);
   dst[0] = r0;
   dst[1] = r1;
   dst[2] = r2;
-  a.radius[i] = radius;
+  dst[3] = r3;
+  a.radius[i] = rx;
+  a.radius[n + i] = ry;
   a.tiles[i] = tiles;
 }
 
@@ -274,49 +248,61 @@ struct BwdArgs {
 template <int DEG>
 __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, double pose_acc[12]) {
   const ProjArgs &a = ba.p;
-  Fwd f;
-  if (!forward_one<DEG>(a, i, f)) return;
   const int64_t n = a.n;
+  Geo f;
+  double t[3];
+  load_pose(a.pose, f.R, t);
+  const double mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
+  if (!geometry(a, i, mu, t, f)) return;
   const float4 *gp4 = (const float4 *)(ba.g2d + i * 12);
   const float4 g0 = gp4[0], g1 = gp4[1], g2 = gp4[2];
   // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -)
-  const double gmx = g0.x, gmy = g0.y, gA = g0.z, gB = g0.w, gC = g1.x, gop = g1.y, gz = g2.y;
-  const double gcol[3] = {g1.z, g1.w, g2.x};
+  const float4 rgbz = *(const float4 *)(a.rec + i * GS_REC_FLOATS + 8);
 
   double gmu[3] = {0.0, 0.0, 0.0};
 
-  // colour -> SH coefficients and view direction (no pose path, section 4.3)
+  // colour -> SH coefficients and view direction (no pose path, section 4.3).
+  // A channel whose colour was clamped at 0 passes no gradient.
   {
+    const float gc0 = rgbz.x > 0.f ? g1.z : 0.f;
+    const float gc1 = rgbz.y > 0.f ? g1.w : 0.f;
+    const float gc2 = rgbz.z > 0.f ? g2.x : 0.f;
+    double dd[3], dinv;
+    view_dir(f.R, t, mu, dd, dinv);
+    const float x = (float)dd[0], y = (float)dd[1], z = (float)dd[2];
+    float gx = 0.f, gy = 0.f, gz = 0.f;
     constexpr int NB = (DEG + 1) * (DEG + 1);
-    double Y[16], wk[16];
-    sh_basis<DEG>(f.dhat[0], f.dhat[1], f.dhat[2], Y);
 #pragma unroll
-    for (int k = 0; k < NB; ++k) wk[k] = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      if (!(f.val[ch] > 0.0)) continue;
-      const double gv = gcol[ch];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        const int64_t off = (int64_t)(k * 3 + ch) * n + i;
-        ba.gsh[off] += (float)(gv * Y[k]);
-        wk[k] += gv * (double)a.sh[off];
+    for (int k = 0; k < NB; ++k) {
+      float Y, ax, ay, az;
+      sh_term<float>(k, x, y, z, Y, ax, ay, az);
+      const int64_t o0 = (int64_t)(k * 3) * n + i;
+      const float s0 = a.sh[o0], s1 = a.sh[o0 + n], s2 = a.sh[o0 + 2 * n];
+      ba.gsh[o0] += gc0 * Y;
+      ba.gsh[o0 + n] += gc1 * Y;
+      ba.gsh[o0 + 2 * n] += gc2 * Y;
+      if (DEG > 0) {
+        const float wk = gc0 * s0 + gc1 * s1 + gc2 * s2;
+        gx += wk * ax;
+        gy += wk * ay;
+        gz += wk * az;
       }
     }
     if (DEG > 0) {
-      double gx, gy, gzz;
-      sh_basis_vjp<DEG>(f.dhat[0], f.dhat[1], f.dhat[2], wk, gx, gy, gzz);
-      const double radial = gx * f.dhat[0] + gy * f.dhat[1] + gzz * f.dhat[2];
-      gmu[0] += (gx - radial * f.dhat[0]) * f.dinv;
-      gmu[1] += (gy - radial * f.dhat[1]) * f.dinv;
-      gmu[2] += (gzz - radial * f.dhat[2]) * f.dinv;
+      const double radial = gx * dd[0] + gy * dd[1] + gz * dd[2];
+      gmu[0] += (gx - radial * dd[0]) * dinv;
+      gmu[1] += (gy - radial * dd[1]) * dinv;
+      gmu[2] += (gz - radial * dd[2]) * dinv;
     }
   }
 
-  ba.go[i] += (float)(gop * f.o * (1.0 - f.o));
+  {
+    const double o = 1.0 / (1.0 + exp(-(double)a.opac[i]));
+    ba.go[i] += (float)((double)g1.y * o * (1.0 - o));
+  }
 
   // conic -> Sigma2: dL/dSigma2 = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
-  const double hB = 0.5 * gB;
+  const double gA = g0.z, hB = 0.5 * (double)g0.w, gC = g1.x;
   const double QG00 = f.A * gA + f.B * hB, QG01 = f.A * hB + f.B * gC;
   const double QG10 = f.B * gA + f.C * hB, QG11 = f.B * hB + f.C * gC;
   const double S00 = -(QG00 * f.A + QG01 * f.B);
@@ -331,26 +317,23 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, doubl
     gTM[3 + c] = 2.0 * (S01 * f.TM[c] + S11 * f.TM[3 + c]);
   }
   // TM = T M: gT = gTM M^T, gM = T^T gTM
-  double gT[6], gM[9];
+  double gT[6];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       gT[3 * r + c] = gTM[3 * r] * f.M[3 * c] + gTM[3 * r + 1] * f.M[3 * c + 1] + gTM[3 * r + 2] * f.M[3 * c + 2];
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) gM[3 * r + c] = f.T[r] * gTM[c] + f.T[3 + r] * gTM[3 + c];
 
-  // M = Rq diag(s): scales and quaternion
+  // M = Rq diag(s): scales and quaternion (gM formed entry by entry)
   double gRq[9];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double gs = 0.0;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      gRq[3 * r + c] = gM[3 * r + c] * f.s[c];
-      gs += gM[3 * r + c] * f.Rq[3 * r + c];
+      const double gM = f.T[r] * gTM[c] + f.T[3 + r] * gTM[3 + c];
+      gRq[3 * r + c] = gM * f.s[c];
+      gs += gM * f.Rq[3 * r + c];
     }
     ba.gl[c * n + i] += (float)(gs * f.s[c]);
   }
@@ -369,24 +352,18 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, doubl
     ba.gq[3 * n + i] += (float)((dz - proj * z) * f.qinv);
   }
 
-  // T = J R: gJ = gT R^T (entries 00, 02, 11, 12), gR from the covariance = J^T gT
+  // T = J R: gJ = gT R^T (entries 00, 02, 11, 12); gR from the covariance = J^T gT
   const double gJ00 = gT[0] * f.R[0] + gT[1] * f.R[1] + gT[2] * f.R[2];
   const double gJ02 = gT[0] * f.R[6] + gT[1] * f.R[7] + gT[2] * f.R[8];
   const double gJ11 = gT[3] * f.R[3] + gT[4] * f.R[4] + gT[5] * f.R[5];
   const double gJ12 = gT[3] * f.R[6] + gT[4] * f.R[7] + gT[5] * f.R[8];
-  double gR[9];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    gR[c] = f.J00 * gT[c];
-    gR[3 + c] = f.J11 * gT[3 + c];
-    gR[6 + c] = f.J02 * gT[c] + f.J12 * gT[3 + c];
-  }
 
   // camera-space point: mean2d, depth and the Jacobian entries
+  const double gmx = g0.x, gmy = g0.y;
   const double iz2 = f.iz * f.iz;
   double gp0 = gmx * a.fx * f.iz;
   double gp1 = gmy * a.fy * f.iz;
-  double gp2 = gz - (gmx * a.fx * f.p[0] + gmy * a.fy * f.p[1]) * iz2 - (gJ00 * a.fx + gJ11 * a.fy) * iz2;
+  double gp2 = (double)g2.y - (gmx * a.fx * f.p[0] + gmy * a.fy * f.p[1]) * iz2 - (gJ00 * a.fx + gJ11 * a.fy) * iz2;
   if (f.clx) {
     gp2 -= gJ02 * f.J02 * f.iz;
   } else {
@@ -408,12 +385,14 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, doubl
   ba.gm[n + i] += (float)gmu[1];
   ba.gm[2 * n + i] += (float)gmu[2];
 
+  // pose: dL/dR = J^T gT (covariance) + gp mu^T; dL/dt = gp
   const double gp[3] = {gp0, gp1, gp2};
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) pose_acc[3 * r + c] += gR[3 * r + c] + gp[r] * f.mu[c];
-    pose_acc[9 + r] += gp[r];
+  for (int c = 0; c < 3; ++c) {
+    pose_acc[c] += f.J00 * gT[c] + gp0 * mu[c];
+    pose_acc[3 + c] += f.J11 * gT[3 + c] + gp1 * mu[c];
+    pose_acc[6 + c] += f.J02 * gT[c] + f.J12 * gT[3 + c] + gp2 * mu[c];
+    pose_acc[9 + c] += gp[c];
   }
 }
 
@@ -422,9 +401,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs ba, const int32_
   double acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ba.p.n; i += stride)
-    if (tiles[i] > 0) backward_one<DEG>(ba, i, acc);
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < ba.p.n && tiles[i] > 0) backward_one<DEG>(ba, i, acc);
 
   // block reduction of the 12 pose partials (fixed order: deterministic)
   __shared__ double red[kBlock / 64][12];
@@ -446,42 +424,45 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs ba, const int32_
 }
 
 // Sum of the block partials (fixed order) into dL/d[R|t] and the left twist.
-__global__ __launch_bounds__(256) void k_pose_reduce(const double *partials, int nparts, const float *pose,
+__global__ __launch_bounds__(256) void k_pose_reduce(const double *partials, int64_t nparts, const float *pose,
                                                      double *d_pose, double *d_twist) {
-  __shared__ double red[12][17];
-  const int q = threadIdx.x / 16, r = threadIdx.x % 16;
-  if (q < 12) {
-    double v = 0.0;
-    for (int b = r; b < nparts; b += 16) v += partials[(int64_t)b * 12 + q];
-    red[q][r] = v;
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+  for (int64_t b = threadIdx.x; b < nparts; b += 256)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] += partials[b * 12 + k];
+  __shared__ double red[4][12];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][k] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double g[12];
-    for (int k = 0; k < 12; ++k) {
-      double v = 0.0;
-      for (int j = 0; j < 16; ++j) v += red[k][j];
-      g[k] = v;
-    }
-    if (d_pose)
-      for (int k = 0; k < 12; ++k) d_pose[k] += g[k];
-    if (d_twist) {
-      double R[9], t[3];
-      for (int k = 0; k < 9; ++k) R[k] = pose[k];
-      for (int k = 0; k < 3; ++k) t[k] = pose[9 + k];
-      // M = dL/dR R^T + dL/dt t^T; rho = dL/dt; phi = (M21 - M12, M02 - M20, M10 - M01)
-      double M[9];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          M[3 * i + j] = g[3 * i] * R[3 * j] + g[3 * i + 1] * R[3 * j + 1] + g[3 * i + 2] * R[3 * j + 2] +
-                         g[9 + i] * t[j];
-      d_twist[0] += g[9];
-      d_twist[1] += g[10];
-      d_twist[2] += g[11];
-      d_twist[3] += M[7] - M[5];
-      d_twist[4] += M[2] - M[6];
-      d_twist[5] += M[3] - M[1];
-    }
+  if (threadIdx.x != 0) return;
+  double g[12];
+  for (int k = 0; k < 12; ++k) g[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+  if (d_pose)
+    for (int k = 0; k < 12; ++k) d_pose[k] += g[k];
+  if (d_twist) {
+    double R[9], t[3];
+    for (int k = 0; k < 9; ++k) R[k] = pose[k];
+    for (int k = 0; k < 3; ++k) t[k] = pose[9 + k];
+    // M = dL/dR R^T + dL/dt t^T; rho = dL/dt; phi = (M21 - M12, M02 - M20, M10 - M01)
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        M[3 * r + c] = g[3 * r] * R[3 * c] + g[3 * r + 1] * R[3 * c + 1] + g[3 * r + 2] * R[3 * c + 2] +
+                       g[9 + r] * t[c];
+    d_twist[0] += g[9];
+    d_twist[1] += g[10];
+    d_twist[2] += g[11];
+    d_twist[3] += M[7] - M[5];
+    d_twist[4] += M[2] - M[6];
+    d_twist[5] += M[3] - M[1];
   }
 }
 
@@ -524,8 +505,6 @@ ProjArgs make_args(const gs_camera *cam, const gs_raster_params *rp, const gs_ga
   return a;
 }
 
-constexpr int kMaxBwdBlocks = 2048;
-
 }  // namespace
 }  // namespace gsmi
 
@@ -564,8 +543,8 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
 namespace gsmi {
 
 size_t project_bwd_workspace(int64_t n) {
-  (void)n;
-  return align_up(sizeof(double) * 12 * kMaxBwdBlocks);
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  return align_up(sizeof(double) * 12 * (size_t)(blocks > 0 ? blocks : 1));
 }
 
 gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
@@ -574,6 +553,7 @@ gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs
   if (g->n == 0) return GS_OK;
   BwdArgs ba;
   ba.p = make_args(cam, rp, g);
+  ba.p.rec = proj->rec;
   ba.g2d = g2d;
   ba.gm = grads->means;
   ba.gl = grads->log_scales;
@@ -581,8 +561,7 @@ gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs
   ba.go = grads->opacity_logits;
   ba.gsh = grads->sh;
   ba.partials = (double *)ws;
-  int64_t blocks = (g->n + kBlock - 1) / kBlock;
-  if (blocks > kMaxBwdBlocks) blocks = kMaxBwdBlocks;
+  const int64_t blocks = (g->n + kBlock - 1) / kBlock;
   switch (g->sh_degree) {
     case 0: GS_LAUNCH("project_bwd", k_project_bwd<0>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
     case 1: GS_LAUNCH("project_bwd", k_project_bwd<1>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
@@ -590,8 +569,7 @@ gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs
     default: GS_LAUNCH("project_bwd", k_project_bwd<3>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
   }
   if (d_pose || d_twist)
-    GS_LAUNCH("pose_reduce", k_pose_reduce, 1, 256, 0, s, (const double *)ws, (int)blocks, cam->pose, d_pose,
-              d_twist);
+    GS_LAUNCH("pose_reduce", k_pose_reduce, 1, 256, 0, s, (const double *)ws, blocks, cam->pose, d_pose, d_twist);
   return GS_OK;
 }
 

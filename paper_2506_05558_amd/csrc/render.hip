@@ -1,20 +1,23 @@
 // Per-tile compositing (forward) and its adjoint.
 //
 // One 256-lane workgroup (four wave64) per 16x16 tile, one lane per pixel;
-// wave w holds pixel rows 4w..4w+3.  The tile's depth-ordered list is walked
-// in batches of 256: each lane gathers one 48-byte render record, turns it
-// into tile-relative form and stages it in LDS; every lane then reads the
-// batch back with broadcast LDS loads.  The workgroup leaves as soon as all
-// 256 pixels have stopped (barrier count), a wave skips compute once its 64
-// pixels are done.
+// wave w owns the 8x8 quadrant (w & 1, w >> 1) of the tile.  The tile's
+// depth-ordered list is walked in batches of 256 entries.  Each lane gathers
+// one 64-byte render record, converts it to tile-relative form and stages it
+// in LDS, and tests the entry's support box against the four quadrants;
+// ballots then build, per quadrant, the in-order list of the batch entries
+// whose box meets it.  Each wave walks only its own list, reading staged
+// entries with broadcast LDS loads, so a small Gaussian costs nothing in the
+// quadrants it cannot reach.  The workgroup leaves once all 256 pixels have
+// stopped; a wave leaves its list once its 64 pixels have.
 //
 // The 2D Gaussian is evaluated in the log2 domain: with d = pixel - mean,
 //   s  = -(A dx^2 + 2 B dx dy + C dy^2) / 2,       alpha = o exp(s)
 //   s2 = s log2(e) = ca dx^2 + cb dx dy + cc dy^2,  exp(s) = 2^s2
 // with (ca, cb, cc) = -log2(e) (A/2, B, C/2) folded in at staging, so one
-// v_exp_f32 per pair.  The forward and the adjoint evaluate s2, 2^s2 and
-// alpha with the same explicit operation sequence, so the adjoint retraces
-// the forward's skip decisions exactly.
+// v_exp_f32 per pair.  The forward and the adjoint stage, cull and evaluate
+// with the same code and explicit operation order, so the adjoint retraces
+// the forward's decisions exactly.
 #include "common.h"
 
 namespace gsmi {
@@ -31,24 +34,59 @@ struct RenderArgs {
   const uint32_t *values, *ranges;
 };
 
-// Staged form of one list entry: (mx, my) relative to the tile origin,
-// (ca, cb, cc), opacity, colour, depth.
-struct Staged {
-  float4 a;  // mx, my, ca, cb
-  float4 b;  // cc, o, z, (unused)
-  float4 c;  // r, g, b, (unused)
+struct Stage {
+  float4 a[kBatch];         // mean x, y relative to the tile origin, ca, cb
+  float4 b[kBatch];         // cc, opacity, depth, -
+  float4 c[kBatch];         // colour r, g, b, -
+  uint8_t list[4][kBatch];  // per quadrant: batch entries whose box meets it, in order
+  int cnt[4][4];            // [entry wave][quadrant] entries
 };
 
-__device__ __forceinline__ void stage(const float *rec, uint32_t gid, float ox, float oy, float4 &sa, float4 &sb,
-                                      float4 &sc) {
-  const float4 *r = (const float4 *)(rec + (size_t)gid * GS_REC_FLOATS);
-  const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-  // integer part minus tile origin is exact; one rounding adds the fraction
-  const float mx = __fadd_rn(__fsub_rn(r0.x, ox), r0.z);
-  const float my = __fadd_rn(__fsub_rn(r0.y, oy), r0.w);
-  sa = make_float4(mx, my, __fmul_rn(-0.5f * kLog2e, r1.x), __fmul_rn(-kLog2e, r1.y));
-  sb = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), r1.w, r2.w, 0.0f);
-  sc = make_float4(r2.x, r2.y, r2.z, 0.0f);
+// Stages entries [base, end) of the tile list (at most kBatch) and builds the
+// per-quadrant lists.  Called by all 256 lanes; contains two barriers.
+__device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, uint32_t end, float ox, float oy,
+                                            Stage &S, uint32_t *gid_out) {
+  const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
+  const uint32_t j = base + t;
+  unsigned mask = 0;
+  if (j < end) {
+    const uint32_t gid = a.values[j];
+    const float4 *r = (const float4 *)(a.rec + (size_t)gid * GS_REC_FLOATS);
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+    // integer part minus tile origin is exact; one rounding adds the fraction
+    const float mx = __fadd_rn(__fsub_rn(r0.x, ox), r0.z);
+    const float my = __fadd_rn(__fsub_rn(r0.y, oy), r0.w);
+    S.a[t] = make_float4(mx, my, __fmul_rn(-0.5f * kLog2e, r1.x), __fmul_rn(-kLog2e, r1.y));
+    S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), r1.w, r2.w, 0.0f);
+    S.c[t] = make_float4(r2.x, r2.y, r2.z, 0.0f);
+    if (gid_out) gid_out[t] = gid;
+    // support box, widened so that FP32 rounding can never cull a pixel the
+    // per-pixel test would accept
+    const float hx = r3.x * (1.0f + 1e-4f) + 1e-3f, hy = r3.y * (1.0f + 1e-4f) + 1e-3f;
+    const bool x0 = mx - hx <= 7.0f && mx + hx >= 0.0f;
+    const bool x1 = mx - hx <= 15.0f && mx + hx >= 8.0f;
+    const bool y0 = my - hy <= 7.0f && my + hy >= 0.0f;
+    const bool y1 = my - hy <= 15.0f && my + hy >= 8.0f;
+    mask = (unsigned)(x0 && y0) | (unsigned)(x1 && y0) << 1 | (unsigned)(x0 && y1) << 2 | (unsigned)(x1 && y1) << 3;
+  }
+  const uint64_t lt = lanemask_lt();
+  int rank[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t bal = __ballot((mask >> q) & 1u);
+    rank[q] = __popcll(bal & lt);
+    if (lane == 0) S.cnt[ew][q] = __popcll(bal);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if ((mask >> q) & 1u) {
+      int off = rank[q];
+      for (int w = 0; w < ew; ++w) off += S.cnt[w][q];
+      S.list[q][off] = (uint8_t)t;
+    }
+  }
+  __syncthreads();
 }
 
 // log2-domain exponent of the 2D Gaussian at offset (dx, dy).
@@ -59,6 +97,22 @@ __device__ __forceinline__ float splat_s2(float ca, float cb, float cc, float dx
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
+struct Pixel {
+  int px, py, u, v;
+  bool inside;
+};
+
+__device__ __forceinline__ Pixel pixel_of(int tile, int tiles_x, int W, int H) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  Pixel p;
+  p.px = (w & 1) * 8 + (l & 7);
+  p.py = (w >> 1) * 8 + (l >> 3);
+  p.u = (tile % tiles_x) * GS_TILE + p.px;
+  p.v = (tile / tiles_x) * GS_TILE + p.py;
+  p.inside = p.u < W && p.v < H;
+  return p;
+}
+
 // ------------------------------------------------------------------ forward
 struct FwdOut {
   float *image, *depth, *alpha, *final_t;
@@ -68,56 +122,55 @@ struct FwdOut {
 __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;  // uniform over the workgroup
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int t = threadIdx.x;
-  const int px = t & 15, py = t >> 4;
-  const int u = tx * GS_TILE + px, v = ty * GS_TILE + py;
-  const bool inside = u < a.W && v < a.H;
+  const int w = threadIdx.x >> 6;
+  const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
-  const float ox = (float)(tx * GS_TILE), oy = (float)(ty * GS_TILE);
-  const float fpx = (float)px, fpy = (float)py;
+  const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
+  const float fpx = (float)P.px, fpy = (float)P.py;
 
-  __shared__ float4 sA[kBatch], sB[kBatch], sC[kBatch];
+  __shared__ Stage S;
 
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
-  int last = 0, ncomp = 0;
-  int examined = (int)(e - s);
-  bool done = !inside;
+  int last = 0, nev = 0, nsup = 0, ncomp = 0;
+  int ntile = (int)(e - s);  // tile-list entries up to and including the stop
+  bool done = !P.inside;
 
   for (uint32_t base = s; base < e; base += kBatch) {
     if (__syncthreads_count(done) == kBatch) break;
-    const uint32_t j = base + t;
-    if (j < e) stage(a.rec, a.values[j], ox, oy, sA[t], sB[t], sC[t]);
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)kBatch, e - base);
-    if (!done) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 A = sA[k];
-        const float4 B = sB[k];
-        const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-        const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
-        const float alpha = fminf(a.alpha_max, __fmul_rn(B.y, ex));
-        if (alpha < a.alpha_min) continue;
-        const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
-        if (Tn < a.t_min) {
-          done = true;
-          examined = (int)(base - s) + k + 1;
-          break;
-        }
-        const float4 C = sC[k];
-        const float w = __fmul_rn(alpha, T);
-        c0 = __fmaf_rn(C.x, w, c0);
-        c1 = __fmaf_rn(C.y, w, c1);
-        c2 = __fmaf_rn(C.z, w, c2);
-        D = __fmaf_rn(B.z, w, D);
-        T = Tn;
-        last = (int)(base - s) + k + 1;
-        ++ncomp;
-      }
+    stage_batch(a, base, e, ox, oy, S, nullptr);
+    const int cnt = S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w];
+    if (__ballot(!done) == 0) continue;
+    const int idx0 = (int)(base - s);
+    for (int i = 0; i < cnt; ++i) {
+      const int k = S.list[w][i];
+      const float4 A = S.a[k];
+      const float4 B = S.b[k];
+      const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
+      const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
+      const float alpha = fminf(a.alpha_max, __fmul_rn(B.y, ex));
+      nev += done ? 0 : 1;
+      const bool take = !done && alpha >= a.alpha_min;
+      if (__ballot(take) == 0) continue;
+      const float4 C = S.c[k];
+      const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
+      const bool stop = take && Tn < a.t_min;
+      const bool comp = take && !stop;
+      const float wgt = comp ? __fmul_rn(alpha, T) : 0.0f;
+      c0 = __fmaf_rn(C.x, wgt, c0);
+      c1 = __fmaf_rn(C.y, wgt, c1);
+      c2 = __fmaf_rn(C.z, wgt, c2);
+      D = __fmaf_rn(B.z, wgt, D);
+      T = comp ? Tn : T;
+      last = comp ? idx0 + k + 1 : last;
+      nsup += take ? 1 : 0;
+      ncomp += comp ? 1 : 0;
+      ntile = stop ? idx0 + k + 1 : ntile;
+      done = done || stop;
+      if (__ballot(!done) == 0) break;
     }
   }
-  if (!inside) return;
-  const int64_t pix = (int64_t)v * a.W + u, np = (int64_t)a.W * a.H;
+  if (!P.inside) return;
+  const int64_t pix = (int64_t)P.v * a.W + P.u, np = (int64_t)a.W * a.H;
   o.image[pix] = __fmaf_rn(T, a.bg0, c0);
   o.image[np + pix] = __fmaf_rn(T, a.bg1, c1);
   o.image[2 * np + pix] = __fmaf_rn(T, a.bg2, c2);
@@ -126,8 +179,10 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   o.final_t[pix] = T;
   o.n_contrib[pix] = last;
   if (o.stats) {
-    o.stats[pix] = examined;
-    o.stats[np + pix] = ncomp;
+    o.stats[pix] = ntile;
+    o.stats[np + pix] = nev;
+    o.stats[2 * np + pix] = nsup;
+    o.stats[3 * np + pix] = ncomp;
   }
 }
 
@@ -139,31 +194,33 @@ struct BwdIn {
   float *g2d;  // [n][12] accumulated per-Gaussian 2D gradients
 };
 
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
 // Per (wave, list entry) the ten partial gradients are summed over the 64
 // lanes with DPP, lane 63 adds them to the batch's LDS accumulator, and
 // after the batch one lane per entry issues the global float atomics.
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;
-  const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int px = t & 15, py = t >> 4;
-  const int u = tx * GS_TILE + px, v = ty * GS_TILE + py;
-  const bool inside = u < a.W && v < a.H;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
-  const float ox = (float)(tx * GS_TILE), oy = (float)(ty * GS_TILE);
-  const float fpx = (float)px, fpy = (float)py;
+  const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
+  const float fpx = (float)P.px, fpy = (float)P.py;
 
-  __shared__ float4 sA[kBatch], sB[kBatch], sC[kBatch];
+  __shared__ Stage S;
   __shared__ uint32_t sGid[kBatch];
   __shared__ float sAcc[10][kBatch];
   __shared__ int sMax;
 
-  const int64_t pix = (int64_t)v * a.W + u, np = (int64_t)a.W * a.H;
+  const int64_t pix = (int64_t)P.v * a.W + P.u, np = (int64_t)a.W * a.H;
   int ncon = 0;
   float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GA = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, ID = 0.f, Tf = 1.f;
-  if (inside) {
+  if (P.inside) {
     ncon = bi.n_contrib[pix];
     G0 = bi.g_image[pix];
     G1 = bi.g_image[np + pix];
@@ -178,7 +235,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   }
   if (t == 0) sMax = 0;
   __syncthreads();
-  if (ncon > 0) atomicMax(&sMax, ncon);
+  const int wmax = wave_max(ncon);
+  if (lane == 0 && wmax > 0) atomicMax(&sMax, wmax);
   __syncthreads();
   const uint32_t stop = min(s + (uint32_t)sMax, e);
 
@@ -186,73 +244,61 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const float GAT = GA * Tf;
 
   for (uint32_t base = s; base < stop; base += kBatch) {
-    __syncthreads();
-    const uint32_t j = base + t;
-    if (j < stop) {
-      const uint32_t gid = a.values[j];
-      sGid[t] = gid;
-      stage(a.rec, gid, ox, oy, sA[t], sB[t], sC[t]);
-    }
+    __syncthreads();  // the previous batch's flush is done with sAcc / sGid
 #pragma unroll
     for (int q = 0; q < 10; ++q) sAcc[q][t] = 0.f;
-    __syncthreads();
-    const int cnt = (int)min((uint32_t)kBatch, stop - base);
+    stage_batch(a, base, stop, ox, oy, S, sGid);
+    const int cnt = S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w];
     const int idx0 = (int)(base - s);
-    for (int k = 0; k < cnt; ++k) {
-      if (ballot(idx0 + k < ncon) == 0) break;  // no pixel of this wave reaches further
+    for (int i = 0; i < cnt; ++i) {
+      const int k = S.list[w][i];
+      if (idx0 + k >= wmax) break;  // lists ascend: no pixel of this wave reaches further
+      const float4 A = S.a[k];
+      const float4 B = S.b[k];
+      const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
+      const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
+      const float raw = __fmul_rn(B.y, ex);
+      const float alpha = fminf(a.alpha_max, raw);
+      const bool take = idx0 + k < ncon && alpha >= a.alpha_min;
+      if (__ballot(take) == 0) continue;
+      const float4 C = S.c[k];
+      const float z = B.z;
+      const float wgt = take ? __fmul_rn(alpha, T) : 0.0f;
+      P0 = __fmaf_rn(C.x, wgt, P0);
+      P1 = __fmaf_rn(C.y, wgt, P1);
+      P2 = __fmaf_rn(C.z, wgt, P2);
+      PD = __fmaf_rn(z, wgt, PD);
+      // suffix sums: everything composited after this entry plus T_final bg
+      const float S0 = I0 - P0, S1 = I1 - P1, S2 = I2 - P2, SD = ID - PD;
+      const float inv = 1.0f / (1.0f - alpha);
+      const float dalpha = G0 * (C.x * T - S0 * inv) + G1 * (C.y * T - S1 * inv) + G2 * (C.z * T - S2 * inv) +
+                           GD * (z * T - SD * inv) + GAT * inv;
+      const bool live = take && raw < a.alpha_max;  // the clamp passes no gradient
+      const float gs = live ? dalpha * raw : 0.0f;    // d alpha / d s (natural log domain)
       float g[10];
+      // d s / d mean = (A dx + B dy, B dx + C dy), A = -2 ca ln2, B = -cb ln2, C = -2 cc ln2
+      const float gl = -gs * kLn2;
+      g[0] = gl * (2.0f * A.z * dx + A.w * dy);
+      g[1] = gl * (A.w * dx + 2.0f * B.x * dy);
+      g[2] = -0.5f * gs * dx * dx;
+      g[3] = -gs * dx * dy;
+      g[4] = -0.5f * gs * dy * dy;
+      g[5] = live ? dalpha * ex : 0.0f;  // d alpha / d o
+      g[6] = G0 * wgt;
+      g[7] = G1 * wgt;
+      g[8] = G2 * wgt;
+      g[9] = GD * wgt;
+      T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
 #pragma unroll
-      for (int q = 0; q < 10; ++q) g[q] = 0.f;
-      bool has = false;
-      if (idx0 + k < ncon) {
-        const float4 A = sA[k];
-        const float4 B = sB[k];
-        const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-        const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
-        const float raw = __fmul_rn(B.y, ex);
-        const float alpha = fminf(a.alpha_max, raw);
-        if (alpha >= a.alpha_min) {
-          has = true;
-          const float4 C = sC[k];
-          const float z = B.z;
-          const float w = __fmul_rn(alpha, T);
-          P0 = __fmaf_rn(C.x, w, P0);
-          P1 = __fmaf_rn(C.y, w, P1);
-          P2 = __fmaf_rn(C.z, w, P2);
-          PD = __fmaf_rn(z, w, PD);
-          // suffix sums: everything composited after this entry plus T_final bg
-          const float S0 = I0 - P0, S1 = I1 - P1, S2 = I2 - P2, SD = ID - PD;
-          const float inv = 1.0f / (1.0f - alpha);
-          const float dalpha = G0 * (C.x * T - S0 * inv) + G1 * (C.y * T - S1 * inv) + G2 * (C.z * T - S2 * inv) +
-                               GD * (z * T - SD * inv) + GAT * inv;
-          g[6] = G0 * w;
-          g[7] = G1 * w;
-          g[8] = G2 * w;
-          g[9] = GD * w;
-          if (raw < a.alpha_max) {
-            g[5] = dalpha * ex;           // d alpha / d o
-            const float gs = dalpha * raw;  // d alpha / d s (natural log domain)
-            g[2] = -0.5f * gs * dx * dx;
-            g[3] = -gs * dx * dy;
-            g[4] = -0.5f * gs * dy * dy;
-            // d s / d mean = (A dx + B dy, B dx + C dy), A = -2 ca ln2, B = -cb ln2, C = -2 cc ln2
-            const float gl = -gs * kLn2;
-            g[0] = gl * (2.0f * A.z * dx + A.w * dy);
-            g[1] = gl * (A.w * dx + 2.0f * B.x * dy);
-          }
-          T = __fmul_rn(T, __fsub_rn(1.0f, alpha));
-        }
-      }
-      if (ballot(has)) {
+      for (int q = 0; q < 10; ++q) g[q] = wave_sum_to_lane63(g[q]);
+      if (lane == 63) {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) {
-          const float r = wave_sum_to_lane63(g[q]);
-          if (lane == 63 && r != 0.f) atomicAdd(&sAcc[q][k], r);
-        }
+        for (int q = 0; q < 10; ++q)
+          if (g[q] != 0.f) atomicAdd(&sAcc[q][k], g[q]);
       }
     }
     __syncthreads();
-    if (t < cnt) {
+    if (base + t < stop) {
       float *dst = bi.g2d + (size_t)sGid[t] * 12;
 #pragma unroll
       for (int q = 0; q < 10; ++q) {

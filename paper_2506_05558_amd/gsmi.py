@@ -27,7 +27,7 @@ _lib = C.CDLL(LIB_PATH)
 
 GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_WORKSPACE = range(5)
 TILE = 16
-REC_FLOATS = 12
+REC_FLOATS = 16
 
 
 class GsError(RuntimeError):
@@ -188,8 +188,8 @@ class Gaussians:
 
 @dataclass
 class Projected:
-    rec: torch.Tensor  # (N, 12)
-    radius: torch.Tensor  # (N,) int32
+    rec: torch.Tensor  # (N, 16) render records
+    radius: torch.Tensor  # (2, N) int32 half-widths (rx, ry) of the support rect
     tiles_touched: torch.Tensor  # (N,) int32
 
     def c(self):
@@ -202,12 +202,17 @@ def default_params() -> Params:
     return Params(p.eps2d, p.alpha_max, p.alpha_min, p.t_min, p.guard)
 
 
+def alloc_projected(n: int, device="cuda") -> Projected:
+    return Projected(torch.empty((n, REC_FLOATS), dtype=torch.float32, device=device),
+                     torch.empty((2, n), dtype=torch.int32, device=device),
+                     torch.empty(n, dtype=torch.int32, device=device))
+
+
 def project(cam: Camera, g: Gaussians, params: Params = Params(), out: Optional[Projected] = None) -> Projected:
     n = g.n
     dev = g.means.device
     if out is None:
-        out = Projected(torch.empty((n, REC_FLOATS), dtype=torch.float32, device=dev),
-                        torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+        out = alloc_projected(n, dev)
     _check(_lib.gs_project(C.byref(cam.c()), C.byref(params.c()), C.byref(g.c()), C.byref(out.c()), _stream()))
     return out
 
@@ -240,7 +245,7 @@ class BinSorter:
         self._key = (n, T, self.capacity)
 
     def __call__(self, cam: Camera, proj: Projected) -> Binned:
-        n = int(proj.radius.shape[0])
+        n = int(proj.tiles_touched.shape[0])
         T = cam.tiles_x * cam.tiles_y
         dev = proj.rec.device
         for _ in range(2):
@@ -270,7 +275,7 @@ class Frame:
     alpha: torch.Tensor  # (H, W)
     final_t: torch.Tensor  # (H, W)
     n_contrib: torch.Tensor  # (H, W) int32
-    stats: Optional[torch.Tensor] = None  # (2, H, W) int32: entries tested, entries composited
+    stats: Optional[torch.Tensor] = None  # (4, H, W) int32: tile entries to the stop, evaluated, support, composited
 
 
 def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Params(),
@@ -283,7 +288,7 @@ def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Pa
                     torch.empty((H, W), dtype=torch.float32, device=dev),
                     torch.empty((H, W), dtype=torch.float32, device=dev),
                     torch.empty((H, W), dtype=torch.int32, device=dev),
-                    torch.empty((2, H, W), dtype=torch.int32, device=dev) if count_pairs else None)
+                    torch.empty((4, H, W), dtype=torch.int32, device=dev) if count_pairs else None)
     _check(_lib.gs_render_fwd(C.byref(cam.c()), C.byref(params.c()), C.byref(proj.c()), binned.values.data_ptr(),
                               binned.ranges.data_ptr(), out.image.data_ptr(), out.depth.data_ptr(),
                               out.alpha.data_ptr(), out.final_t.data_ptr(), out.n_contrib.data_ptr(),

@@ -39,7 +39,7 @@ def _check_projection(view, scene, proj):
     op = orc.project(ocam, og)
     rec, _, _, radius, _ = _proj_parts(proj)
     vis_o = op["visible"] > 0
-    vis_g = radius > 0
+    vis_g = radius[0] > 0
     # images are tiny relative to 2^23 px, so visibility must agree exactly
     assert np.array_equal(vis_o, vis_g), f"visibility differs at {np.nonzero(vis_o != vis_g)[0][:10]}"
     v = vis_o
@@ -51,17 +51,20 @@ def _check_projection(view, scene, proj):
     assert (np.abs(conic[v] - ref[v]) <= 1e-6 * np.abs(ref[v]).max(axis=1, keepdims=True) + 1e-30).all()
     assert np.abs(rec[v, 7] - op["opacity"][v]).max() <= 1e-6
     assert np.abs(rec[v, 8:11] - op["rgb"].T[v]).max() <= 1e-6
-    # radius = ceil(r (1 + 1e-4) + 1e-3) exactly unless the argument is within 1e-9 of an integer
-    arg = op["radius"][v] * (1 + 1e-4) + 1e-3
-    near_int = np.abs(arg - np.round(arg)) < 1e-9 * np.maximum(arg, 1)
-    assert np.array_equal(radius[v][~near_int], np.ceil(arg[~near_int]).astype(np.int32))
+    # support box half-extents, and rx = ceil(hx (1 + 1e-4) + 1e-3) exactly unless
+    # the argument is within 1e-9 of an integer
+    assert np.abs(rec[v, 12:14] - op["half"].T[v]).max() <= 1e-6 * (1 + np.abs(op["half"]).max())
+    for axis in range(2):
+        arg = op["half"][axis][v] * (1 + 1e-4) + 1e-3
+        near_int = np.abs(arg - np.round(arg)) < 1e-9 * np.maximum(arg, 1)
+        assert np.array_equal(radius[axis][v][~near_int], np.ceil(arg[~near_int]).astype(np.int32))
     return ocam, og, op
 
 
 def _check_binning(view, proj, binned):
     _, mx, my, radius, tiles = _proj_parts(proj)
     depth = proj.rec[:, 11].cpu().numpy()
-    ref = binning.bin_and_sort(mx, my, radius, depth, view.width, view.height, 16)
+    ref = binning.bin_and_sort(mx, my, radius[0], radius[1], depth, view.width, view.height, 16)
     assert np.array_equal(tiles, ref["tiles_touched"]), "tiles_touched differs"
     M = binned.n_instances
     assert M == len(ref["values"]), (M, len(ref["values"]))
@@ -116,11 +119,12 @@ def _full_case(name, view, scene, seed, bg=(0.0, 0.0, 0.0)):
     _check_binning(view, proj, binned)
     ref = orc.render(ocam, op, flag_rel=FLAG_REL)
     _check_image(name, frame, ref)
-    # pair counters: composited entries match the definition's count exactly
+    # pair counters: support and composited entries match the definition's counts
     ok = ref["flags"] == 0
     stats = frame.stats.cpu().numpy()
-    assert np.array_equal(stats[1][ok], ref["n_contrib"][ok])
-    assert (stats[0] >= stats[1]).all() and (stats[0][ok] >= ref["n_support"][ok]).all()
+    assert np.array_equal(stats[2][ok], ref["n_support"][ok])
+    assert np.array_equal(stats[3][ok], ref["n_contrib"][ok])
+    assert (stats[0] >= stats[1]).all() and (stats[1] >= stats[2]).all() and (stats[2] >= stats[3]).all()
     gi, gd, ga = gc.flagged_upstream((view.height, view.width), ref["flags"], seed)
     d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
     d_twist = torch.zeros(6, dtype=torch.float64, device="cuda")

@@ -366,3 +366,21 @@ def test_depth_tie_flag(oracle_lib):
                           np.full(2, 0.0), np.zeros((1, 3, 2)), 0)
         _, out = orc.forward(orc.Camera.from_view(view), g)
         assert bool(out["flags"][4, 4] & 8) == expect, zs
+
+
+def test_support_box_is_the_ellipse_bounding_box(oracle_lib):
+    """hx, hy bound every pixel offset with alpha >= alpha_min and are attained
+    on the boundary ellipse d^T Sigma2^-1 d = 2 ln(o / alpha_min)."""
+    orc = oracle_lib
+    view, sc, _ = synth.tiny_scene(4)
+    cam = _cam(orc, view)
+    proj = orc.project(cam, _g(orc, sc))
+    th = np.linspace(0, 2 * np.pi, 20001)
+    for i in np.nonzero(proj["visible"])[0][:50]:
+        a, b, c = proj["cov2d"][:, i]
+        qmax = 2 * np.log(proj["opacity"][i] * 255.0)
+        L = np.linalg.cholesky(np.array([[a, b], [b, c]]))
+        d = L @ np.stack([np.cos(th), np.sin(th)]) * np.sqrt(qmax)
+        assert abs(np.abs(d[0]).max() - proj["half"][0, i]) < 1e-6 * proj["half"][0, i]
+        assert abs(np.abs(d[1]).max() - proj["half"][1, i]) < 1e-6 * proj["half"][1, i]
+        assert proj["half"][:, i].max() <= proj["radius"][i] * (1 + 1e-12)
