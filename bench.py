@@ -116,7 +116,7 @@ def main():
     f = lambda *s, dt=torch.float32: torch.empty(s, dtype=dt, device=dev)
     frame = gsmi.Frame(f(3, H, W), f(H, W), f(H, W), f(H, W), f(H, W, dt=torch.int32))
     g_img = f(3, H, W)
-    bwd_ws = torch.empty(gsmi.render_bwd_workspace(n), dtype=torch.uint8, device=dev)
+    bwd_ws = torch.empty(gsmi.render_bwd_workspace(n, sorter.capacity), dtype=torch.uint8, device=dev)
     loss_ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
     cams = [gsmi.Camera(W, H, v.fx, v.fy, v.cx, v.cy, poses[i]) for i, v in enumerate(views)]
     lr = dict(means=1.6e-4 * 10, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4,

@@ -140,17 +140,22 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
  * over pairs emitted in Gaussian-index order.  Implemented as a stable LSD
  * radix sort of the visible Gaussians by depth followed by a stable LSD
  * radix sort of the emitted pairs by tile.
- *   tile_ids [capacity]  out: tile id of each sorted pair
- *   values   [capacity]  out: Gaussian index of each sorted pair
- *   ranges   [T][2]      out: [start, end) of each tile's run (0,0 if empty)
- *   n_instances (HOST)   out: the number M of pairs
- * Synchronises the stream once (8-byte read of M).  If M > capacity it
+ *   tile_ids   [capacity] out: tile id of each sorted pair
+ *   values     [capacity] out: Gaussian index of each sorted pair
+ *   slots      [capacity] out: emission index of each sorted pair; the pairs
+ *                         of Gaussian g have slots first_slot[g] ..
+ *                         first_slot[g] + tiles_touched[g] - 1
+ *   ranges     [T][2]     out: [start, end) of each tile's run (0,0 if empty)
+ *   first_slot [n]        out: first slot of each Gaussian (written where
+ *                         tiles_touched > 0)
+ *   n_instances (HOST)    out: the number M of pairs
+ * Synchronises the stream once (4-byte read of M).  If M > capacity it
  * returns GS_ERR_CAPACITY with *n_instances = M and writes no list output.
  * ws must be at least gs_bin_sort_workspace(n, capacity) bytes. */
 gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t *bytes);
 gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
-                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *ranges, int64_t *n_instances,
-                      void *stream);
+                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots, uint32_t *ranges,
+                      uint32_t *first_slot, int64_t *n_instances, void *stream);
 
 /* ---- gs_render_fwd ------------------------------------------------------
  * Front-to-back compositing per pixel over its tile's list: with
@@ -177,8 +182,9 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
  * Adjoint of gs_project + gs_render_fwd for upstream gradients of image
  * [3][H][W], depth [H][W] and alpha [H][W] (dL_ddepth / dL_dalpha may be
  * NULL = zero).  image, depth, final_t and n_contrib must be the forward's
- * outputs for the same inputs.  Accumulates into grads (same layout as g;
- * grads->n and sh_degree must match g) and, if not NULL, into
+ * outputs and values / slots / ranges / first_slot / n_instances
+ * gs_bin_sort's for the same inputs.  Accumulates into grads (same layout
+ * as g; grads->n and sh_degree must match g) and, if not NULL, into
  *   dL_dpose  [12] (double) gradient w.r.t. R (row-major) and t,
  *   dL_dtwist [6]  (double) gradient w.r.t. a left twist (rho, phi):
  *                  T <- exp(xi^) T, rho the translation part.
@@ -186,10 +192,13 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
  * only, not through the SH view direction (section 4.3).  The Gaussian
  * gradients include the view-direction path.  Decisions (skip, stop, alpha
  * clamp, colour clamp, guard band) are held fixed: the clamp's derivative
- * is zero.  ws: gs_render_bwd_workspace(n) bytes. */
-gs_status gs_render_bwd_workspace(int64_t n, size_t *bytes);
+ * is zero.  Per-tile contributions go to a per-pair buffer in the workspace
+ * (no global atomics) and are summed per Gaussian in slot order.
+ * ws: gs_render_bwd_workspace(n, n_instances) bytes. */
+gs_status gs_render_bwd_workspace(int64_t n, int64_t n_instances, size_t *bytes);
 gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
-                        const gs_projected *proj, const uint32_t *values, const uint32_t *ranges, const float *image,
+                        const gs_projected *proj, const uint32_t *values, const uint32_t *slots,
+                        const uint32_t *ranges, const uint32_t *first_slot, int64_t n_instances, const float *image,
                         const float *depth, const float *final_t, const int32_t *n_contrib, const float *dL_dimage,
                         const float *dL_ddepth, const float *dL_dalpha, gs_gaussians *grads, double *dL_dpose,
                         double *dL_dtwist, void *ws, size_t ws_bytes, void *stream);

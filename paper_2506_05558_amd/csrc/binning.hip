@@ -145,11 +145,12 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(const uint32_t *keys
   for (int d = lane; d < ndig; d += 64) hist[(int64_t)d * nchunks + chunk] = cnt[w][d];
 }
 
+template <bool TWO>
 __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
-                                                               uint32_t *kout, uint32_t *vout,
-                                                               const uint32_t *count_dev, uint32_t count_max,
-                                                               int shift, int bits, int64_t nchunks,
-                                                               const uint32_t *offsets) {
+                                                               const uint32_t *win, uint32_t *kout, uint32_t *vout,
+                                                               uint32_t *wout, const uint32_t *count_dev,
+                                                               uint32_t count_max, int shift, int bits,
+                                                               int64_t nchunks, const uint32_t *offsets) {
   __shared__ uint32_t run[kWaves][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t chunk = (int64_t)blockIdx.x * kWaves + w;
@@ -164,10 +165,11 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *k
     const int64_t i = c0 + it * 64 + lane;
     const bool valid = i < (int64_t)count;
     if (__ballot(valid) == 0) break;
-    uint32_t key = 0, val = 0;
+    uint32_t key = 0, val = 0, val2 = 0;
     if (valid) {
       key = kin[i];
       val = vin[i];
+      if (TWO) val2 = win[i];
     }
     const uint32_t d = (key >> shift) & mask;
     const uint64_t peers = peers_of(d, bits, valid);
@@ -176,6 +178,7 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *k
       const uint32_t pos = base + (uint32_t)__popcll(peers & lt);
       kout[pos] = key;
       vout[pos] = val;
+      if (TWO) wout[pos] = val2;
       const uint64_t higher = peers & ~(lt | (1ull << lane));
       if (higher == 0) run[w][d] = base + (uint32_t)__popcll(peers);
     }
@@ -204,12 +207,16 @@ __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev
   cnt[j] = j < (int64_t)*count_dev ? (uint32_t)tiles[order[j]] : 0u;
 }
 
+// Emits the pairs of the j-th Gaussian in depth order at its offset: tile
+// id, Gaussian index and the pair's emission index ("slot"); the pairs of a
+// Gaussian occupy slots [first_slot[g], first_slot[g] + tiles_touched[g]).
 __global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const float *rec,
                             const int32_t *radius, int64_t n, int W, int H, int tiles_x, uint32_t capacity,
-                            uint32_t *tile_keys, uint32_t *vals) {
+                            uint32_t *tile_keys, uint32_t *vals, uint32_t *slots, uint32_t *first_slot) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= (int64_t)*count_dev) return;
   const uint32_t g = order[j];
+  first_slot[g] = offs[j];
   const float4 r0 = *(const float4 *)(rec + (size_t)g * GS_REC_FLOATS);
   int tx0, ty0, tx1, ty1;
   if (!tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[g], radius[n + g], W, H, tx0, ty0, tx1,
@@ -221,6 +228,7 @@ __global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, co
       if (o >= capacity) return;
       tile_keys[o] = (uint32_t)(ty * tiles_x + tx);
       vals[o] = g;
+      slots[o] = o;
       ++o;
     }
 }
@@ -264,8 +272,9 @@ size_t radix_hist_elems(int64_t count_max) { return 256 * (size_t)nchunks_of(cou
 
 // Sorts (k[0], v[0]) by the given passes, ping-ponging with (k[1], v[1]).
 // Returns the index (0 or 1) of the buffer pair holding the result.
-gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], const uint32_t *count_dev, int64_t count_max, int npasses,
-                     const int *shifts, const int *widths, const RadixWs &rw, hipStream_t s, int *result) {
+gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], uint32_t *v2[2], const uint32_t *count_dev, int64_t count_max,
+                     int npasses, const int *shifts, const int *widths, const RadixWs &rw, hipStream_t s,
+                     int *result) {
   int cur = 0;
   const int64_t nch = nchunks_of(count_max);
   const int64_t blocks = (nch + kWaves - 1) / kWaves;
@@ -275,8 +284,14 @@ gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], const uint32_t *count_dev, 
               shifts[p], widths[p], nch, rw.hist);
     gs_status st = scan_exclusive(rw.hist, rw.hist, (int64_t)(1 << widths[p]) * nch, nullptr, rw.scan_ws, s);
     if (st != GS_OK) return st;
-    GS_LAUNCH("radix_scatter", k_radix_scatter, blocks, kRadixBlock, 0, s, k[cur], v[cur], k[1 - cur], v[1 - cur],
-              count_dev, (uint32_t)count_max, shifts[p], widths[p], nch, rw.hist);
+    if (v2)
+      GS_LAUNCH("radix_scatter", k_radix_scatter<true>, blocks, kRadixBlock, 0, s, k[cur], v[cur], v2[cur],
+                k[1 - cur], v[1 - cur], v2[1 - cur], count_dev, (uint32_t)count_max, shifts[p], widths[p], nch,
+                rw.hist);
+    else
+      GS_LAUNCH("radix_scatter", k_radix_scatter<false>, blocks, kRadixBlock, 0, s, k[cur], v[cur], nullptr,
+                k[1 - cur], v[1 - cur], nullptr, count_dev, (uint32_t)count_max, shifts[p], widths[p], nch,
+                rw.hist);
     cur = 1 - cur;
   }
   *result = cur;
@@ -312,7 +327,7 @@ using namespace gsmi;
 namespace {
 
 struct BinLayout {
-  uint32_t *flags, *pos, *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *scalars, *ktmp, *vtmp;
+  uint32_t *flags, *pos, *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *scalars, *ktmp, *vtmp, *stmp;
   void *scan_ws;
   size_t bytes;
 };
@@ -336,6 +351,7 @@ BinLayout bin_layout(void *ws, int64_t n, int64_t capacity) {
   L.scalars = cv.take<uint32_t>(4);
   L.ktmp = cv.take<uint32_t>(cc);
   L.vtmp = cv.take<uint32_t>(cc);
+  L.stmp = cv.take<uint32_t>(cc);
   L.bytes = cv.off;
   return L;
 }
@@ -356,15 +372,16 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t *bytes) {
 }
 
 gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
-                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *ranges, int64_t *n_instances,
-                      void *stream) {
+                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots, uint32_t *ranges,
+                      uint32_t *first_slot, int64_t *n_instances, void *stream) {
   gs_status st = validate_camera(cam, "gs_bin_sort");
   if (st != GS_OK) return st;
   GS_REQUIRE(proj && ranges && n_instances, "gs_bin_sort: NULL argument");
   GS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "gs_bin_sort: n out of range");
   GS_REQUIRE(capacity >= 0 && capacity < (int64_t(1) << 32) - 1, "gs_bin_sort: capacity out of range");
   if (n > 0) GS_REQUIRE(proj->rec && proj->radius && proj->tiles_touched, "gs_bin_sort: NULL projection plane");
-  if (capacity > 0) GS_REQUIRE(tile_ids && values, "gs_bin_sort: NULL list output");
+  if (capacity > 0) GS_REQUIRE(tile_ids && values && slots, "gs_bin_sort: NULL list output");
+  if (n > 0) GS_REQUIRE(first_slot, "gs_bin_sort: NULL first_slot");
   size_t need = 0;
   gs_bin_sort_workspace(n, capacity, &need);
   if (ws_bytes < need || !ws) {
@@ -389,7 +406,7 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
     int shifts[8], widths[8];
     const int np = plan_passes(31, shifts, widths);
     uint32_t *kk[2] = {L.kA, L.kB}, *vv[2] = {L.vA, L.vB};
-    if ((st = radix_sort(kk, vv, V, n, np, shifts, widths, rw, s, &order_buf)) != GS_OK) return st;
+    if ((st = radix_sort(kk, vv, nullptr, V, n, np, shifts, widths, rw, s, &order_buf)) != GS_OK) return st;
     const uint32_t *order = vv[order_buf];
     // 3. pair offsets in depth order
     GS_LAUNCH("bin_counts", k_gather_counts, grid1(n), 256, 0, s, order, V, proj->tiles_touched, n, L.cnt);
@@ -411,17 +428,17 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
   int shifts[8], widths[8];
   const int np = plan_passes(tb, shifts, widths);
   // start in the buffer pair that makes the final pass land in the caller's arrays
-  uint32_t *kk[2], *vv[2];
+  uint32_t *kk[2], *vv[2], *ss[2];
   if (np % 2 == 0) {
-    kk[0] = tile_ids; vv[0] = values; kk[1] = L.ktmp; vv[1] = L.vtmp;
+    kk[0] = tile_ids; vv[0] = values; ss[0] = slots; kk[1] = L.ktmp; vv[1] = L.vtmp; ss[1] = L.stmp;
   } else {
-    kk[0] = L.ktmp; vv[0] = L.vtmp; kk[1] = tile_ids; vv[1] = values;
+    kk[0] = L.ktmp; vv[0] = L.vtmp; ss[0] = L.stmp; kk[1] = tile_ids; vv[1] = values; ss[1] = slots;
   }
   const uint32_t *order = order_buf ? L.vB : L.vA;
   GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, proj->rec, proj->radius, n, W, H, tx,
-            (uint32_t)capacity, kk[0], vv[0]);
+            (uint32_t)capacity, kk[0], vv[0], ss[0], first_slot);
   int res = 0;
-  if ((st = radix_sort(kk, vv, nullptr, M, np, shifts, widths, rw, s, &res)) != GS_OK) return st;
+  if ((st = radix_sort(kk, vv, ss, nullptr, M, np, shifts, widths, rw, s, &res)) != GS_OK) return st;
   GS_LAUNCH("bin_ranges", k_ranges, grid1(M), 256, 0, s, tile_ids, M, ranges);
   return GS_OK;
 }

@@ -6,8 +6,10 @@
 // 48-byte read.  Geometry runs in FP64: on gfx950 the FP64 vector rate
 // equals the unpacked FP32 rate, so the extra precision costs nothing in a
 // kernel bounded by HBM traffic (236 B in + 72 B out per SH-degree-3
-// Gaussian).  The SH colour terms of the adjoint stream one coefficient at
-// a time in FP32 to keep the register footprint, and with it occupancy, up.
+// Gaussian).  The adjoint runs in FP32 (hardware exp, rcp, rsqrt) with the
+// SH terms streamed one coefficient at a time, which keeps its register
+// footprint and with it occupancy up; the camera-pose sum over all Gaussians
+// is reduced in FP64.
 #include "common.h"
 
 namespace gsmi {
@@ -84,60 +86,73 @@ struct ProjArgs {
   int32_t *radius, *tiles;  // radius: [2][n] (rx, ry)
 };
 
-// Geometry of one Gaussian's forward, in FP64.
+// Geometry of one Gaussian's forward: FP64 for the forward projection (the
+// render record needs a sub-1e-6-pixel mean), FP32 for the adjoint, whose
+// 2D covariance is kept well conditioned by the eps2d dilation.
+template <class Real>
 struct Geo {
-  double R[9];
-  double p[3], iz;
+  Real R[9];
+  Real p[3], iz;
   bool clx, cly;
-  double J00, J02, J11, J12;
-  double qn[4], qinv;
-  double Rq[9], s[3], M[9];
-  double T[6], TM[6];
-  double a, b, c, A, B, C;
+  Real J00, J02, J11, J12;
+  Real qn[4], qinv;
+  Real Rq[9], s[3], M[9];
+  Real T[6], TM[6];
+  Real a, b, c, A, B, C;
 };
 
-__device__ __forceinline__ void load_pose(const float *pose, double R[9], double t[3]) {
+template <class Real>
+__device__ __forceinline__ void load_pose(const float *pose, Real R[9], Real t[3]) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = (double)pose[k];
+  for (int k = 0; k < 9; ++k) R[k] = (Real)pose[k];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) t[k] = (double)pose[9 + k];
+  for (int k = 0; k < 3; ++k) t[k] = (Real)pose[9 + k];
 }
+
+__device__ __forceinline__ double real_exp(double x) { return exp(x); }
+__device__ __forceinline__ float real_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double real_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float real_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double real_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float real_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Camera-space point and the 2D covariance.  Returns false if culled by
 // the near plane or a non-positive determinant.
-__device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const double mu[3], const double t[3],
-                                         Geo &f) {
+template <class Real>
+__device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const Real mu[3], const Real t[3],
+                                         Geo<Real> &f) {
   const int64_t n = a.n;
 #pragma unroll
   for (int r = 0; r < 3; ++r) f.p[r] = f.R[3 * r] * mu[0] + f.R[3 * r + 1] * mu[1] + f.R[3 * r + 2] * mu[2] + t[r];
-  if (!(f.p[2] > a.near_plane)) return false;
-  f.iz = 1.0 / f.p[2];
-  const double limx = a.guard * 0.5 * a.W / a.fx, limy = a.guard * 0.5 * a.H / a.fy;
-  const double tx = f.p[0] * f.iz, ty = f.p[1] * f.iz;
+  if (!(f.p[2] > (Real)a.near_plane)) return false;
+  f.iz = real_rcp(f.p[2]);
+  const Real limx = (Real)(a.guard * 0.5 * a.W / a.fx), limy = (Real)(a.guard * 0.5 * a.H / a.fy);
+  const Real tx = f.p[0] * f.iz, ty = f.p[1] * f.iz;
   f.clx = tx < -limx || tx > limx;
   f.cly = ty < -limy || ty > limy;
-  const double xc = f.clx ? (tx < 0.0 ? -limx : limx) * f.p[2] : f.p[0];
-  const double yc = f.cly ? (ty < 0.0 ? -limy : limy) * f.p[2] : f.p[1];
-  f.J00 = a.fx * f.iz;
-  f.J11 = a.fy * f.iz;
-  f.J02 = -a.fx * xc * f.iz * f.iz;
-  f.J12 = -a.fy * yc * f.iz * f.iz;
+  const Real xc = f.clx ? (tx < 0 ? -limx : limx) * f.p[2] : f.p[0];
+  const Real yc = f.cly ? (ty < 0 ? -limy : limy) * f.p[2] : f.p[1];
+  const Real fx = (Real)a.fx, fy = (Real)a.fy;
+  f.J00 = fx * f.iz;
+  f.J11 = fy * f.iz;
+  f.J02 = -fx * xc * f.iz * f.iz;
+  f.J12 = -fy * yc * f.iz * f.iz;
 
-  const double q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
-  f.qinv = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  const double w = q0 * f.qinv, x = q1 * f.qinv, y = q2 * f.qinv, z = q3 * f.qinv;
+  const Real q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
+  f.qinv = real_rsqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  const Real w = q0 * f.qinv, x = q1 * f.qinv, y = q2 * f.qinv, z = q3 * f.qinv;
   f.qn[0] = w; f.qn[1] = x; f.qn[2] = y; f.qn[3] = z;
-  f.Rq[0] = 1.0 - 2.0 * (y * y + z * z);
-  f.Rq[1] = 2.0 * (x * y - w * z);
-  f.Rq[2] = 2.0 * (x * z + w * y);
-  f.Rq[3] = 2.0 * (x * y + w * z);
-  f.Rq[4] = 1.0 - 2.0 * (x * x + z * z);
-  f.Rq[5] = 2.0 * (y * z - w * x);
-  f.Rq[6] = 2.0 * (x * z - w * y);
-  f.Rq[7] = 2.0 * (y * z + w * x);
-  f.Rq[8] = 1.0 - 2.0 * (x * x + y * y);
+  f.Rq[0] = 1 - 2 * (y * y + z * z);
+  f.Rq[1] = 2 * (x * y - w * z);
+  f.Rq[2] = 2 * (x * z + w * y);
+  f.Rq[3] = 2 * (x * y + w * z);
+  f.Rq[4] = 1 - 2 * (x * x + z * z);
+  f.Rq[5] = 2 * (y * z - w * x);
+  f.Rq[6] = 2 * (x * z - w * y);
+  f.Rq[7] = 2 * (y * z + w * x);
+  f.Rq[8] = 1 - 2 * (x * x + y * y);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) f.s[k] = exp((double)a.log_scales[k * n + i]);
+  for (int k = 0; k < 3; ++k) f.s[k] = real_exp((Real)a.log_scales[k * n + i]);
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -153,12 +168,12 @@ __device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const dou
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       f.TM[3 * r + c] = f.T[3 * r] * f.M[c] + f.T[3 * r + 1] * f.M[3 + c] + f.T[3 * r + 2] * f.M[6 + c];
-  f.a = f.TM[0] * f.TM[0] + f.TM[1] * f.TM[1] + f.TM[2] * f.TM[2] + a.eps2d;
+  f.a = f.TM[0] * f.TM[0] + f.TM[1] * f.TM[1] + f.TM[2] * f.TM[2] + (Real)a.eps2d;
   f.b = f.TM[0] * f.TM[3] + f.TM[1] * f.TM[4] + f.TM[2] * f.TM[5];
-  f.c = f.TM[3] * f.TM[3] + f.TM[4] * f.TM[4] + f.TM[5] * f.TM[5] + a.eps2d;
-  const double det = f.a * f.c - f.b * f.b;
-  if (!(det > 0.0)) return false;
-  const double idet = 1.0 / det;
+  f.c = f.TM[3] * f.TM[3] + f.TM[4] * f.TM[4] + f.TM[5] * f.TM[5] + (Real)a.eps2d;
+  const Real det = f.a * f.c - f.b * f.b;
+  if (!(det > 0)) return false;
+  const Real idet = real_rcp(det);
   f.A = f.c * idet;
   f.B = -f.b * idet;
   f.C = f.a * idet;
@@ -166,13 +181,13 @@ __device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const dou
 }
 
 // Unit view direction from the camera centre C = -R^T t and 1/|mu - C|.
-__device__ __forceinline__ void view_dir(const double R[9], const double t[3], const double mu[3], double d[3],
-                                         double &dinv) {
-  const double Cx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
-  const double Cy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
-  const double Cz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
-  const double dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
-  dinv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+template <class Real>
+__device__ __forceinline__ void view_dir(const Real R[9], const Real t[3], const Real mu[3], Real d[3], Real &dinv) {
+  const Real Cx = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
+  const Real Cy = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
+  const Real Cz = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
+  const Real dx = mu[0] - Cx, dy = mu[1] - Cy, dz = mu[2] - Cz;
+  dinv = real_rsqrt(dx * dx + dy * dy + dz * dz);
   d[0] = dx * dinv;
   d[1] = dy * dinv;
   d[2] = dz * dinv;
@@ -183,13 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= a.n) return;
   const int64_t n = a.n;
-  Geo f;
+  Geo<double> f;
   double t[3];
-  load_pose(a.pose, f.R, t);
+  load_pose<double>(a.pose, f.R, t);
   const double mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
   float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, r3 = r0;
   int rx = 0, ry = 0, tiles = 0;
-  bool ok = geometry(a, i, mu, t, f);
+  bool ok = geometry<double>(a, i, mu, t, f);
   double mx = 0, my = 0, o = 0;
   if (ok) {
     mx = a.fx * f.p[0] * f.iz + a.cx;
@@ -208,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs a) {
     rx = (int)ceil(fmin(hx * (1.0 + 1e-4) + 1e-3, 4194304.0));
     ry = (int)ceil(fmin(hy * (1.0 + 1e-4) + 1e-3, 4194304.0));
     double d[3], dinv;
-    view_dir(f.R, t, mu, d, dinv);
+    view_dir<double>(f.R, t, mu, d, dinv);
     double val[3] = {0.5, 0.5, 0.5};
     constexpr int NB = (DEG + 1) * (DEG + 1);
 #pragma unroll
@@ -240,26 +255,39 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs a) {
 // ---------------------------------------------------------------- backward
 struct BwdArgs {
   ProjArgs p;
-  const float *g2d;  // [n][12] per-Gaussian 2D gradients (first 10 used)
+  const float *pair_grad;     // [M][12] 2D gradients per (Gaussian, tile) pair (first 10 used)
+  const uint32_t *first_slot; // first pair slot of each visible Gaussian
   float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
   double *partials;  // [gridDim.x][12] pose partial sums
 };
 
+// Adjoint of one visible Gaussian, in FP32 (the forward decided
+// visibility; the adjoint only chains gradients).  Writes the pose terms of
+// this Gaussian into pose[12]: dL/dR (row-major) and dL/dt.
 template <int DEG>
-__device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, double pose_acc[12]) {
+__device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int ntiles, float pose[12]) {
   const ProjArgs &a = ba.p;
   const int64_t n = a.n;
-  Geo f;
-  double t[3];
-  load_pose(a.pose, f.R, t);
-  const double mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
-  if (!geometry(a, i, mu, t, f)) return;
-  const float4 *gp4 = (const float4 *)(ba.g2d + i * 12);
-  const float4 g0 = gp4[0], g1 = gp4[1], g2 = gp4[2];
+  Geo<float> f;
+  float t[3];
+  load_pose<float>(a.pose, f.R, t);
+  const float mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
+  geometry<float>(a, i, mu, t, f);
+  // the Gaussian's pairs are contiguous: sum their 2D gradients in slot order
+  float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0, g2 = g0;
+  {
+    const float4 *gp4 = (const float4 *)(ba.pair_grad + (size_t)ba.first_slot[i] * 12);
+    for (int j = 0; j < ntiles; ++j) {
+      const float4 a0 = gp4[3 * j], a1 = gp4[3 * j + 1], a2 = gp4[3 * j + 2];
+      g0.x += a0.x; g0.y += a0.y; g0.z += a0.z; g0.w += a0.w;
+      g1.x += a1.x; g1.y += a1.y; g1.z += a1.z; g1.w += a1.w;
+      g2.x += a2.x; g2.y += a2.y;
+    }
+  }
   // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -)
   const float4 rgbz = *(const float4 *)(a.rec + i * GS_REC_FLOATS + 8);
 
-  double gmu[3] = {0.0, 0.0, 0.0};
+  float gmu[3] = {0.f, 0.f, 0.f};
 
   // colour -> SH coefficients and view direction (no pose path, section 4.3).
   // A channel whose colour was clamped at 0 passes no gradient.
@@ -267,142 +295,145 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, doubl
     const float gc0 = rgbz.x > 0.f ? g1.z : 0.f;
     const float gc1 = rgbz.y > 0.f ? g1.w : 0.f;
     const float gc2 = rgbz.z > 0.f ? g2.x : 0.f;
-    double dd[3], dinv;
-    view_dir(f.R, t, mu, dd, dinv);
-    const float x = (float)dd[0], y = (float)dd[1], z = (float)dd[2];
+    float d[3], dinv;
+    view_dir<float>(f.R, t, mu, d, dinv);
     float gx = 0.f, gy = 0.f, gz = 0.f;
     constexpr int NB = (DEG + 1) * (DEG + 1);
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
       float Y, ax, ay, az;
-      sh_term<float>(k, x, y, z, Y, ax, ay, az);
+      sh_term<float>(k, d[0], d[1], d[2], Y, ax, ay, az);
       const int64_t o0 = (int64_t)(k * 3) * n + i;
-      const float s0 = a.sh[o0], s1 = a.sh[o0 + n], s2 = a.sh[o0 + 2 * n];
       ba.gsh[o0] += gc0 * Y;
       ba.gsh[o0 + n] += gc1 * Y;
       ba.gsh[o0 + 2 * n] += gc2 * Y;
       if (DEG > 0) {
-        const float wk = gc0 * s0 + gc1 * s1 + gc2 * s2;
+        const float wk = gc0 * a.sh[o0] + gc1 * a.sh[o0 + n] + gc2 * a.sh[o0 + 2 * n];
         gx += wk * ax;
         gy += wk * ay;
         gz += wk * az;
       }
     }
     if (DEG > 0) {
-      const double radial = gx * dd[0] + gy * dd[1] + gz * dd[2];
-      gmu[0] += (gx - radial * dd[0]) * dinv;
-      gmu[1] += (gy - radial * dd[1]) * dinv;
-      gmu[2] += (gz - radial * dd[2]) * dinv;
+      const float radial = gx * d[0] + gy * d[1] + gz * d[2];
+      gmu[0] += (gx - radial * d[0]) * dinv;
+      gmu[1] += (gy - radial * d[1]) * dinv;
+      gmu[2] += (gz - radial * d[2]) * dinv;
     }
   }
 
   {
-    const double o = 1.0 / (1.0 + exp(-(double)a.opac[i]));
-    ba.go[i] += (float)((double)g1.y * o * (1.0 - o));
+    const float o = real_rcp(1.0f + __expf(-a.opac[i]));
+    ba.go[i] += g1.y * o * (1.0f - o);
   }
 
   // conic -> Sigma2: dL/dSigma2 = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
-  const double gA = g0.z, hB = 0.5 * (double)g0.w, gC = g1.x;
-  const double QG00 = f.A * gA + f.B * hB, QG01 = f.A * hB + f.B * gC;
-  const double QG10 = f.B * gA + f.C * hB, QG11 = f.B * hB + f.C * gC;
-  const double S00 = -(QG00 * f.A + QG01 * f.B);
-  const double S01 = -(QG00 * f.B + QG01 * f.C);
-  const double S11 = -(QG10 * f.B + QG11 * f.C);
+  const float gA = g0.z, hB = 0.5f * g0.w, gC = g1.x;
+  const float QG00 = f.A * gA + f.B * hB, QG01 = f.A * hB + f.B * gC;
+  const float QG10 = f.B * gA + f.C * hB, QG11 = f.B * hB + f.C * gC;
+  const float S00 = -(QG00 * f.A + QG01 * f.B);
+  const float S01 = -(QG00 * f.B + QG01 * f.C);
+  const float S11 = -(QG10 * f.B + QG11 * f.C);
 
   // Sigma2 = TM TM^T: gTM = 2 S TM
-  double gTM[6];
+  float gTM[6];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    gTM[c] = 2.0 * (S00 * f.TM[c] + S01 * f.TM[3 + c]);
-    gTM[3 + c] = 2.0 * (S01 * f.TM[c] + S11 * f.TM[3 + c]);
+    gTM[c] = 2.0f * (S00 * f.TM[c] + S01 * f.TM[3 + c]);
+    gTM[3 + c] = 2.0f * (S01 * f.TM[c] + S11 * f.TM[3 + c]);
   }
-  // TM = T M: gT = gTM M^T, gM = T^T gTM
-  double gT[6];
+  // TM = T M: gT = gTM M^T
+  float gT[6];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       gT[3 * r + c] = gTM[3 * r] * f.M[3 * c] + gTM[3 * r + 1] * f.M[3 * c + 1] + gTM[3 * r + 2] * f.M[3 * c + 2];
 
-  // M = Rq diag(s): scales and quaternion (gM formed entry by entry)
-  double gRq[9];
+  // M = Rq diag(s), gM = T^T gTM entry by entry: scales and quaternion
+  float gRq[9];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double gs = 0.0;
+    float gs = 0.f;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const double gM = f.T[r] * gTM[c] + f.T[3 + r] * gTM[3 + c];
+      const float gM = f.T[r] * gTM[c] + f.T[3 + r] * gTM[3 + c];
       gRq[3 * r + c] = gM * f.s[c];
       gs += gM * f.Rq[3 * r + c];
     }
-    ba.gl[c * n + i] += (float)(gs * f.s[c]);
+    ba.gl[c * n + i] += gs * f.s[c];
   }
   {
-    const double w = f.qn[0], x = f.qn[1], y = f.qn[2], z = f.qn[3];
-    const double G0 = gRq[0], G1 = gRq[1], G2 = gRq[2], G3 = gRq[3], G4 = gRq[4], G5 = gRq[5], G6 = gRq[6],
-                 G7 = gRq[7], G8 = gRq[8];
-    const double dw = 2.0 * (z * (G3 - G1) + y * (G2 - G6) + x * (G7 - G5));
-    const double dx = 2.0 * (y * (G1 + G3) + z * (G2 + G6) + w * (G7 - G5)) - 4.0 * x * (G4 + G8);
-    const double dy = 2.0 * (x * (G1 + G3) + w * (G2 - G6) + z * (G5 + G7)) - 4.0 * y * (G0 + G8);
-    const double dz = 2.0 * (w * (G3 - G1) + x * (G2 + G6) + y * (G5 + G7)) - 4.0 * z * (G0 + G4);
-    const double proj = dw * w + dx * x + dy * y + dz * z;
-    ba.gq[i] += (float)((dw - proj * w) * f.qinv);
-    ba.gq[n + i] += (float)((dx - proj * x) * f.qinv);
-    ba.gq[2 * n + i] += (float)((dy - proj * y) * f.qinv);
-    ba.gq[3 * n + i] += (float)((dz - proj * z) * f.qinv);
+    const float w = f.qn[0], x = f.qn[1], y = f.qn[2], z = f.qn[3];
+    const float G0 = gRq[0], G1 = gRq[1], G2 = gRq[2], G3 = gRq[3], G4 = gRq[4], G5 = gRq[5], G6 = gRq[6],
+                G7 = gRq[7], G8 = gRq[8];
+    const float dw = 2.0f * (z * (G3 - G1) + y * (G2 - G6) + x * (G7 - G5));
+    const float dx = 2.0f * (y * (G1 + G3) + z * (G2 + G6) + w * (G7 - G5)) - 4.0f * x * (G4 + G8);
+    const float dy = 2.0f * (x * (G1 + G3) + w * (G2 - G6) + z * (G5 + G7)) - 4.0f * y * (G0 + G8);
+    const float dz = 2.0f * (w * (G3 - G1) + x * (G2 + G6) + y * (G5 + G7)) - 4.0f * z * (G0 + G4);
+    const float proj = dw * w + dx * x + dy * y + dz * z;
+    ba.gq[i] += (dw - proj * w) * f.qinv;
+    ba.gq[n + i] += (dx - proj * x) * f.qinv;
+    ba.gq[2 * n + i] += (dy - proj * y) * f.qinv;
+    ba.gq[3 * n + i] += (dz - proj * z) * f.qinv;
   }
 
   // T = J R: gJ = gT R^T (entries 00, 02, 11, 12); gR from the covariance = J^T gT
-  const double gJ00 = gT[0] * f.R[0] + gT[1] * f.R[1] + gT[2] * f.R[2];
-  const double gJ02 = gT[0] * f.R[6] + gT[1] * f.R[7] + gT[2] * f.R[8];
-  const double gJ11 = gT[3] * f.R[3] + gT[4] * f.R[4] + gT[5] * f.R[5];
-  const double gJ12 = gT[3] * f.R[6] + gT[4] * f.R[7] + gT[5] * f.R[8];
+  const float gJ00 = gT[0] * f.R[0] + gT[1] * f.R[1] + gT[2] * f.R[2];
+  const float gJ02 = gT[0] * f.R[6] + gT[1] * f.R[7] + gT[2] * f.R[8];
+  const float gJ11 = gT[3] * f.R[3] + gT[4] * f.R[4] + gT[5] * f.R[5];
+  const float gJ12 = gT[3] * f.R[6] + gT[4] * f.R[7] + gT[5] * f.R[8];
 
   // camera-space point: mean2d, depth and the Jacobian entries
-  const double gmx = g0.x, gmy = g0.y;
-  const double iz2 = f.iz * f.iz;
-  double gp0 = gmx * a.fx * f.iz;
-  double gp1 = gmy * a.fy * f.iz;
-  double gp2 = (double)g2.y - (gmx * a.fx * f.p[0] + gmy * a.fy * f.p[1]) * iz2 - (gJ00 * a.fx + gJ11 * a.fy) * iz2;
+  const float fx = (float)a.fx, fy = (float)a.fy;
+  const float gmx = g0.x, gmy = g0.y;
+  const float iz2 = f.iz * f.iz;
+  float gp0 = gmx * fx * f.iz;
+  float gp1 = gmy * fy * f.iz;
+  float gp2 = g2.y - (gmx * fx * f.p[0] + gmy * fy * f.p[1]) * iz2 - (gJ00 * fx + gJ11 * fy) * iz2;
   if (f.clx) {
     gp2 -= gJ02 * f.J02 * f.iz;
   } else {
-    gp0 -= gJ02 * a.fx * iz2;
-    gp2 += gJ02 * 2.0 * a.fx * f.p[0] * iz2 * f.iz;
+    gp0 -= gJ02 * fx * iz2;
+    gp2 += gJ02 * 2.0f * fx * f.p[0] * iz2 * f.iz;
   }
   if (f.cly) {
     gp2 -= gJ12 * f.J12 * f.iz;
   } else {
-    gp1 -= gJ12 * a.fy * iz2;
-    gp2 += gJ12 * 2.0 * a.fy * f.p[1] * iz2 * f.iz;
+    gp1 -= gJ12 * fy * iz2;
+    gp2 += gJ12 * 2.0f * fy * f.p[1] * iz2 * f.iz;
   }
 
   // p = R mu + t
   gmu[0] += f.R[0] * gp0 + f.R[3] * gp1 + f.R[6] * gp2;
   gmu[1] += f.R[1] * gp0 + f.R[4] * gp1 + f.R[7] * gp2;
   gmu[2] += f.R[2] * gp0 + f.R[5] * gp1 + f.R[8] * gp2;
-  ba.gm[i] += (float)gmu[0];
-  ba.gm[n + i] += (float)gmu[1];
-  ba.gm[2 * n + i] += (float)gmu[2];
+  ba.gm[i] += gmu[0];
+  ba.gm[n + i] += gmu[1];
+  ba.gm[2 * n + i] += gmu[2];
 
   // pose: dL/dR = J^T gT (covariance) + gp mu^T; dL/dt = gp
-  const double gp[3] = {gp0, gp1, gp2};
+  const float gp[3] = {gp0, gp1, gp2};
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    pose_acc[c] += f.J00 * gT[c] + gp0 * mu[c];
-    pose_acc[3 + c] += f.J11 * gT[3 + c] + gp1 * mu[c];
-    pose_acc[6 + c] += f.J02 * gT[c] + f.J12 * gT[3 + c] + gp2 * mu[c];
-    pose_acc[9 + c] += gp[c];
+    pose[c] = f.J00 * gT[c] + gp0 * mu[c];
+    pose[3 + c] = f.J11 * gT[3 + c] + gp1 * mu[c];
+    pose[6 + c] = f.J02 * gT[c] + f.J12 * gT[3 + c] + gp2 * mu[c];
+    pose[9 + c] = gp[c];
   }
 }
 
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs ba, const int32_t *tiles) {
+  float term[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) term[k] = 0.f;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int nt = i < ba.p.n ? tiles[i] : 0;
+  if (nt > 0) backward_one<DEG>(ba, i, nt, term);
   double acc[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = 0.0;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < ba.p.n && tiles[i] > 0) backward_one<DEG>(ba, i, acc);
+  for (int k = 0; k < 12; ++k) acc[k] = (double)term[k];
 
   // block reduction of the 12 pose partials (fixed order: deterministic)
   __shared__ double red[kBlock / 64][12];
@@ -464,11 +495,6 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const double *partials, int
     d_twist[4] += M[2] - M[6];
     d_twist[5] += M[3] - M[1];
   }
-}
-
-__global__ void k_zero_f32(float *p, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0.0f;
 }
 
 gs_status check_camera(const gs_camera *cam, const char *fn) {
@@ -548,13 +574,14 @@ size_t project_bwd_workspace(int64_t n) {
 }
 
 gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
-                      const gs_projected *proj, const float *g2d, gs_gaussians *grads, double *d_pose,
-                      double *d_twist, void *ws, hipStream_t s) {
+                      const gs_projected *proj, const float *pair_grad, const uint32_t *first_slot,
+                      gs_gaussians *grads, double *d_pose, double *d_twist, void *ws, hipStream_t s) {
   if (g->n == 0) return GS_OK;
   BwdArgs ba;
   ba.p = make_args(cam, rp, g);
   ba.p.rec = proj->rec;
-  ba.g2d = g2d;
+  ba.pair_grad = pair_grad;
+  ba.first_slot = first_slot;
   ba.gm = grads->means;
   ba.gl = grads->log_scales;
   ba.gq = grads->quats;
@@ -570,12 +597,6 @@ gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs
   }
   if (d_pose || d_twist)
     GS_LAUNCH("pose_reduce", k_pose_reduce, 1, 256, 0, s, (const double *)ws, blocks, cam->pose, d_pose, d_twist);
-  return GS_OK;
-}
-
-gs_status zero_f32(float *p, int64_t count, hipStream_t s) {
-  if (count <= 0) return GS_OK;
-  GS_LAUNCH("zero", k_zero_f32, (count + 255) / 256, 256, 0, s, p, count);
   return GS_OK;
 }
 

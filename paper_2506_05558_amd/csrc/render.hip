@@ -36,8 +36,8 @@ struct RenderArgs {
 
 struct Stage {
   float4 a[kBatch];         // mean x, y relative to the tile origin, ca, cb
-  float4 b[kBatch];         // cc, opacity, depth, -
-  float4 c[kBatch];         // colour r, g, b, -
+  float4 b[kBatch];         // cc, opacity, depth, colour r
+  float2 c[kBatch];         // colour g, b
   uint8_t list[4][kBatch];  // per quadrant: batch entries whose box meets it, in order
   int cnt[4][4];            // [entry wave][quadrant] entries
 };
@@ -57,8 +57,8 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
     const float mx = __fadd_rn(__fsub_rn(r0.x, ox), r0.z);
     const float my = __fadd_rn(__fsub_rn(r0.y, oy), r0.w);
     S.a[t] = make_float4(mx, my, __fmul_rn(-0.5f * kLog2e, r1.x), __fmul_rn(-kLog2e, r1.y));
-    S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), r1.w, r2.w, 0.0f);
-    S.c[t] = make_float4(r2.x, r2.y, r2.z, 0.0f);
+    S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), r1.w, r2.w, r2.x);
+    S.c[t] = make_float2(r2.y, r2.z);
     if (gid_out) gid_out[t] = gid;
     // support box, widened so that FP32 rounding can never cull a pixel the
     // per-pixel test would accept
@@ -81,8 +81,7 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if ((mask >> q) & 1u) {
-      int off = rank[q];
-      for (int w = 0; w < ew; ++w) off += S.cnt[w][q];
+      const int off = rank[q] + (ew > 0 ? S.cnt[0][q] : 0) + (ew > 1 ? S.cnt[1][q] : 0) + (ew > 2 ? S.cnt[2][q] : 0);
       S.list[q][off] = (uint8_t)t;
     }
   }
@@ -96,6 +95,15 @@ __device__ __forceinline__ float splat_s2(float ca, float cb, float cc, float dx
 }
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Entry i of wave w's quadrant list and the list's length: the same for
+// every lane, so they live in scalar registers and the loops stay uniform.
+__device__ __forceinline__ int list_entry(const Stage &S, int w, int i) {
+  return __builtin_amdgcn_readfirstlane((int)S.list[w][i]);
+}
+__device__ __forceinline__ int list_count(const Stage &S, int w) {
+  return __builtin_amdgcn_readfirstlane(S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w]);
+}
 
 struct Pixel {
   int px, py, u, v;
@@ -119,6 +127,7 @@ struct FwdOut {
   int32_t *n_contrib, *stats;
 };
 
+template <bool STATS>
 __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;  // uniform over the workgroup
@@ -138,35 +147,41 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   for (uint32_t base = s; base < e; base += kBatch) {
     if (__syncthreads_count(done) == kBatch) break;
     stage_batch(a, base, e, ox, oy, S, nullptr);
-    const int cnt = S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w];
+    const int cnt = list_count(S, w);
     if (__ballot(!done) == 0) continue;
     const int idx0 = (int)(base - s);
+    int kn = list_entry(S, w, 0);  // the next index is read one iteration ahead
     for (int i = 0; i < cnt; ++i) {
-      const int k = S.list[w][i];
+      const int k = kn;
+      if (i + 1 < cnt) kn = list_entry(S, w, i + 1);
       const float4 A = S.a[k];
       const float4 B = S.b[k];
       const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
       const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
       const float alpha = fminf(a.alpha_max, __fmul_rn(B.y, ex));
-      nev += done ? 0 : 1;
+      if (STATS) nev += done ? 0 : 1;
       const bool take = !done && alpha >= a.alpha_min;
       if (__ballot(take) == 0) continue;
-      const float4 C = S.c[k];
+      const float2 C = S.c[k];
       const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
       const bool stop = take && Tn < a.t_min;
       const bool comp = take && !stop;
       const float wgt = comp ? __fmul_rn(alpha, T) : 0.0f;
-      c0 = __fmaf_rn(C.x, wgt, c0);
-      c1 = __fmaf_rn(C.y, wgt, c1);
-      c2 = __fmaf_rn(C.z, wgt, c2);
+      c0 = __fmaf_rn(B.w, wgt, c0);
+      c1 = __fmaf_rn(C.x, wgt, c1);
+      c2 = __fmaf_rn(C.y, wgt, c2);
       D = __fmaf_rn(B.z, wgt, D);
       T = comp ? Tn : T;
       last = comp ? idx0 + k + 1 : last;
-      nsup += take ? 1 : 0;
-      ncomp += comp ? 1 : 0;
-      ntile = stop ? idx0 + k + 1 : ntile;
-      done = done || stop;
-      if (__ballot(!done) == 0) break;
+      if (STATS) {
+        nsup += take ? 1 : 0;
+        ncomp += comp ? 1 : 0;
+        ntile = stop ? idx0 + k + 1 : ntile;
+      }
+      if (__ballot(stop) != 0) {
+        done = done || stop;
+        if (__ballot(!done) == 0) break;
+      }
     }
   }
   if (!P.inside) return;
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   o.alpha[pix] = 1.0f - T;
   o.final_t[pix] = T;
   o.n_contrib[pix] = last;
-  if (o.stats) {
+  if (STATS) {
     o.stats[pix] = ntile;
     o.stats[np + pix] = nev;
     o.stats[2 * np + pix] = nsup;
@@ -191,7 +206,8 @@ struct BwdIn {
   const float *image, *depth, *final_t;
   const int32_t *n_contrib;
   const float *g_image, *g_depth, *g_alpha;
-  float *g2d;  // [n][12] accumulated per-Gaussian 2D gradients
+  const uint32_t *slots;  // emission index of each sorted pair
+  float *pair_grad;       // [M][12] per (Gaussian, tile) pair: the ten 2D gradients
 };
 
 __device__ __forceinline__ int wave_max(int x) {
@@ -200,9 +216,81 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-// Per (wave, list entry) the ten partial gradients are summed over the 64
-// lanes with DPP, lane 63 adds them to the batch's LDS accumulator, and
-// after the batch one lane per entry issues the global float atomics.
+constexpr int kChunk = 8;    // entries per wave handed from phase 1 to phase 2
+constexpr int kPad = kChunk + 1;  // row stride of the per-pixel chunk table (bank-conflict free)
+
+struct BwdShared {
+  float gs[4][64][kPad];    // per wave, pixel, chunk slot: d L / d s  (natural-log exponent)
+  float wt[4][64][kPad];    // per wave, pixel, chunk slot: blending weight alpha T
+  float G[4][4][64];        // per wave: upstream colour (3) and depth gradient per pixel
+  uint8_t slot[4][kChunk];  // per wave: batch entry of each chunk slot
+};
+
+// Phase 2 of the adjoint for one wave: the chunk's entries are spread over
+// the lanes as (slot e = lane & 7, pixel eighth r = lane >> 3); each lane
+// sums its 8 pixels, the eight partial sums are combined with three
+// shuffles, and the slot's lane r = 0 turns the sums into the ten 2D
+// gradients and adds them to the tile's LDS accumulator of that entry.
+//   sum gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2 and sum gs give the mean,
+//   conic and opacity gradients (d s / d mean = (A dx + B dy, B dx + C dy),
+//   d alpha / d o = gs / o); sum w G_c and sum w G_depth the colour and
+//   depth gradients.
+__device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, int nslots,
+                                           float (*acc)[kBatch]) {
+  const int lane = threadIdx.x & 63, e = lane & 7, r = lane >> 3;
+  float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
+  int k = 0;
+  if (e < nslots) {
+    k = B.slot[w][e];
+    const float4 A = S.a[k];
+    const float dy = (float)((w >> 1) * 8 + r) - A.y;  // pixels p = 8 r + i share the row r
+    const float x0 = (float)((w & 1) * 8) - A.x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int p = r * 8 + i;
+      const float gs = B.gs[w][p][e], wt = B.wt[w][p][e];
+      const float dx = x0 + (float)i;
+      const float gdx = gs * dx;
+      m0 += gs;
+      mx += gdx;
+      mxx = __fmaf_rn(gdx, dx, mxx);
+      mxy = __fmaf_rn(gdx, dy, mxy);
+      s0 = __fmaf_rn(wt, B.G[w][0][p], s0);
+      s1 = __fmaf_rn(wt, B.G[w][1][p], s1);
+      s2 = __fmaf_rn(wt, B.G[w][2][p], s2);
+      sd = __fmaf_rn(wt, B.G[w][3][p], sd);
+    }
+    my = m0 * dy;
+    myy = my * dy;
+  }
+  float v[10] = {m0, mx, my, mxx, mxy, myy, s0, s1, s2, sd};
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    v[q] += __shfl_xor(v[q], 8, 64);
+    v[q] += __shfl_xor(v[q], 16, 64);
+    v[q] += __shfl_xor(v[q], 32, 64);
+  }
+  if (r == 0 && e < nslots) {
+    const float4 A = S.a[k];
+    const float4 Bb = S.b[k];
+    // A = -2 ca ln2, B = -cb ln2, C = -2 cc ln2
+    float g[10];
+    g[0] = -kLn2 * (2.0f * A.z * v[1] + A.w * v[2]);
+    g[1] = -kLn2 * (A.w * v[1] + 2.0f * Bb.x * v[2]);
+    g[2] = -0.5f * v[3];
+    g[3] = -v[4];
+    g[4] = -0.5f * v[5];
+    g[5] = v[0] / Bb.y;
+    g[6] = v[6];
+    g[7] = v[7];
+    g[8] = v[8];
+    g[9] = v[9];
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+      if (g[q] != 0.f) atomicAdd(&acc[q][k], g[q]);  // the quadrant waves of one tile meet here
+  }
+}
+
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;
@@ -213,13 +301,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const float fpx = (float)P.px, fpy = (float)P.py;
 
   __shared__ Stage S;
-  __shared__ uint32_t sGid[kBatch];
+  __shared__ uint32_t sSlot[kBatch];
   __shared__ float sAcc[10][kBatch];
+  __shared__ BwdShared B;
   __shared__ int sMax;
 
   const int64_t pix = (int64_t)P.v * a.W + P.u, np = (int64_t)a.W * a.H;
   int ncon = 0;
-  float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GA = 0.f, I0 = 0.f, I1 = 0.f, I2 = 0.f, ID = 0.f, Tf = 1.f;
+  float G0 = 0.f, G1 = 0.f, G2 = 0.f, GD = 0.f, GA = 0.f, GI = 0.f, Tf = 1.f;
   if (P.inside) {
     ncon = bi.n_contrib[pix];
     G0 = bi.g_image[pix];
@@ -227,85 +316,82 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     G2 = bi.g_image[2 * np + pix];
     GD = bi.g_depth ? bi.g_depth[pix] : 0.f;
     GA = bi.g_alpha ? bi.g_alpha[pix] : 0.f;
-    I0 = bi.image[pix];
-    I1 = bi.image[np + pix];
-    I2 = bi.image[2 * np + pix];
-    ID = bi.depth[pix];
+    // G . (everything the pixel outputs): colour incl. background, and depth
+    GI = G0 * bi.image[pix] + G1 * bi.image[np + pix] + G2 * bi.image[2 * np + pix] + GD * bi.depth[pix];
     Tf = bi.final_t[pix];
   }
+  B.G[w][0][lane] = G0;
+  B.G[w][1][lane] = G1;
+  B.G[w][2][lane] = G2;
+  B.G[w][3][lane] = GD;
   if (t == 0) sMax = 0;
   __syncthreads();
-  const int wmax = wave_max(ncon);
+  const int wmax = __builtin_amdgcn_readfirstlane(wave_max(ncon));
   if (lane == 0 && wmax > 0) atomicMax(&sMax, wmax);
   __syncthreads();
   const uint32_t stop = min(s + (uint32_t)sMax, e);
 
-  float T = 1.0f, P0 = 0.f, P1 = 0.f, P2 = 0.f, PD = 0.f;
+  // T: transmittance before the entry; GP: G . (colour, depth) composited so far.
+  // d alpha_k = T_k (G . c_k) - (G . suffix_k) / (1 - alpha_k) + G_alpha T_final / (1 - alpha_k)
+  // with G . suffix_k = GI - GP_k (GP_k includes entry k).
+  float T = 1.0f, GP = 0.f;
   const float GAT = GA * Tf;
 
   for (uint32_t base = s; base < stop; base += kBatch) {
-    __syncthreads();  // the previous batch's flush is done with sAcc / sGid
+    __syncthreads();  // every wave is done with the previous batch's stage and accumulator
 #pragma unroll
     for (int q = 0; q < 10; ++q) sAcc[q][t] = 0.f;
-    stage_batch(a, base, stop, ox, oy, S, sGid);
-    const int cnt = S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w];
+    if (base + t < stop) sSlot[t] = bi.slots[base + t];
+    stage_batch(a, base, stop, ox, oy, S, nullptr);
+    const int cnt = list_count(S, w);
     const int idx0 = (int)(base - s);
+    int nslots = 0;
+    int kn = list_entry(S, w, 0);  // the next index is read one iteration ahead
     for (int i = 0; i < cnt; ++i) {
-      const int k = S.list[w][i];
+      const int k = kn;
       if (idx0 + k >= wmax) break;  // lists ascend: no pixel of this wave reaches further
+      if (i + 1 < cnt) kn = list_entry(S, w, i + 1);
       const float4 A = S.a[k];
-      const float4 B = S.b[k];
+      const float4 Bv = S.b[k];
       const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-      const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
-      const float raw = __fmul_rn(B.y, ex);
+      const float ex = exp2_fast(splat_s2(A.z, A.w, Bv.x, dx, dy));
+      const float raw = __fmul_rn(Bv.y, ex);
       const float alpha = fminf(a.alpha_max, raw);
       const bool take = idx0 + k < ncon && alpha >= a.alpha_min;
       if (__ballot(take) == 0) continue;
-      const float4 C = S.c[k];
-      const float z = B.z;
+      const float2 C = S.c[k];
       const float wgt = take ? __fmul_rn(alpha, T) : 0.0f;
-      P0 = __fmaf_rn(C.x, wgt, P0);
-      P1 = __fmaf_rn(C.y, wgt, P1);
-      P2 = __fmaf_rn(C.z, wgt, P2);
-      PD = __fmaf_rn(z, wgt, PD);
-      // suffix sums: everything composited after this entry plus T_final bg
-      const float S0 = I0 - P0, S1 = I1 - P1, S2 = I2 - P2, SD = ID - PD;
-      const float inv = 1.0f / (1.0f - alpha);
-      const float dalpha = G0 * (C.x * T - S0 * inv) + G1 * (C.y * T - S1 * inv) + G2 * (C.z * T - S2 * inv) +
-                           GD * (z * T - SD * inv) + GAT * inv;
+      const float gc = G0 * Bv.w + G1 * C.x + G2 * C.y + GD * Bv.z;
+      GP = __fmaf_rn(wgt, gc, GP);
+      const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+      const float dalpha = T * gc + (GAT - GI + GP) * inv;
       const bool live = take && raw < a.alpha_max;  // the clamp passes no gradient
-      const float gs = live ? dalpha * raw : 0.0f;    // d alpha / d s (natural log domain)
-      float g[10];
-      // d s / d mean = (A dx + B dy, B dx + C dy), A = -2 ca ln2, B = -cb ln2, C = -2 cc ln2
-      const float gl = -gs * kLn2;
-      g[0] = gl * (2.0f * A.z * dx + A.w * dy);
-      g[1] = gl * (A.w * dx + 2.0f * B.x * dy);
-      g[2] = -0.5f * gs * dx * dx;
-      g[3] = -gs * dx * dy;
-      g[4] = -0.5f * gs * dy * dy;
-      g[5] = live ? dalpha * ex : 0.0f;  // d alpha / d o
-      g[6] = G0 * wgt;
-      g[7] = G1 * wgt;
-      g[8] = G2 * wgt;
-      g[9] = GD * wgt;
+      B.gs[w][lane][nslots] = live ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
+      B.wt[w][lane][nslots] = wgt;
+      if (lane == 0) B.slot[w][nslots] = (uint8_t)k;
       T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
-#pragma unroll
-      for (int q = 0; q < 10; ++q) g[q] = wave_sum_to_lane63(g[q]);
-      if (lane == 63) {
-#pragma unroll
-        for (int q = 0; q < 10; ++q)
-          if (g[q] != 0.f) atomicAdd(&sAcc[q][k], g[q]);
+      if (++nslots == kChunk) {
+        bwd_phase2(S, B, w, nslots, sAcc);
+        nslots = 0;
       }
     }
+    if (nslots > 0) bwd_phase2(S, B, w, nslots, sAcc);
     __syncthreads();
+    // one plain store per (tile, entry): the pair's slot is owned by this tile
     if (base + t < stop) {
-      float *dst = bi.g2d + (size_t)sGid[t] * 12;
-#pragma unroll
-      for (int q = 0; q < 10; ++q) {
-        const float r = sAcc[q][t];
-        if (r != 0.f) unsafeAtomicAdd(dst + q, r);
-      }
+      float4 *dst = (float4 *)(bi.pair_grad + (size_t)sSlot[t] * 12);
+      dst[0] = make_float4(sAcc[0][t], sAcc[1][t], sAcc[2][t], sAcc[3][t]);
+      dst[1] = make_float4(sAcc[4][t], sAcc[5][t], sAcc[6][t], sAcc[7][t]);
+      dst[2] = make_float4(sAcc[8][t], sAcc[9][t], 0.f, 0.f);
     }
+  }
+  // entries past the last contributor of every pixel receive nothing from this tile
+  for (uint32_t j = stop + t; j < e; j += kBatch) {
+    float4 *dst = (float4 *)(bi.pair_grad + (size_t)bi.slots[j] * 12);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    dst[0] = z;
+    dst[1] = z;
+    dst[2] = z;
   }
 }
 
@@ -315,9 +401,8 @@ gs_status validate_camera(const gs_camera *cam, const char *fn);
 gs_status validate_gaussians(const gs_gaussians *g, const char *fn);
 size_t project_bwd_workspace(int64_t n);
 gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
-                      const gs_projected *proj, const float *g2d, gs_gaussians *grads, double *d_pose,
-                      double *d_twist, void *ws, hipStream_t s);
-gs_status zero_f32(float *p, int64_t count, hipStream_t s);
+                      const gs_projected *proj, const float *pair_grad, const uint32_t *first_slot,
+                      gs_gaussians *grads, double *d_pose, double *d_twist, void *ws, hipStream_t s);
 
 static RenderArgs render_args(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                               const uint32_t *values, const uint32_t *ranges) {
@@ -357,18 +442,22 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
              "gs_render_fwd: raster params out of range");
   RenderArgs a = render_args(cam, rp, proj, values, ranges);
   FwdOut o{image, depth, alpha, final_t, n_contrib, stats};
-  GS_LAUNCH("render_fwd", k_render_fwd, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
+  if (stats)
+    GS_LAUNCH("render_fwd", k_render_fwd<true>, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
+  else
+    GS_LAUNCH("render_fwd", k_render_fwd<false>, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
   return GS_OK;
 }
 
-gs_status gs_render_bwd_workspace(int64_t n, size_t *bytes) {
-  GS_REQUIRE(bytes && n >= 0, "gs_render_bwd_workspace: bad argument");
-  *bytes = align_up(sizeof(float) * 12 * (size_t)n) + project_bwd_workspace(n);
+gs_status gs_render_bwd_workspace(int64_t n, int64_t n_instances, size_t *bytes) {
+  GS_REQUIRE(bytes && n >= 0 && n_instances >= 0, "gs_render_bwd_workspace: bad argument");
+  *bytes = align_up(sizeof(float) * 12 * (size_t)n_instances) + project_bwd_workspace(n);
   return GS_OK;
 }
 
 gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
-                        const gs_projected *proj, const uint32_t *values, const uint32_t *ranges, const float *image,
+                        const gs_projected *proj, const uint32_t *values, const uint32_t *slots,
+                        const uint32_t *ranges, const uint32_t *first_slot, int64_t n_instances, const float *image,
                         const float *depth, const float *final_t, const int32_t *n_contrib, const float *dL_dimage,
                         const float *dL_ddepth, const float *dL_dalpha, gs_gaussians *grads, double *dL_dpose,
                         double *dL_dtwist, void *ws, size_t ws_bytes, void *stream) {
@@ -379,21 +468,22 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
   GS_REQUIRE(grads->n == g->n && grads->sh_degree == g->sh_degree, "gs_render_bwd: grads shape differs from g");
   GS_REQUIRE(rp && proj && ranges && image && depth && final_t && n_contrib && dL_dimage,
              "gs_render_bwd: NULL argument");
+  GS_REQUIRE(n_instances >= 0, "gs_render_bwd: n_instances < 0");
+  if (n_instances > 0) GS_REQUIRE(values && slots && first_slot, "gs_render_bwd: NULL list argument");
   size_t need = 0;
-  gs_render_bwd_workspace(g->n, &need);
+  gs_render_bwd_workspace(g->n, n_instances, &need);
   if (ws_bytes < need || (need && !ws)) {
     set_error("gs_render_bwd: workspace %zu bytes < %zu", ws_bytes, need);
     return GS_ERR_WORKSPACE;
   }
   hipStream_t s = (hipStream_t)stream;
   Carve cv(ws);
-  float *g2d = cv.take<float>(12 * (size_t)g->n);
+  float *pair_grad = cv.take<float>(12 * (size_t)n_instances);
   void *pose_ws = cv.take<char>(project_bwd_workspace(g->n));
-  if ((st = zero_f32(g2d, 12 * g->n, s)) != GS_OK) return st;
   RenderArgs a = render_args(cam, rp, proj, values, ranges);
-  BwdIn bi{image, depth, final_t, n_contrib, dL_dimage, dL_ddepth, dL_dalpha, g2d};
+  BwdIn bi{image, depth, final_t, n_contrib, dL_dimage, dL_ddepth, dL_dalpha, slots, pair_grad};
   GS_LAUNCH("render_bwd", k_render_bwd, padded_grid(a.ntiles), 256, 0, s, a, bi);
-  return project_bwd(cam, rp, g, proj, g2d, grads, dL_dpose, dL_dtwist, pose_ws, s);
+  return project_bwd(cam, rp, g, proj, pair_grad, first_slot, grads, dL_dpose, dL_dtwist, pose_ws, s);
 }
 
 }  // extern "C"

@@ -63,12 +63,13 @@ _sig = {
     "gs_last_error": (C.c_char_p, []),
     "gs_project": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp]),
     "gs_bin_sort_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
-    "gs_bin_sort": (C.c_int, [_P(_Camera), _P(_Proj), _i64, _i64, _vp, _sz, _vp, _vp, _vp, _P(_i64), _vp]),
+    "gs_bin_sort": (C.c_int, [_P(_Camera), _P(_Proj), _i64, _i64, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _P(_i64),
+                              _vp]),
     "gs_render_fwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),
-    "gs_render_bwd_workspace": (C.c_int, [_i64, _P(_sz)]),
-    "gs_render_bwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp,
-                                _vp, _vp, _vp, _P(_Gauss), _vp, _vp, _vp, _sz, _vp]),
+    "gs_render_bwd_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
+    "gs_render_bwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp, _vp, _vp, _vp, _i64, _vp,
+                                _vp, _vp, _vp, _vp, _vp, _vp, _P(_Gauss), _vp, _vp, _vp, _sz, _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
     "gs_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _i64, _vp]),
@@ -219,9 +220,11 @@ def project(cam: Camera, g: Gaussians, params: Params = Params(), out: Optional[
 
 @dataclass
 class Binned:
-    tile_ids: torch.Tensor  # (capacity,) uint32 as int32
-    values: torch.Tensor  # (capacity,) uint32 as int32
+    tile_ids: torch.Tensor  # (capacity,) uint32 as int32: tile of each sorted pair
+    values: torch.Tensor  # (capacity,) uint32 as int32: Gaussian of each sorted pair
+    slots: torch.Tensor  # (capacity,) uint32 as int32: emission index of each sorted pair
     ranges: torch.Tensor  # (T, 2) uint32 as int32
+    first_slot: torch.Tensor  # (N,) uint32 as int32: first slot of each visible Gaussian
     n_instances: int
 
 
@@ -238,10 +241,13 @@ class BinSorter:
     def _alloc(self, n, T, dev):
         need = C.c_size_t()
         _check(_lib.gs_bin_sort_workspace(n, self.capacity, C.byref(need)))
+        cap = max(self.capacity, 1)
         self._bufs = dict(ws=torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev),
-                          tile_ids=torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev),
-                          values=torch.empty(max(self.capacity, 1), dtype=torch.int32, device=dev),
-                          ranges=torch.empty((T, 2), dtype=torch.int32, device=dev))
+                          tile_ids=torch.empty(cap, dtype=torch.int32, device=dev),
+                          values=torch.empty(cap, dtype=torch.int32, device=dev),
+                          slots=torch.empty(cap, dtype=torch.int32, device=dev),
+                          ranges=torch.empty((T, 2), dtype=torch.int32, device=dev),
+                          first_slot=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
         self._key = (n, T, self.capacity)
 
     def __call__(self, cam: Camera, proj: Projected) -> Binned:
@@ -255,12 +261,13 @@ class BinSorter:
             m = C.c_int64()
             st = _lib.gs_bin_sort(C.byref(cam.c()), C.byref(proj.c()), n, self.capacity, b["ws"].data_ptr(),
                                   b["ws"].numel(), b["tile_ids"].data_ptr(), b["values"].data_ptr(),
-                                  b["ranges"].data_ptr(), C.byref(m), _stream())
+                                  b["slots"].data_ptr(), b["ranges"].data_ptr(), b["first_slot"].data_ptr(),
+                                  C.byref(m), _stream())
             if st == GS_ERR_CAPACITY:
                 self.capacity = int(m.value * self.growth) + 1024
                 continue
             _check(st)
-            return Binned(b["tile_ids"], b["values"], b["ranges"], int(m.value))
+            return Binned(b["tile_ids"], b["values"], b["slots"], b["ranges"], b["first_slot"], int(m.value))
         raise GsError(GS_ERR_CAPACITY, "bin_sort: capacity did not converge")
 
 
@@ -296,9 +303,9 @@ def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Pa
     return out
 
 
-def render_bwd_workspace(n: int) -> int:
+def render_bwd_workspace(n: int, n_instances: int) -> int:
     need = C.c_size_t()
-    _check(_lib.gs_render_bwd_workspace(n, C.byref(need)))
+    _check(_lib.gs_render_bwd_workspace(n, n_instances, C.byref(need)))
     return int(need.value)
 
 
@@ -308,7 +315,8 @@ def render_bwd(cam: Camera, g: Gaussians, proj: Projected, binned: Binned, frame
                dL_dpose: Optional[torch.Tensor] = None, dL_dtwist: Optional[torch.Tensor] = None,
                params: Params = Params(), ws: Optional[torch.Tensor] = None):
     """Accumulates into grads (new zeros if None) and the optional float64
-    dL_dpose [12] / dL_dtwist [6]; returns grads."""
+    dL_dpose [12] / dL_dtwist [6]; returns grads.  ws, if given, is grown
+    by reallocation only when too small (pass a large one to avoid it)."""
     H, W = cam.height, cam.width
     _require(dL_dimage, torch.float32, (3, H, W), "dL_dimage")
     if dL_ddepth is not None:
@@ -317,14 +325,15 @@ def render_bwd(cam: Camera, g: Gaussians, proj: Projected, binned: Binned, frame
         _require(dL_dalpha, torch.float32, (H, W), "dL_dalpha")
     if grads is None:
         grads = g.zeros_like()
-    need = render_bwd_workspace(g.n)
+    need = render_bwd_workspace(g.n, binned.n_instances)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.means.device)
     for t, nm, k in ((dL_dpose, "dL_dpose", 12), (dL_dtwist, "dL_dtwist", 6)):
         if t is not None:
             _require(t, torch.float64, (k,), nm)
     _check(_lib.gs_render_bwd(C.byref(cam.c()), C.byref(params.c()), C.byref(g.c()), C.byref(proj.c()),
-                              binned.values.data_ptr(), binned.ranges.data_ptr(), frame.image.data_ptr(),
+                              binned.values.data_ptr(), binned.slots.data_ptr(), binned.ranges.data_ptr(),
+                              binned.first_slot.data_ptr(), binned.n_instances, frame.image.data_ptr(),
                               frame.depth.data_ptr(), frame.final_t.data_ptr(), frame.n_contrib.data_ptr(),
                               dL_dimage.data_ptr(), _ptr(dL_ddepth), _ptr(dL_dalpha), C.byref(grads.c()),
                               _ptr(dL_dpose), _ptr(dL_dtwist), ws.data_ptr(), ws.numel(), _stream()))

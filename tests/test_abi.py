@@ -83,5 +83,5 @@ def test_workspace_queries(lib):
     assert lib.gs_bin_sort_workspace(2_000_000, 20_000_000, C.byref(sz)) == 0
     assert sz.value >= 4 * (8 * 2_000_000 + 2 * 20_000_000)
     assert lib.gs_bin_sort_workspace(-1, 0, C.byref(sz)) == 1
-    lib.gs_render_bwd_workspace.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
-    assert lib.gs_render_bwd_workspace(1000, C.byref(sz)) == 0 and sz.value >= 48_000
+    lib.gs_render_bwd_workspace.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
+    assert lib.gs_render_bwd_workspace(1000, 3000, C.byref(sz)) == 0 and sz.value >= 48 * 3000

@@ -73,6 +73,17 @@ def _check_binning(view, proj, binned):
     assert np.array_equal(tids.astype(np.uint64), ref["keys"] >> np.uint64(32)), "tile ids differ"
     assert np.array_equal(vals, ref["values"]), "Gaussian order differs"
     assert np.array_equal(binned.ranges.cpu().numpy().view(np.uint32), ref["ranges"]), "ranges differ"
+    # slots: a permutation of [0, M); the pairs of Gaussian g hold slots
+    # first_slot[g] + (row-major index of the tile inside g's rect)
+    slots = binned.slots[:M].cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(np.sort(slots), np.arange(M))
+    first = binned.first_slot.cpu().numpy().view(np.uint32).astype(np.int64)
+    tx0, ty0, tx1, ty1, _ = binning.tile_rects(mx, my, radius[0], radius[1], view.width, view.height, 16)
+    g = vals.astype(np.int64)
+    tiles_x = (view.width + 15) // 16
+    t = tids.astype(np.int64)
+    local = (t // tiles_x - ty0[g]) * (tx1[g] - tx0[g] + 1) + (t % tiles_x - tx0[g])
+    assert np.array_equal(slots, first[g] + local)
     return M
 
 
