@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crops", type=int, default=12)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with one plain 256 MiB device copy, the reference for HBM byte counters")
     return ap.parse_args()
 
 
@@ -221,6 +223,7 @@ def main():
     roofline = roof(dominant)
     if roofline is not None:
         roofline["kernel"] = dominant
+        roofline["traffic"] = measured_traffic(dominant)
     others = {k: roof(k) for k in ["render_fwd", "render_bwd", "project", "project_bwd"] if k in kernels}
 
     out = {
@@ -248,7 +251,30 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(views[3], start, args.cpu_crops)
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by a plain copy of known size), or None
+    if none were taken or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("k_" + kernel)
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(view, scene, n_crops):
