@@ -43,12 +43,17 @@ MASK64 = (1 << 64) - 1
 
 
 def log_kernel_f64(sigma: float = 1.0):
+    """Analytic LoG taps on the integer grid, radius ceil(4 sigma), shifted by
+    their exactly rounded mean so that they sum to zero."""
     r = int(math.ceil(4 * sigma))
-    y, x = np.mgrid[-r:r + 1, -r:r + 1].astype(np.float64)
-    rr = x * x + y * y
-    g = np.exp(-rr / (2 * sigma * sigma)) / (2 * math.pi * sigma * sigma)
-    k = (rr - 2 * sigma * sigma) / sigma ** 4 * g
-    return k - k.mean()
+    n = 2 * r + 1
+    k = np.zeros((n, n))
+    for y in range(-r, r + 1):
+        for x in range(-r, r + 1):
+            rr = float(x * x + y * y)
+            g = math.exp(-rr / (2 * sigma * sigma)) / (2 * math.pi * sigma * sigma)
+            k[y + r, x + r] = (rr - 2 * sigma * sigma) / sigma ** 4 * g
+    return k - math.fsum(k.ravel()) / (n * n)
 
 
 def _padded(img, r):

@@ -28,11 +28,12 @@ constexpr int kRadixBlock = 256;                    // 4 waves
 constexpr int kWaves = kRadixBlock / 64;
 
 // ------------------------------------------------------------------- scan
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
   const int lane = __lane_id();
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
+    const T y = __shfl_up(x, off, 64);
     if (lane >= off) x += y;
   }
   return x;
@@ -40,13 +41,14 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 
 // Exclusive scan of one value per thread over the workgroup; returns the
 // workgroup total through *total.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *total) {
-  __shared__ uint32_t wsum[kScanBlock / 64];
+template <class T>
+__device__ __forceinline__ T block_excl_scan(T x, T *total) {
+  __shared__ T wsum[kScanBlock / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t inc = wave_incl_scan(x);
+  const T inc = wave_incl_scan<T>(x);
   if (lane == 63) wsum[w] = inc;
   __syncthreads();
-  uint32_t before = 0, all = 0;
+  T before = 0, all = 0;
 #pragma unroll
   for (int i = 0; i < kScanBlock / 64; ++i) {
     if (i < w) before += wsum[i];
@@ -57,30 +59,32 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *total)
   return before + inc - x;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const uint32_t *in, int64_t count, uint32_t *partials) {
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const T *in, int64_t count, T *partials) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t sum = 0;
+  T sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k)
     if (base + k < count) sum += in[base + k];
-  uint32_t total;
-  block_excl_scan(sum, &total);
+  T total;
+  block_excl_scan<T>(sum, &total);
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
 // One workgroup: exclusive scan of the partials in place, total -> *total.
-__global__ __launch_bounds__(kScanBlock) void k_scan_spine(uint32_t *partials, int64_t nparts, uint32_t *total) {
-  uint32_t carry = 0;
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_spine(T *partials, int64_t nparts, T *total) {
+  T carry = 0;
   for (int64_t base = 0; base < nparts; base += kScanTile) {
     const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
-    uint32_t v[kScanItems], sum = 0;
+    T v[kScanItems], sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-      v[k] = (i0 + k < nparts) ? partials[i0 + k] : 0u;
+      v[k] = (i0 + k < nparts) ? partials[i0 + k] : (T)0;
       sum += v[k];
     }
-    uint32_t tot;
-    uint32_t run = carry + block_excl_scan(sum, &tot);
+    T tot;
+    T run = carry + block_excl_scan<T>(sum, &tot);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
       if (i0 + k < nparts) partials[i0 + k] = run;
@@ -91,22 +95,28 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_spine(uint32_t *partials, i
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t *in, uint32_t *out, int64_t count,
-                                                           const uint32_t *partials) {
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, int64_t count, const T *partials) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems], sum = 0;
+  T v[kScanItems], sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < count) ? in[base + k] : 0u;
+    v[k] = (base + k < count) ? in[base + k] : (T)0;
     sum += v[k];
   }
-  uint32_t tot;
-  uint32_t run = partials[blockIdx.x] + block_excl_scan(sum, &tot);
+  T tot;
+  T run = partials[blockIdx.x] + block_excl_scan<T>(sum, &tot);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < count) out[base + k] = run;
     run += v[k];
   }
+}
+
+template <class T>
+__global__ void k_fill(T *p, int64_t count, T value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = value;
 }
 
 // ------------------------------------------------------------- radix sort
@@ -233,10 +243,6 @@ __global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, co
     }
 }
 
-__global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t value) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = value;
-}
 
 __global__ void k_ranges(const uint32_t *tile_keys, uint32_t M, uint32_t *ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -302,22 +308,31 @@ gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], uint32_t *v2[2], const uint
 
 size_t scan_workspace(int64_t count) {
   const int64_t nparts = (count + kScanTile - 1) / kScanTile;
-  return align_up(sizeof(uint32_t) * (size_t)(nparts + 1));
+  return align_up(sizeof(uint64_t) * (size_t)(nparts + 1));
+}
+
+template <class T>
+static gs_status scan_exclusive_t(const T *in, T *out, int64_t count, T *total, void *ws, hipStream_t s) {
+  if (count <= 0) {
+    if (total) GS_LAUNCH("fill", k_fill<T>, 1, 64, 0, s, total, 1, (T)0);
+    return GS_OK;
+  }
+  const int64_t nparts = (count + kScanTile - 1) / kScanTile;
+  T *partials = (T *)ws;
+  GS_LAUNCH("scan", k_scan_reduce<T>, nparts, kScanBlock, 0, s, in, count, partials);
+  GS_LAUNCH("scan", k_scan_spine<T>, 1, kScanBlock, 0, s, partials, nparts, total);
+  GS_LAUNCH("scan", k_scan_apply<T>, nparts, kScanBlock, 0, s, in, out, count, (const T *)partials);
+  return GS_OK;
 }
 
 // Exclusive scan; in may equal out.  total (device, may be NULL) receives the sum.
 gs_status scan_exclusive(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total, void *ws,
                          hipStream_t s) {
-  if (count <= 0) {
-    if (total) GS_LAUNCH("fill", k_fill_u32, 1, 64, 0, s, total, 1, 0u);
-    return GS_OK;
-  }
-  const int64_t nparts = (count + kScanTile - 1) / kScanTile;
-  uint32_t *partials = (uint32_t *)ws;
-  GS_LAUNCH("scan", k_scan_reduce, nparts, kScanBlock, 0, s, in, count, partials);
-  GS_LAUNCH("scan", k_scan_spine, 1, kScanBlock, 0, s, partials, nparts, total);
-  GS_LAUNCH("scan", k_scan_apply, nparts, kScanBlock, 0, s, in, out, count, (const uint32_t *)partials);
-  return GS_OK;
+  return scan_exclusive_t<uint32_t>(in, out, count, total, ws, s);
+}
+gs_status scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t count, uint64_t *total, void *ws,
+                             hipStream_t s) {
+  return scan_exclusive_t<uint64_t>(in, out, count, total, ws, s);
 }
 
 }  // namespace gsmi
@@ -419,7 +434,7 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
     set_error("gs_bin_sort: %u pairs exceed capacity %lld", M, (long long)capacity);
     return GS_ERR_CAPACITY;
   }
-  GS_LAUNCH("bin_fill", k_fill_u32, grid1(2 * (int64_t)T), 256, 0, s, ranges, 2 * (int64_t)T, 0u);
+  GS_LAUNCH("bin_fill", k_fill<uint32_t>, grid1(2 * (int64_t)T), 256, 0, s, ranges, 2 * (int64_t)T, 0u);
   if (M == 0) return GS_OK;
 
   // 4. emit pairs in depth order, 5. stable sort by tile, 6. ranges

@@ -67,6 +67,8 @@ struct Carve {
 size_t scan_workspace(int64_t count);
 gs_status scan_exclusive(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total, void *ws,
                          hipStream_t s);
+gs_status scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t count, uint64_t *total, void *ws,
+                             hipStream_t s);
 
 // -------------------------------------------------------------- device side
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
