@@ -238,6 +238,77 @@ gs_status gs_zero(void *ptr, size_t bytes, void *stream);
  * processed, which the sparse Adam step of section 4.3 updates. */
 gs_status gs_mark_visible(const int32_t *tiles_touched, int64_t n, int32_t *mask, void *stream);
 
+/* ---- spawning (section 4.2) ---------------------------------------------
+ * A new frame spawns primitives where its image has structure that the
+ * current model does not render (Eq. 1-3):
+ *   P_L(p) = min(|LoG * I|(p), 1), the L2 norm over R, G, B of the response
+ *            of the input image I to a Laplacian-of-Gaussian filter;
+ *   P~(p)  = the same quantity on the image rendered from the new view
+ *            (absent on the first frame: P~ = 0);
+ *   P_s(p) = max(P_L(p) - P~(p), 0), the spawn probability.
+ * The filter: the analytic LoG of standard deviation sigma sampled on the
+ * integer grid out to radius r = ceil(4 sigma), minus the taps' exactly
+ * rounded mean (so they sum to zero), rounded to float32; replicated
+ * borders.  The probability is computed in float32 in a fixed order (taps
+ * row by row, each product rounded then added; squares of R, G, B added in
+ * that order; correctly rounded sqrt), so every spawn decision below, an
+ * integer function of it, is reproducible bit for bit.
+ *
+ * Selection (the paper samples pixels by P_s; the draws are fixed here):
+ *   q(p) = floor(P_s(p) 2^24);
+ *   GS_SPAWN_BERNOULLI: pixel p spawns iff u(p) < q(p), u(p) = the top 24
+ *     bits of SplitMix64 (Steele, Lea, Flood 2014) of seed + p, p the flat
+ *     pixel index v W + u;
+ *   GS_SPAWN_FIXED_K: systematic sampling of K thresholds over the integer
+ *     masses: S = sum q, o = top 24 bits of SplitMix64(seed),
+ *     U = floor(S o / 2^24), t_j = floor((j S + U) / K), j = 0..K-1; a pixel
+ *     spawns (once) if some t_j falls in [prefix(p), prefix(p) + q(p)).
+ * Initialisation (the paper's direct rule): position at the pixel's depth D
+ * on its ray, mean = R^T (D ((u - cx)/fx, (v - cy)/fy, 1) - t); isotropic
+ * scale D / (2 f sqrt(max(P_L, min_prob))), f = sqrt(fx fy), the
+ * nearest-neighbour distance of a Poisson process of intensity P_L per
+ * pixel (Clark-Evans) in world units; rotation = the camera's axes (the
+ * unit quaternion of R^T with w >= 0); opacity `opacity`; colour = the
+ * pixel's, as the DC SH term (rgb - 0.5) 2 sqrt(pi), higher SH zero. */
+typedef enum { GS_SPAWN_BERNOULLI = 0, GS_SPAWN_FIXED_K = 1 } gs_spawn_mode;
+
+typedef struct {
+  float sigma;      /* LoG standard deviation in pixels, (0, 2] (1) */
+  int32_t mode;     /* gs_spawn_mode (GS_SPAWN_BERNOULLI) */
+  int64_t k;        /* thresholds for GS_SPAWN_FIXED_K, >= 0 */
+  uint64_t seed;    /* counter base of the draws (0) */
+  float opacity;    /* initial opacity, (0, 1) (0.1) */
+  float min_prob;   /* floor of P_L in the scale rule, > 0 (1e-4) */
+} gs_spawn_params;  /* HOST memory */
+
+void gs_default_spawn_params(gs_spawn_params *sp);
+
+/* The float32 LoG taps: writes (2r+1)^2 row-major values into HOST taps
+ * (room for 289) and r into HOST *radius.  Host only, no device work. */
+gs_status gs_spawn_log_taps(float sigma, float *taps, int32_t *radius);
+
+/* image, rendered: [3][H][W] float32 in [0, 1] (rendered may be NULL: first
+ * frame).  Writes p_s [H][W] and, if not NULL, p_l [H][W]. */
+gs_status gs_spawn_probability(const gs_camera *cam, const float *image, const float *rendered,
+                               const gs_spawn_params *sp, float *p_l, float *p_s, void *stream);
+
+/* Selects pixels from p_s [H][W] and writes their flat indices in
+ * increasing order to pixels [capacity], the count to HOST *n_selected.
+ * Synchronises the stream once (to read the count).  If the count exceeds
+ * capacity: GS_ERR_CAPACITY, *n_selected = the count, pixels unwritten.
+ * ws: gs_spawn_select_workspace(W, H) bytes. */
+gs_status gs_spawn_select_workspace(int32_t width, int32_t height, size_t *bytes);
+gs_status gs_spawn_select(const gs_camera *cam, const float *p_s, const gs_spawn_params *sp, int64_t capacity,
+                          int32_t *pixels, int64_t *n_selected, void *ws, size_t ws_bytes, void *stream);
+
+/* Writes the rule's parameters of `count` primitives spawned at pixels
+ * [count] into entries [offset, offset + count) of out (planes of stride
+ * out->n; offset + count > out->n is GS_ERR_CAPACITY).  image [3][H][W],
+ * depth [H][W] (> 0 at the selected pixels), p_l [H][W]. */
+gs_status gs_spawn_rule(const gs_camera *cam, const float *image, const float *depth, const float *p_l,
+                        const int32_t *pixels, int64_t count, const gs_spawn_params *sp, gs_gaussians *out,
+                        int64_t offset, void *stream);
+
 /* ---- profiling ----------------------------------------------------------
  * When enabled, every kernel launch is bracketed with HIP events on its
  * stream; gs_profile_read sums the elapsed milliseconds of all launches of

@@ -119,8 +119,14 @@ def splitmix64(x: int) -> int:
 
 
 def uniform24(seed: int, count: int) -> np.ndarray:
-    """u(p) for p = 0..count-1: top 24 bits of splitmix64(seed + p)."""
-    return np.array([splitmix64((seed + p) & MASK64) >> 40 for p in range(count)], np.int64)
+    """u(p) for p = 0..count-1: top 24 bits of splitmix64(seed + p), the same
+    steps as `splitmix64` on uint64 arrays (wrapping arithmetic)."""
+    z = np.arange(count, dtype=np.uint64) + np.uint64(seed & MASK64)
+    z = z + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(40)).astype(np.int64)
 
 
 def quantize(ps_f32):

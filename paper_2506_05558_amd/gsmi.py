@@ -56,6 +56,11 @@ class _Proj(C.Structure):
     _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles_touched", C.c_void_p)]
 
 
+class _SpawnParams(C.Structure):
+    _fields_ = [("sigma", C.c_float), ("mode", C.c_int32), ("k", C.c_int64), ("seed", C.c_uint64),
+                ("opacity", C.c_float), ("min_prob", C.c_float)]
+
+
 _vp, _i64, _i32, _f, _sz = C.c_void_p, C.c_int64, C.c_int32, C.c_float, C.c_size_t
 _P = C.POINTER
 _sig = {
@@ -77,6 +82,13 @@ _sig = {
     "gs_pose_6d_bwd": (C.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gs_zero": (C.c_int, [_vp, _sz, _vp]),
     "gs_mark_visible": (C.c_int, [_vp, _i64, _vp, _vp]),
+    "gs_default_spawn_params": (None, [_P(_SpawnParams)]),
+    "gs_spawn_log_taps": (C.c_int, [_f, _P(C.c_float), _P(_i32)]),
+    "gs_spawn_probability": (C.c_int, [_P(_Camera), _vp, _vp, _P(_SpawnParams), _vp, _vp, _vp]),
+    "gs_spawn_select_workspace": (C.c_int, [_i32, _i32, _P(_sz)]),
+    "gs_spawn_select": (C.c_int, [_P(_Camera), _vp, _P(_SpawnParams), _i64, _vp, _P(_i64), _vp, _sz, _vp]),
+    "gs_spawn_rule": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _vp, _i64, _P(_SpawnParams), _P(_Gauss), _i64,
+                                _vp]),
     "gs_profile_enable": (None, [C.c_int]),
     "gs_profile_reset": (None, []),
     "gs_profile_read": (C.c_int, [C.c_char_p, _P(C.c_double), _P(_i64)]),
@@ -381,6 +393,90 @@ def zero_(t: torch.Tensor):
 def mark_visible(proj: Projected, mask: torch.Tensor):
     _check(_lib.gs_mark_visible(proj.tiles_touched.data_ptr(), proj.tiles_touched.numel(), mask.data_ptr(),
                                 _stream()))
+
+
+# ------------------------------------------------------------------ spawning
+SPAWN_BERNOULLI, SPAWN_FIXED_K = 0, 1
+
+
+@dataclass
+class SpawnParams:
+    sigma: float = 1.0
+    mode: int = SPAWN_BERNOULLI
+    k: int = 0
+    seed: int = 0
+    opacity: float = 0.1
+    min_prob: float = 1e-4
+
+    def c(self):
+        return _SpawnParams(self.sigma, self.mode, self.k, self.seed & ((1 << 64) - 1), self.opacity, self.min_prob)
+
+
+def default_spawn_params() -> SpawnParams:
+    p = _SpawnParams()
+    _lib.gs_default_spawn_params(C.byref(p))
+    return SpawnParams(p.sigma, p.mode, p.k, p.seed, p.opacity, p.min_prob)
+
+
+def spawn_log_taps(sigma: float = 1.0):
+    """The library's float32 LoG taps as a (2r+1, 2r+1) CPU tensor (host call)."""
+    buf = (C.c_float * 289)()
+    r = C.c_int32()
+    _check(_lib.gs_spawn_log_taps(sigma, buf, C.byref(r)))
+    n = 2 * r.value + 1
+    return torch.tensor(list(buf[:n * n]), dtype=torch.float32).reshape(n, n)
+
+
+def spawn_probability(cam: Camera, image: torch.Tensor, rendered: Optional[torch.Tensor] = None,
+                      sp: SpawnParams = SpawnParams(), p_l: Optional[torch.Tensor] = None,
+                      p_s: Optional[torch.Tensor] = None):
+    """(P_L, P_s) [H][W] of a [3][H][W] image against the rendered one (Eq. 1-3)."""
+    H, W = cam.height, cam.width
+    _require(image, torch.float32, (3, H, W), "image")
+    if rendered is not None:
+        _require(rendered, torch.float32, (3, H, W), "rendered")
+    if p_l is None:
+        p_l = torch.empty((H, W), dtype=torch.float32, device=image.device)
+    if p_s is None:
+        p_s = torch.empty((H, W), dtype=torch.float32, device=image.device)
+    _require(p_l, torch.float32, (H, W), "p_l")
+    _require(p_s, torch.float32, (H, W), "p_s")
+    _check(_lib.gs_spawn_probability(C.byref(cam.c()), image.data_ptr(), _ptr(rendered), C.byref(sp.c()),
+                                     p_l.data_ptr(), p_s.data_ptr(), _stream()))
+    return p_l, p_s
+
+
+def spawn_select(cam: Camera, p_s: torch.Tensor, sp: SpawnParams = SpawnParams(),
+                 capacity: Optional[int] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Flat indices (int32, increasing) of the pixels that spawn."""
+    H, W = cam.height, cam.width
+    _require(p_s, torch.float32, (H, W), "p_s")
+    need = C.c_size_t()
+    _check(_lib.gs_spawn_select_workspace(W, H, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=p_s.device)
+    if capacity is None:
+        capacity = H * W
+    pixels = torch.empty(max(capacity, 1), dtype=torch.int32, device=p_s.device)
+    count = C.c_int64()
+    _check(_lib.gs_spawn_select(C.byref(cam.c()), p_s.data_ptr(), C.byref(sp.c()), capacity, pixels.data_ptr(),
+                                C.byref(count), ws.data_ptr(), ws.numel(), _stream()))
+    return pixels[:count.value]
+
+
+def spawn_rule(cam: Camera, image: torch.Tensor, depth: torch.Tensor, p_l: torch.Tensor, pixels: torch.Tensor,
+               out: Gaussians, offset: int = 0, sp: SpawnParams = SpawnParams()):
+    """Writes the direct rule's parameters of the spawned pixels into out[offset:offset+len(pixels)]."""
+    H, W = cam.height, cam.width
+    _require(image, torch.float32, (3, H, W), "image")
+    _require(depth, torch.float32, (H, W), "depth")
+    _require(p_l, torch.float32, (H, W), "p_l")
+    if pixels.numel():
+        _require(pixels, torch.int32, (pixels.numel(),), "pixels")
+    _check(_lib.gs_spawn_rule(C.byref(cam.c()), image.data_ptr(), depth.data_ptr(), p_l.data_ptr(),
+                              _ptr(pixels) if pixels.numel() else None, pixels.numel(), C.byref(sp.c()),
+                              C.byref(out.c()), offset, _stream()))
+    return out
 
 
 def profile_enable(on: bool = True):

@@ -219,3 +219,36 @@ def small_scene(seed: int, n: int = 12, size: int = 32, sh_degree: int = 0, spre
     if nb > 1:
         sh[1:] = rng.normal(0.0, 0.3, (nb - 1, 3, n))
     return view, Scene(means, log_scales, quats, opacity_logits, sh, sh_degree)
+
+
+def spawn_frame(seed: int, width: int = 1920, height: int = 1080, n_rects: int = 60, missing: float = 0.5):
+    """A new frame for the spawn step (section 4.2): (image, rendered, depth).
+
+    image [3][H][W] in [0,1]: a smooth background colour gradient, `n_rects`
+    random axis-aligned rectangles of uniform random colour (sides
+    U[2%, 30%] of the image, so edges at all scales), and N(0, 0.02) pixel
+    noise clipped to [0, 1] (the sensor noise that gives every pixel a small
+    P_L).  rendered: the same composition with a random `missing` fraction of
+    the rectangles left out and no noise -- the model renders part of the
+    frame's structure.  depth [H][W]: the smooth depth field of `ray_scene`
+    in [1, 20], with each rectangle at its own constant depth U[1, 20]."""
+    rng = np.random.default_rng(seed)
+    H, W = height, width
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    base = np.stack([0.3 + 0.4 * x / max(W - 1, 1), 0.3 + 0.4 * y / max(H - 1, 1),
+                     np.full((H, W), 0.5)])
+    img, ren = base.copy(), base.copy()
+    dz = _depth_field(rng, W, H)(x, y)
+    keep = rng.random(n_rects) >= missing
+    for i in range(n_rects):
+        w = int(rng.uniform(0.02, 0.3) * W) + 1
+        h = int(rng.uniform(0.02, 0.3) * H) + 1
+        x0 = int(rng.integers(0, max(W - w, 1)))
+        y0 = int(rng.integers(0, max(H - h, 1)))
+        col = rng.random(3)
+        img[:, y0:y0 + h, x0:x0 + w] = col[:, None, None]
+        if keep[i]:
+            ren[:, y0:y0 + h, x0:x0 + w] = col[:, None, None]
+        dz[y0:y0 + h, x0:x0 + w] = rng.uniform(1.0, 20.0)
+    img = np.clip(img + rng.normal(0, 0.02, img.shape), 0, 1)
+    return img.astype(np.float32), ren.astype(np.float32), dz.astype(np.float32)

@@ -85,3 +85,44 @@ def test_workspace_queries(lib):
     assert lib.gs_bin_sort_workspace(-1, 0, C.byref(sz)) == 1
     lib.gs_render_bwd_workspace.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
     assert lib.gs_render_bwd_workspace(1000, 3000, C.byref(sz)) == 0 and sz.value >= 48 * 3000
+
+
+def test_spawn_taps_equal_the_oracle_bitwise(lib):
+    """The library's LoG taps (host arithmetic: libm exp, exactly rounded
+    mean) are the oracle's taps rounded to float32, bit for bit."""
+    import numpy as np
+    from oracle import spawn
+    from paper_2506_05558_amd import gsmi
+    for sigma in (1.0, 0.7, 1.5, 2.0):
+        t = gsmi.spawn_log_taps(sigma).numpy()
+        o = spawn.log_kernel_f64(float(np.float32(sigma))).astype(np.float32)
+        assert t.shape == o.shape and np.array_equal(t.view(np.uint32), o.view(np.uint32)), sigma
+    with pytest.raises(gsmi.GsError):
+        gsmi.spawn_log_taps(2.5)  # radius beyond the kernel's halo
+
+
+def test_spawn_validation(lib):
+    from paper_2506_05558_amd import gsmi as g
+    cam = g._Camera(16, 16, 10.0, 10.0, 8.0, 8.0, 0.2, (C.c_float * 3)(0, 0, 0), 16)
+    sp = g._SpawnParams()
+    g._lib.gs_default_spawn_params(C.byref(sp))
+    assert abs(sp.sigma - 1.0) < 1e-7 and sp.mode == g.SPAWN_BERNOULLI and abs(sp.opacity - 0.1) < 1e-7
+    # NULL image
+    assert g._lib.gs_spawn_probability(C.byref(cam), None, None, C.byref(sp), None, 16, None) == g.GS_ERR_INVALID_ARG
+    sp.mode = 7
+    assert g._lib.gs_spawn_probability(C.byref(cam), 16, None, C.byref(sp), None, 16, None) == g.GS_ERR_INVALID_ARG
+    assert b"mode" in g._lib.gs_last_error()
+    sp.mode, sp.k = g.SPAWN_FIXED_K, -1
+    n = C.c_int64()
+    assert g._lib.gs_spawn_select(C.byref(cam), 16, C.byref(sp), 0, None, C.byref(n), None, 0,
+                                  None) == g.GS_ERR_INVALID_ARG
+    sp.k, sp.opacity = 10, 1.0
+    gau = g._Gauss(4, 0, 16, 16, 16, 16, 16)
+    assert g._lib.gs_spawn_rule(C.byref(cam), 16, 16, 16, 16, 1, C.byref(sp), C.byref(gau), 0,
+                                None) == g.GS_ERR_INVALID_ARG
+    sp.opacity = 0.1
+    # destination too small: offset + count > n
+    assert g._lib.gs_spawn_rule(C.byref(cam), 16, 16, 16, 16, 3, C.byref(sp), C.byref(gau), 2,
+                                None) == g.GS_ERR_CAPACITY
+    sz = C.c_size_t()
+    assert g._lib.gs_spawn_select_workspace(1920, 1080, C.byref(sz)) == 0 and sz.value >= 24 * 1920 * 1080

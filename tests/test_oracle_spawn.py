@@ -107,6 +107,11 @@ def test_splitmix64_published_value():
 
 def test_uniform_draws_are_uniform():
     u = spawn.uniform24(12345, 20000)
+    # the array form is the scalar generator, including the wrap of seed + p past 2^64
+    for p in (0, 1, 777, 19999):
+        assert u[p] == spawn.splitmix64(12345 + p) >> 40
+    w = spawn.uniform24((1 << 64) - 2, 5)
+    assert [int(x) for x in w] == [spawn.splitmix64(((1 << 64) - 2 + p) % (1 << 64)) >> 40 for p in range(5)]
     assert u.min() >= 0 and u.max() < (1 << 24)
     hist = np.bincount(u >> 20, minlength=16)
     assert (np.abs(hist - 1250) < 200).all()
