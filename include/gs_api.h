@@ -309,6 +309,62 @@ gs_status gs_spawn_rule(const gs_camera *cam, const float *image, const float *d
                         const int32_t *pixels, int64_t count, const gs_spawn_params *sp, gs_gaussians *out,
                         int64_t offset, void *stream);
 
+/* ---- learned spawn initialisation ----------------------------------------
+ * A 196 -> 64 -> 64 -> 7 MLP with exact GELU, 0.5 x (1 + erf(x / sqrt 2)),
+ * predicts residuals over the rule above for a primitive spawned at pixel
+ * p = (u, v): outputs 0..2 are added to the three log-scales (camera x, y,
+ * ray axis), 3 to the opacity logit, 4..6 to the colour (so the DC SH term
+ * moves by 2 sqrt(pi) times them).  Inputs: the 7x7 RGB patch centred on p
+ * (row-major, channel-last: input (3 (7 dy + dx) + c)), then the 7x7 depth
+ * patch as log(D(q) / D(p)) (input 147 + 7 dy + dx); replicated borders.
+ * Parameters theta [GS_MLP_PARAMS] float32: W1 [64][196], b1 [64],
+ * W2 [64][64], b2 [64], W3 [7][64], b3 [7] (row-major: layer = W x + b).
+ * Inference runs on BF16 matrix cores (inputs, weights and hidden
+ * activations rounded to bfloat16 to nearest-even, FP32 accumulation);
+ * training in FP32. */
+#define GS_MLP_INPUTS 196
+#define GS_MLP_OUTPUTS 7
+#define GS_MLP_PARAMS 17223
+
+/* Bytes of the packed BF16 inference weights. */
+size_t gs_mlp_packed_bytes(void);
+/* theta [GS_MLP_PARAMS] -> packed [gs_mlp_packed_bytes()] (device). */
+gs_status gs_mlp_pack_bf16(const float *theta, void *packed, void *stream);
+/* features [count][196] of the pixels [count] (flat indices) of a frame:
+ * image [3][H][W], depth [H][W] > 0. */
+gs_status gs_mlp_features(const gs_camera *cam, const float *image, const float *depth, const int32_t *pixels,
+                          int64_t count, float *features, void *stream);
+/* out [count][7] = MLP(features [count][196]) on the BF16 path. */
+gs_status gs_mlp_forward_bf16(const void *packed, const float *features, int64_t count, float *out, void *stream);
+/* Adds the MLP's residuals, computed from the frame at pixels [count], onto
+ * the parameters of entries [offset, offset + count) of out, which hold the
+ * rule's values (gs_spawn_rule).  Features are gathered inside the kernel. */
+gs_status gs_spawn_mlp(const gs_camera *cam, const float *image, const float *depth, const int32_t *pixels,
+                       int64_t count, const void *packed, gs_gaussians *out, int64_t offset, void *stream);
+
+/* One FP32 training step on a batch: loss = mean over batch x 7 of
+ * (MLP(features) - targets)^2 (targets [batch][7]); its gradient is written
+ * to grad [GS_MLP_PARAMS] if not NULL and the loss (before the update) to
+ * *loss (device float) if not NULL; then, if lr != 0, one Adam step on
+ * theta with moments m, v (the update of gs_adam_step, step >= 1).
+ * ws: gs_mlp_train_workspace(batch) bytes.  batch 1 .. 2^24. */
+gs_status gs_mlp_train_workspace(int64_t batch, size_t *bytes);
+gs_status gs_mlp_train_step(float *theta, float *m, float *v, const float *features, const float *targets,
+                            int64_t batch, float lr, float beta1, float beta2, float eps, int32_t step, float *loss,
+                            float *grad, void *ws, size_t ws_bytes, void *stream);
+
+/* The whole spawn step of a new frame: probability, selection, the rule and,
+ * if mlp_packed is not NULL, the learned residuals.  Spawned primitives are
+ * written to out entries [offset, offset + *n_spawned); the selection may
+ * hold at most out->n - offset of them (else GS_ERR_CAPACITY with
+ * *n_spawned = the count, out untouched).  rendered may be NULL (first
+ * frame).  Synchronises the stream once.
+ * ws: gs_spawn_init_workspace(W, H, out->n - offset) bytes. */
+gs_status gs_spawn_init_workspace(int32_t width, int32_t height, int64_t capacity, size_t *bytes);
+gs_status gs_spawn_init(const gs_camera *cam, const float *image, const float *depth, const float *rendered,
+                        const gs_spawn_params *sp, const void *mlp_packed, gs_gaussians *out, int64_t offset,
+                        int64_t *n_spawned, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- profiling ----------------------------------------------------------
  * When enabled, every kernel launch is bracketed with HIP events on its
  * stream; gs_profile_read sums the elapsed milliseconds of all launches of

@@ -404,3 +404,64 @@ gs_status gs_spawn_rule(const gs_camera *cam, const float *image, const float *d
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- composite
+namespace {
+
+struct InitLayout {
+  float *p_l, *p_s;
+  int32_t *pixels;
+  void *sel_ws;
+  size_t sel_bytes, bytes;
+};
+
+InitLayout init_layout(void *ws, int32_t W, int32_t H, int64_t capacity) {
+  Carve cv(ws);
+  InitLayout L;
+  const size_t np = (size_t)W * H;
+  L.p_l = cv.take<float>(np);
+  L.p_s = cv.take<float>(np);
+  L.pixels = cv.take<int32_t>((size_t)(capacity > 0 ? capacity : 1));
+  L.sel_bytes = sel_layout(nullptr, (int64_t)np).bytes;
+  L.sel_ws = cv.take<char>(L.sel_bytes);
+  L.bytes = cv.off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+gs_status gs_spawn_mlp(const gs_camera *cam, const float *image, const float *depth, const int32_t *pixels,
+                       int64_t count, const void *packed, gs_gaussians *out, int64_t offset, void *stream);
+
+gs_status gs_spawn_init_workspace(int32_t width, int32_t height, int64_t capacity, size_t *bytes) {
+  GS_REQUIRE(bytes && width > 0 && height > 0 && capacity >= 0, "gs_spawn_init_workspace: bad argument");
+  *bytes = init_layout(nullptr, width, height, capacity).bytes;
+  return GS_OK;
+}
+
+gs_status gs_spawn_init(const gs_camera *cam, const float *image, const float *depth, const float *rendered,
+                        const gs_spawn_params *sp, const void *mlp_packed, gs_gaussians *out, int64_t offset,
+                        int64_t *n_spawned, void *ws, size_t ws_bytes, void *stream) {
+  gs_status st = validate_camera(cam, "gs_spawn_init");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(out && n_spawned && offset >= 0 && offset <= out->n, "gs_spawn_init: bad argument");
+  const int64_t capacity = out->n - offset;
+  InitLayout L = init_layout(ws, cam->width, cam->height, capacity);
+  if (!ws || ws_bytes < L.bytes) {
+    set_error("gs_spawn_init: workspace %zu bytes < %zu", ws_bytes, L.bytes);
+    return GS_ERR_WORKSPACE;
+  }
+  if ((st = gs_spawn_probability(cam, image, rendered, sp, L.p_l, L.p_s, stream)) != GS_OK) return st;
+  if ((st = gs_spawn_select(cam, L.p_s, sp, capacity, L.pixels, n_spawned, L.sel_ws, L.sel_bytes, stream)) !=
+      GS_OK)
+    return st;
+  if ((st = gs_spawn_rule(cam, image, depth, L.p_l, L.pixels, *n_spawned, sp, out, offset, stream)) != GS_OK)
+    return st;
+  if (mlp_packed)
+    return gs_spawn_mlp(cam, image, depth, L.pixels, *n_spawned, mlp_packed, out, offset, stream);
+  return GS_OK;
+}
+
+}  // extern "C"

@@ -89,6 +89,17 @@ _sig = {
     "gs_spawn_select": (C.c_int, [_P(_Camera), _vp, _P(_SpawnParams), _i64, _vp, _P(_i64), _vp, _sz, _vp]),
     "gs_spawn_rule": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _vp, _i64, _P(_SpawnParams), _P(_Gauss), _i64,
                                 _vp]),
+    "gs_mlp_packed_bytes": (C.c_size_t, []),
+    "gs_mlp_pack_bf16": (C.c_int, [_vp, _vp, _vp]),
+    "gs_mlp_features": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _i64, _vp, _vp]),
+    "gs_mlp_forward_bf16": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "gs_spawn_mlp": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _i64, _vp, _P(_Gauss), _i64, _vp]),
+    "gs_mlp_train_workspace": (C.c_int, [_i64, _P(_sz)]),
+    "gs_mlp_train_step": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _vp, _vp, _sz,
+                                    _vp]),
+    "gs_spawn_init_workspace": (C.c_int, [_i32, _i32, _i64, _P(_sz)]),
+    "gs_spawn_init": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _P(_SpawnParams), _vp, _P(_Gauss), _i64, _P(_i64), _vp,
+                                _sz, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
     "gs_profile_reset": (None, []),
     "gs_profile_read": (C.c_int, [C.c_char_p, _P(C.c_double), _P(_i64)]),
@@ -477,6 +488,105 @@ def spawn_rule(cam: Camera, image: torch.Tensor, depth: torch.Tensor, p_l: torch
                               _ptr(pixels) if pixels.numel() else None, pixels.numel(), C.byref(sp.c()),
                               C.byref(out.c()), offset, _stream()))
     return out
+
+
+def spawn_init(cam: Camera, image: torch.Tensor, depth: torch.Tensor, out: Gaussians, offset: int = 0,
+               rendered: Optional[torch.Tensor] = None, sp: SpawnParams = SpawnParams(),
+               mlp_packed: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> int:
+    """The whole spawn step; returns the number of primitives written at out[offset:]."""
+    H, W = cam.height, cam.width
+    _require(image, torch.float32, (3, H, W), "image")
+    _require(depth, torch.float32, (H, W), "depth")
+    if rendered is not None:
+        _require(rendered, torch.float32, (3, H, W), "rendered")
+    need = C.c_size_t()
+    _check(_lib.gs_spawn_init_workspace(W, H, out.n - offset, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=image.device)
+    n = C.c_int64()
+    _check(_lib.gs_spawn_init(C.byref(cam.c()), image.data_ptr(), depth.data_ptr(), _ptr(rendered), C.byref(sp.c()),
+                              _ptr(mlp_packed), C.byref(out.c()), offset, C.byref(n), ws.data_ptr(), ws.numel(),
+                              _stream()))
+    return n.value
+
+
+# ----------------------------------------------------------------- spawn MLP
+MLP_INPUTS, MLP_OUTPUTS, MLP_PARAMS = 196, 7, 17223
+
+
+def mlp_pack_bf16(theta: torch.Tensor, packed: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _require(theta, torch.float32, (MLP_PARAMS,), "theta")
+    nbytes = int(_lib.gs_mlp_packed_bytes())
+    if packed is None:
+        packed = torch.empty(nbytes, dtype=torch.uint8, device=theta.device)
+    _check(_lib.gs_mlp_pack_bf16(theta.data_ptr(), packed.data_ptr(), _stream()))
+    return packed
+
+
+def mlp_features(cam: Camera, image: torch.Tensor, depth: torch.Tensor, pixels: torch.Tensor) -> torch.Tensor:
+    H, W = cam.height, cam.width
+    _require(image, torch.float32, (3, H, W), "image")
+    _require(depth, torch.float32, (H, W), "depth")
+    out = torch.empty((pixels.numel(), MLP_INPUTS), dtype=torch.float32, device=image.device)
+    if pixels.numel():
+        _require(pixels, torch.int32, (pixels.numel(),), "pixels")
+        _check(_lib.gs_mlp_features(C.byref(cam.c()), image.data_ptr(), depth.data_ptr(), pixels.data_ptr(),
+                                    pixels.numel(), out.data_ptr(), _stream()))
+    return out
+
+
+def mlp_forward_bf16(packed: torch.Tensor, features: torch.Tensor) -> torch.Tensor:
+    n = features.shape[0]
+    _require(features, torch.float32, (n, MLP_INPUTS), "features")
+    out = torch.empty((n, MLP_OUTPUTS), dtype=torch.float32, device=features.device)
+    _check(_lib.gs_mlp_forward_bf16(packed.data_ptr(), features.data_ptr(), n, out.data_ptr(), _stream()))
+    return out
+
+
+def spawn_mlp(cam: Camera, image: torch.Tensor, depth: torch.Tensor, pixels: torch.Tensor, packed: torch.Tensor,
+              out: Gaussians, offset: int = 0):
+    H, W = cam.height, cam.width
+    _require(image, torch.float32, (3, H, W), "image")
+    _require(depth, torch.float32, (H, W), "depth")
+    if pixels.numel():
+        _require(pixels, torch.int32, (pixels.numel(),), "pixels")
+    _check(_lib.gs_spawn_mlp(C.byref(cam.c()), image.data_ptr(), depth.data_ptr(),
+                             _ptr(pixels) if pixels.numel() else None, pixels.numel(), packed.data_ptr(),
+                             C.byref(out.c()), offset, _stream()))
+    return out
+
+
+class MlpTrainer:
+    """FP32 training state of the spawn MLP (theta, Adam moments, workspace)."""
+
+    def __init__(self, theta: torch.Tensor, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        _require(theta, torch.float32, (MLP_PARAMS,), "theta")
+        self.theta = theta
+        self.m = torch.zeros_like(theta)
+        self.v = torch.zeros_like(theta)
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.step_count = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=theta.device)
+        self.ws = torch.empty(0, dtype=torch.uint8, device=theta.device)
+
+    def step(self, features: torch.Tensor, targets: torch.Tensor, lr: Optional[float] = None,
+             grad: Optional[torch.Tensor] = None):
+        b = features.shape[0]
+        _require(features, torch.float32, (b, MLP_INPUTS), "features")
+        _require(targets, torch.float32, (b, MLP_OUTPUTS), "targets")
+        need = C.c_size_t()
+        _check(_lib.gs_mlp_train_workspace(b, C.byref(need)))
+        if self.ws.numel() < need.value:
+            self.ws = torch.empty(int(need.value), dtype=torch.uint8, device=features.device)
+        lr = self.lr if lr is None else lr
+        if lr != 0.0:
+            self.step_count += 1
+        _check(_lib.gs_mlp_train_step(self.theta.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                      features.data_ptr(), targets.data_ptr(), b, lr, self.beta1, self.beta2,
+                                      self.eps, max(self.step_count, 1), self.loss.data_ptr(), _ptr(grad),
+                                      self.ws.data_ptr(), self.ws.numel(), _stream()))
+        return self.loss
 
 
 def profile_enable(on: bool = True):

@@ -252,3 +252,17 @@ def spawn_frame(seed: int, width: int = 1920, height: int = 1080, n_rects: int =
         dz[y0:y0 + h, x0:x0 + w] = rng.uniform(1.0, 20.0)
     img = np.clip(img + rng.normal(0, 0.02, img.shape), 0, 1)
     return img.astype(np.float32), ren.astype(np.float32), dz.astype(np.float32)
+
+
+def mlp_init(seed: int, dims=(196, 64, 64, 7), last_scale: float = 0.1) -> np.ndarray:
+    """Initial parameters of the spawn MLP, packed as (W1, b1, W2, b2, W3, b3)
+    with W row-major [out][in]: W ~ N(0, 1/fan_in) (the last layer scaled by
+    `last_scale`, so the untrained network starts near the rule), biases 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i in range(len(dims) - 1):
+        w = rng.standard_normal((dims[i + 1], dims[i])) / math.sqrt(dims[i])
+        if i == len(dims) - 2:
+            w *= last_scale
+        parts += [w.ravel(), np.zeros(dims[i + 1])]
+    return np.concatenate(parts).astype(np.float32)
