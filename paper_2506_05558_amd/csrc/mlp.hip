@@ -471,7 +471,7 @@ gs_status gs_mlp_forward_bf16(const void *packed, const float *features, int64_t
   if (count == 0) return GS_OK;
   GS_REQUIRE(packed && features && out, "gs_mlp_forward_bf16: NULL argument");
   const int64_t groups = (count + 15) / 16;
-  const int64_t grid = std::min<int64_t>((groups + 3) / 4, 2048);
+  const int64_t grid = std::min<int64_t>((groups + 3) / 4, 4096);
   GS_LAUNCH("mlp_infer", (k_mlp_infer<FromArray, ToArray>), grid, 256, 0, (hipStream_t)stream,
             (const uint8_t *)packed, FromArray{features}, count, ToArray{out});
   return GS_OK;
@@ -491,7 +491,7 @@ gs_status gs_spawn_mlp(const gs_camera *cam, const float *image, const float *de
     return GS_ERR_CAPACITY;
   }
   const int64_t groups = (count + 15) / 16;
-  const int64_t grid = std::min<int64_t>((groups + 3) / 4, 2048);
+  const int64_t grid = std::min<int64_t>((groups + 3) / 4, 4096);
   FromImage src{image, depth, pixels, cam->width, cam->height};
   ToGaussians sink{out->log_scales, out->opacity_logits, out->sh, out->n, offset};
   GS_LAUNCH("mlp_infer", (k_mlp_infer<FromImage, ToGaussians>), grid, 256, 0, (hipStream_t)stream,

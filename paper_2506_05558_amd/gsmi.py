@@ -490,6 +490,12 @@ def spawn_rule(cam: Camera, image: torch.Tensor, depth: torch.Tensor, p_l: torch
     return out
 
 
+def spawn_init_workspace(width: int, height: int, capacity: int) -> int:
+    need = C.c_size_t()
+    _check(_lib.gs_spawn_init_workspace(width, height, capacity, C.byref(need)))
+    return int(need.value)
+
+
 def spawn_init(cam: Camera, image: torch.Tensor, depth: torch.Tensor, out: Gaussians, offset: int = 0,
                rendered: Optional[torch.Tensor] = None, sp: SpawnParams = SpawnParams(),
                mlp_packed: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> int:
@@ -499,10 +505,9 @@ def spawn_init(cam: Camera, image: torch.Tensor, depth: torch.Tensor, out: Gauss
     _require(depth, torch.float32, (H, W), "depth")
     if rendered is not None:
         _require(rendered, torch.float32, (3, H, W), "rendered")
-    need = C.c_size_t()
-    _check(_lib.gs_spawn_init_workspace(W, H, out.n - offset, C.byref(need)))
-    if ws is None or ws.numel() < need.value:
-        ws = torch.empty(int(need.value), dtype=torch.uint8, device=image.device)
+    need = spawn_init_workspace(W, H, out.n - offset)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=image.device)
     n = C.c_int64()
     _check(_lib.gs_spawn_init(C.byref(cam.c()), image.data_ptr(), depth.data_ptr(), _ptr(rendered), C.byref(sp.c()),
                               _ptr(mlp_packed), C.byref(out.c()), offset, C.byref(n), ws.data_ptr(), ws.numel(),
