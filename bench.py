@@ -139,9 +139,13 @@ def main():
     f = lambda *s, dt=torch.float32: torch.empty(s, dtype=dt, device=dev)
     frame = gsmi.Frame(f(3, H, W), f(H, W), f(H, W), f(H, W), f(H, W, dt=torch.int32))
     g_img = f(3, H, W)
-    bwd_ws = torch.empty(gsmi.render_bwd_workspace(n, sorter.capacity), dtype=torch.uint8, device=dev)
     loss_ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
     cams = [gsmi.Camera(W, H, v.fx, v.fy, v.cx, v.cy, poses[i]) for i, v in enumerate(views)]
+    # per-view buffers of the window: projections, first slots and pair gradients live until the
+    # projection adjoint, which runs once over all views
+    wviews = [gsmi.View(cams[i], gsmi.alloc_projected(n, dev), None,
+                        torch.empty(n, dtype=torch.int32, device=dev), d_pose[i]) for i in range(N_VIEWS)]
+    pbwd_ws = torch.empty(gsmi.project_bwd_views_workspace(n, N_VIEWS), dtype=torch.uint8, device=dev)
     lr = dict(means=1.6e-4 * 10, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4,
               pose=1e-4)
     state = dict(step=0)
@@ -186,21 +190,24 @@ def main():
         gsmi.zero_(dx6)
         gsmi.zero_(visible)
         gsmi.pose_from_6d(x6, poses)
-        for i, cam in enumerate(cams):
-            gsmi.project(cam, g, params, out=proj)
-            b = sorter(cam, proj)
+        gsmi.project_views(wviews, g, params)
+        for i, (cam, vw) in enumerate(zip(cams, wviews)):
+            b = sorter(cam, vw.proj, first_slot=vw.first_slot)
             fr = frame
             if count_pairs:
                 fr = gsmi.Frame(frame.image, frame.depth, frame.alpha, frame.final_t, frame.n_contrib,
                                 torch.empty((4, H, W), dtype=torch.int32, device=dev))
-            gsmi.render_fwd(cam, proj, b, params, out=fr)
+            gsmi.render_fwd(cam, vw.proj, b, params, out=fr)
             gsmi.loss_l1(fr.image, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i], loss_ws)
-            gsmi.render_bwd(cam, g, proj, b, fr, g_img, grads=grads, dL_dpose=d_pose[i], params=params, ws=bwd_ws)
-            gsmi.mark_visible(proj, visible)
+            if vw.pair_grad is None or vw.pair_grad.shape[0] < b.n_instances:
+                vw.pair_grad = torch.empty((int(b.n_instances * 1.25) + 1024, 12), dtype=torch.float32, device=dev)
+            gsmi.render_bwd_pairs(cam, vw.proj, b, fr, g_img, vw.pair_grad, params=params)
+            gsmi.mark_visible(vw.proj, visible)
             if count_pairs:
                 st = fr.stats.view(4, -1).to(torch.int64).sum(1).cpu().numpy()
                 pairs.append((int(st[0]), int(st[1]), int(st[2]), int(st[3]),
                               int(fr.n_contrib.to(torch.int64).sum()), b.n_instances))
+        gsmi.project_bwd_views(wviews, g, grads, params, ws=pbwd_ws)
         gsmi.pose_6d_bwd(x6, d_pose, dx6)
         for name in ["means", "log_scales", "quats", "opacity_logits"]:
             gsmi.adam_step(getattr(g, name), getattr(grads, name), getattr(m1, name), getattr(m2, name), lr[name],
@@ -260,11 +267,13 @@ def main():
             a = ops / t / 1e12
             return dict(bound="alu", achieved=a, peak=PEAK_VALU_TOPS, unit="Tlane-op/s", frac=a / PEAK_VALU_TOPS,
                         traffic=None)
+        # one launch of each covers the 8 views: parameters read once (236 B), per view a
+        # 76 B record + half-widths + tile count written; the adjoint reads parameters and per
+        # view 24 B (tile count, first slot, colour record) + 48 B per pair, and updates the
+        # 236 B of gradients once
         per_launch_bytes = {
-            "project": n * (236 + 56),
-            "project_bwd": n * (236 + 40 + 2 * 236 + 4),
-            "radix_scatter": None,
-            "adam": None,
+            "project": n * (236 + N_VIEWS * 76),
+            "project_bwd": n * (236 + 2 * 236 + N_VIEWS * 24) + N_VIEWS * M * 48,
         }.get(name)
         if per_launch_bytes is None:
             return None

@@ -203,6 +203,46 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
                         const float *dL_ddepth, const float *dL_dalpha, gs_gaussians *grads, double *dL_dpose,
                         double *dL_dtwist, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- several views of one window --------------------------------------
+ * The joint step renders the same Gaussians from every keyframe of the
+ * window (section 4.3).  The projection and its adjoint are bounded by the
+ * HBM traffic of the per-Gaussian parameters and gradients, so these forms
+ * take a list of views and read each Gaussian's parameters once and write
+ * its gradients once per call (up to eight views per pass; longer lists run
+ * in passes of eight).  Results equal those of the single-view calls:
+ * gs_project_views writes each view's gs_projected exactly as gs_project;
+ * gs_render_bwd_pairs + gs_project_bwd_views over one view is gs_render_bwd.
+ */
+typedef struct {
+  gs_camera cam;               /* the view's camera (pose on the device) */
+  gs_projected proj;           /* its projection: written by gs_project_views, read by the adjoint */
+  const float *pair_grad;      /* DEVICE [M][12] per-pair 2D gradients from gs_render_bwd_pairs */
+  const uint32_t *first_slot;  /* DEVICE [n] from gs_bin_sort of this view */
+  double *dL_dpose;            /* DEVICE [12] or NULL, accumulated (as gs_render_bwd) */
+  double *dL_dtwist;           /* DEVICE [6] or NULL, accumulated */
+} gs_view;                     /* HOST array of n_views */
+
+gs_status gs_project_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                           const gs_gaussians *g, void *stream);
+
+/* The compositing adjoint of one view only: writes, for every (Gaussian,
+ * tile) pair of the view's lists, its 2D gradient record (dL/d mean x, y,
+ * conic A, B, C, opacity, colour r, g, b, depth, 0, 0) into pair_grad
+ * [n_instances][12] at the pair's emission slot; arguments as gs_render_bwd. */
+gs_status gs_render_bwd_pairs(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                              const uint32_t *values, const uint32_t *slots, const uint32_t *ranges,
+                              int64_t n_instances, const float *image, const float *depth, const float *final_t,
+                              const int32_t *n_contrib, const float *dL_dimage, const float *dL_ddepth,
+                              const float *dL_dalpha, float *pair_grad, void *stream);
+
+/* The projection adjoint over n_views views: per Gaussian, the 2D gradients
+ * of its pairs in each view are chained to its parameters and summed over
+ * the views into grads (accumulated), and each view's pose gradient goes to
+ * its dL_dpose / dL_dtwist.  ws: gs_project_bwd_views_workspace(n, n_views). */
+gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *bytes);
+gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                               const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- loss, metrics and optimiser (helpers of the joint optimisation) ----
  * gs_loss_l1: over count values, sums[0] = sum |image - target|,
  * sums[1] = sum (image - target)^2 (double, DEVICE, overwritten), and if

@@ -1,9 +1,10 @@
 // Per-Gaussian EWA projection (forward) and its adjoint, including the
 // camera-pose gradient reduction.
 //
-// One lane per Gaussian; parameters are read as SoA planes (every load of a
-// wave is one contiguous 256-byte segment per plane), the pose is a uniform
-// 48-byte read.  Geometry runs in FP64: on gfx950 the FP64 vector rate
+// One lane per Gaussian and up to eight views per launch; parameters are
+// read once as SoA planes (every load of a wave is one contiguous 256-byte
+// segment per plane) and held in registers across the views, each view's
+// pose is a uniform 48-byte read.  Geometry runs in FP64: on gfx950 the FP64 vector rate
 // equals the unpacked FP32 rate, so the extra precision costs nothing in a
 // kernel bounded by HBM traffic (236 B in + 72 B out per SH-degree-3
 // Gaussian).  The adjoint runs in FP32 (hardware exp, rcp, rsqrt) with the
@@ -76,22 +77,62 @@ __device__ __forceinline__ void sh_term(int k, T x, T y, T z, T &Y, T &gx, T &gy
   }
 }
 
-struct ProjArgs {
-  int64_t n;
+// One view: camera and the per-view buffers of the forward (written) and of
+// the adjoint (read).
+struct ViewArgs {
+  const float *pose;  // [12] R row-major, t
+  float fx, fy, cx, cy, near_plane;
   int W, H;
-  double fx, fy, cx, cy, near_plane, eps2d, alpha_min, guard;
-  const float *pose;
-  const float *means, *log_scales, *quats, *opac, *sh;
   float *rec;
-  int32_t *radius, *tiles;  // radius: [2][n] (rx, ry)
+  int32_t *radius, *tiles;     // radius: [2][n] (rx, ry)
+  const float *pair_grad;      // [M][12] 2D gradients per (Gaussian, tile) pair (first 10 used)
+  const uint32_t *first_slot;  // first pair slot of each visible Gaussian
+  double *d_pose, *d_twist;    // pose-gradient outputs (accumulated), may be NULL
 };
 
-// Geometry of one Gaussian's forward: FP64 for the forward projection (the
-// render record needs a sub-1e-6-pixel mean), FP32 for the adjoint, whose
-// 2D covariance is kept well conditioned by the eps2d dilation.
+// The views of one launch share the Gaussians: their parameters are read
+// once per Gaussian and its gradients written once, whatever the number of
+// views, which is what bounds both kernels (HBM traffic per Gaussian).
+constexpr int kMaxViews = 8;
+
+struct MultiArgs {
+  int64_t n;
+  int nv;
+  float eps2d, alpha_min, guard;
+  const float *means, *log_scales, *quats, *opac, *sh;
+  float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
+  double *partials;                // [nv][gridDim.x][12] pose partial sums
+  ViewArgs v[kMaxViews];
+};
+
+// One Gaussian's parameters, loaded once for all views.
+template <int DEG>
+struct GParams {
+  static constexpr int NB = (DEG + 1) * (DEG + 1);
+  float mu[3], q[4], ls[3], logit;
+  float sh[NB * 3];  // [k][channel]
+};
+
+template <int DEG>
+__device__ __forceinline__ void load_params(const MultiArgs &m, int64_t i, GParams<DEG> &P) {
+  const int64_t n = m.n;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.mu[k] = m.means[k * n + i];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) P.q[k] = m.quats[k * n + i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.ls[k] = m.log_scales[k * n + i];
+  P.logit = m.opac[i];
+#pragma unroll
+  for (int k = 0; k < GParams<DEG>::NB * 3; ++k) P.sh[k] = m.sh[(int64_t)k * n + i];
+}
+
+// Geometry of one Gaussian in one view: FP64 for the forward projection
+// (the render record needs a sub-1e-6-pixel mean), FP32 for the adjoint,
+// whose 2D covariance is kept well conditioned by the eps2d dilation.
 template <class Real>
 struct Geo {
-  Real R[9];
+  Real R[9], t[3];
   Real p[3], iz;
   bool clx, cly;
   Real J00, J02, J11, J12;
@@ -100,14 +141,6 @@ struct Geo {
   Real T[6], TM[6];
   Real a, b, c, A, B, C;
 };
-
-template <class Real>
-__device__ __forceinline__ void load_pose(const float *pose, Real R[9], Real t[3]) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = (Real)pose[k];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) t[k] = (Real)pose[9 + k];
-}
 
 __device__ __forceinline__ double real_exp(double x) { return exp(x); }
 __device__ __forceinline__ float real_exp(float x) { return __expf(x); }
@@ -118,27 +151,32 @@ __device__ __forceinline__ float real_rcp(float x) { return __builtin_amdgcn_rcp
 
 // Camera-space point and the 2D covariance.  Returns false if culled by
 // the near plane or a non-positive determinant.
-template <class Real>
-__device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const Real mu[3], const Real t[3],
+template <class Real, int DEG>
+__device__ __forceinline__ bool geometry(const MultiArgs &m, const ViewArgs &v, const GParams<DEG> &P,
                                          Geo<Real> &f) {
-  const int64_t n = a.n;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) f.p[r] = f.R[3 * r] * mu[0] + f.R[3 * r + 1] * mu[1] + f.R[3 * r + 2] * mu[2] + t[r];
-  if (!(f.p[2] > (Real)a.near_plane)) return false;
+  for (int k = 0; k < 9; ++k) f.R[k] = (Real)v.pose[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f.t[k] = (Real)v.pose[9 + k];
+  const Real mu[3] = {(Real)P.mu[0], (Real)P.mu[1], (Real)P.mu[2]};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    f.p[r] = f.R[3 * r] * mu[0] + f.R[3 * r + 1] * mu[1] + f.R[3 * r + 2] * mu[2] + f.t[r];
+  if (!(f.p[2] > (Real)v.near_plane)) return false;
   f.iz = real_rcp(f.p[2]);
-  const Real limx = (Real)(a.guard * 0.5 * a.W / a.fx), limy = (Real)(a.guard * 0.5 * a.H / a.fy);
+  const Real limx = (Real)(m.guard * 0.5 * v.W / v.fx), limy = (Real)(m.guard * 0.5 * v.H / v.fy);
   const Real tx = f.p[0] * f.iz, ty = f.p[1] * f.iz;
   f.clx = tx < -limx || tx > limx;
   f.cly = ty < -limy || ty > limy;
   const Real xc = f.clx ? (tx < 0 ? -limx : limx) * f.p[2] : f.p[0];
   const Real yc = f.cly ? (ty < 0 ? -limy : limy) * f.p[2] : f.p[1];
-  const Real fx = (Real)a.fx, fy = (Real)a.fy;
+  const Real fx = (Real)v.fx, fy = (Real)v.fy;
   f.J00 = fx * f.iz;
   f.J11 = fy * f.iz;
   f.J02 = -fx * xc * f.iz * f.iz;
   f.J12 = -fy * yc * f.iz * f.iz;
 
-  const Real q0 = a.quats[i], q1 = a.quats[n + i], q2 = a.quats[2 * n + i], q3 = a.quats[3 * n + i];
+  const Real q0 = P.q[0], q1 = P.q[1], q2 = P.q[2], q3 = P.q[3];
   f.qinv = real_rsqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
   const Real w = q0 * f.qinv, x = q1 * f.qinv, y = q2 * f.qinv, z = q3 * f.qinv;
   f.qn[0] = w; f.qn[1] = x; f.qn[2] = y; f.qn[3] = z;
@@ -152,7 +190,7 @@ __device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const Rea
   f.Rq[7] = 2 * (y * z + w * x);
   f.Rq[8] = 1 - 2 * (x * x + y * y);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) f.s[k] = real_exp((Real)a.log_scales[k * n + i]);
+  for (int k = 0; k < 3; ++k) f.s[k] = real_exp((Real)P.ls[k]);
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -168,9 +206,9 @@ __device__ __forceinline__ bool geometry(const ProjArgs &a, int64_t i, const Rea
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       f.TM[3 * r + c] = f.T[3 * r] * f.M[c] + f.T[3 * r + 1] * f.M[3 + c] + f.T[3 * r + 2] * f.M[6 + c];
-  f.a = f.TM[0] * f.TM[0] + f.TM[1] * f.TM[1] + f.TM[2] * f.TM[2] + (Real)a.eps2d;
+  f.a = f.TM[0] * f.TM[0] + f.TM[1] * f.TM[1] + f.TM[2] * f.TM[2] + (Real)m.eps2d;
   f.b = f.TM[0] * f.TM[3] + f.TM[1] * f.TM[4] + f.TM[2] * f.TM[5];
-  f.c = f.TM[3] * f.TM[3] + f.TM[4] * f.TM[4] + f.TM[5] * f.TM[5] + (Real)a.eps2d;
+  f.c = f.TM[3] * f.TM[3] + f.TM[4] * f.TM[4] + f.TM[5] * f.TM[5] + (Real)m.eps2d;
   const Real det = f.a * f.c - f.b * f.b;
   if (!(det > 0)) return false;
   const Real idet = real_rcp(det);
@@ -193,45 +231,42 @@ __device__ __forceinline__ void view_dir(const Real R[9], const Real t[3], const
   d[2] = dz * dinv;
 }
 
+// Forward of Gaussian i in view v: render record, support half-widths, tiles.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void k_project(ProjArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= a.n) return;
-  const int64_t n = a.n;
+__device__ __forceinline__ void project_one(const MultiArgs &m, const ViewArgs &v, int64_t i,
+                                            const GParams<DEG> &P) {
+  const int64_t n = m.n;
   Geo<double> f;
-  double t[3];
-  load_pose<double>(a.pose, f.R, t);
-  const double mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
   float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, r3 = r0;
   int rx = 0, ry = 0, tiles = 0;
-  bool ok = geometry<double>(a, i, mu, t, f);
+  bool ok = geometry<double, DEG>(m, v, P, f);
   double mx = 0, my = 0, o = 0;
   if (ok) {
-    mx = a.fx * f.p[0] * f.iz + a.cx;
-    my = a.fy * f.p[1] * f.iz + a.cy;
+    mx = (double)v.fx * f.p[0] * f.iz + (double)v.cx;
+    my = (double)v.fy * f.p[1] * f.iz + (double)v.cy;
     ok = fabs(mx) < 8388608.0 && fabs(my) < 8388608.0;  // |mean| < 2^23 px
   }
   if (ok) {
-    o = 1.0 / (1.0 + exp(-(double)a.opac[i]));
-    ok = o >= a.alpha_min;
+    o = 1.0 / (1.0 + exp(-(double)P.logit));
+    ok = o >= (double)m.alpha_min;
   }
   if (ok) {
     // support: o exp(-q/2) >= alpha_min  <=>  q = d^T Sigma2^-1 d <= qmax;
     // its bounding box has half-extents sqrt(qmax a), sqrt(qmax c)
-    const double qmax = 2.0 * log(o / a.alpha_min);
+    const double qmax = 2.0 * log(o / (double)m.alpha_min);
     const double hx = sqrt(qmax * f.a), hy = sqrt(qmax * f.c);
     rx = (int)ceil(fmin(hx * (1.0 + 1e-4) + 1e-3, 4194304.0));
     ry = (int)ceil(fmin(hy * (1.0 + 1e-4) + 1e-3, 4194304.0));
+    const double mu[3] = {P.mu[0], P.mu[1], P.mu[2]};
     double d[3], dinv;
-    view_dir<double>(f.R, t, mu, d, dinv);
+    view_dir<double>(f.R, f.t, mu, d, dinv);
     double val[3] = {0.5, 0.5, 0.5};
-    constexpr int NB = (DEG + 1) * (DEG + 1);
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
+    for (int k = 0; k < GParams<DEG>::NB; ++k) {
       double Y, gx, gy, gz;
       sh_term<double>(k, d[0], d[1], d[2], Y, gx, gy, gz);
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) val[ch] += (double)a.sh[(int64_t)(k * 3 + ch) * n + i] * Y;
+      for (int ch = 0; ch < 3; ++ch) val[ch] += (double)P.sh[k * 3 + ch] * Y;
     }
     const double hxm = rint(mx), hym = rint(my);
     r0 = make_float4((float)hxm, (float)hym, (float)(mx - hxm), (float)(my - hym));
@@ -239,44 +274,50 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjArgs a) {
     r2 = make_float4((float)fmax(val[0], 0.0), (float)fmax(val[1], 0.0), (float)fmax(val[2], 0.0), (float)f.p[2]);
     r3 = make_float4((float)hx, (float)hy, 0.f, 0.f);
     int tx0, ty0, tx1, ty1;
-    if (tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), rx, ry, a.W, a.H, tx0, ty0, tx1, ty1))
+    if (tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), rx, ry, v.W, v.H, tx0, ty0, tx1, ty1))
       tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
   }
-  float4 *dst = (float4 *)(a.rec + i * GS_REC_FLOATS);
+  float4 *dst = (float4 *)(v.rec + i * GS_REC_FLOATS);
   dst[0] = r0;
   dst[1] = r1;
   dst[2] = r2;
   dst[3] = r3;
-  a.radius[i] = rx;
-  a.radius[n + i] = ry;
-  a.tiles[i] = tiles;
+  v.radius[i] = rx;
+  v.radius[n + i] = ry;
+  v.tiles[i] = tiles;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_views(MultiArgs m) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m.n) return;
+  GParams<DEG> P;
+  load_params<DEG>(m, i, P);
+  for (int v = 0; v < m.nv; ++v) project_one<DEG>(m, m.v[v], i, P);
 }
 
 // ---------------------------------------------------------------- backward
-struct BwdArgs {
-  ProjArgs p;
-  const float *pair_grad;     // [M][12] 2D gradients per (Gaussian, tile) pair (first 10 used)
-  const uint32_t *first_slot; // first pair slot of each visible Gaussian
-  float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
-  double *partials;  // [gridDim.x][12] pose partial sums
+// Gradient accumulators of one Gaussian over the views of a launch.
+template <int DEG>
+struct GAcc {
+  float gm[3], gl[3], gq[4], go;
+  float gsh[GParams<DEG>::NB * 3];
 };
 
-// Adjoint of one visible Gaussian, in FP32 (the forward decided
-// visibility; the adjoint only chains gradients).  Writes the pose terms of
-// this Gaussian into pose[12]: dL/dR (row-major) and dL/dt.
+// Adjoint of Gaussian i in one view where it is visible, in FP32 (the
+// forward decided visibility; the adjoint only chains gradients).  Adds
+// the parameter gradients to acc and writes this Gaussian's pose terms into
+// pose[12]: dL/dR (row-major) and dL/dt.
 template <int DEG>
-__device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int ntiles, float pose[12]) {
-  const ProjArgs &a = ba.p;
-  const int64_t n = a.n;
+__device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs &v, int64_t i, int ntiles,
+                                              const GParams<DEG> &P, GAcc<DEG> &acc, float pose[12]) {
   Geo<float> f;
-  float t[3];
-  load_pose<float>(a.pose, f.R, t);
-  const float mu[3] = {a.means[i], a.means[n + i], a.means[2 * n + i]};
-  geometry<float>(a, i, mu, t, f);
+  geometry<float, DEG>(m, v, P, f);
+  const float mu[3] = {P.mu[0], P.mu[1], P.mu[2]};
   // the Gaussian's pairs are contiguous: sum their 2D gradients in slot order
   float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0, g2 = g0;
   {
-    const float4 *gp4 = (const float4 *)(ba.pair_grad + (size_t)ba.first_slot[i] * 12);
+    const float4 *gp4 = (const float4 *)(v.pair_grad + (size_t)v.first_slot[i] * 12);
     for (int j = 0; j < ntiles; ++j) {
       const float4 a0 = gp4[3 * j], a1 = gp4[3 * j + 1], a2 = gp4[3 * j + 2];
       g0.x += a0.x; g0.y += a0.y; g0.z += a0.z; g0.w += a0.w;
@@ -285,9 +326,7 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
     }
   }
   // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -)
-  const float4 rgbz = *(const float4 *)(a.rec + i * GS_REC_FLOATS + 8);
-
-  float gmu[3] = {0.f, 0.f, 0.f};
+  const float4 rgbz = *(const float4 *)(v.rec + i * GS_REC_FLOATS + 8);
 
   // colour -> SH coefficients and view direction (no pose path, section 4.3).
   // A channel whose colour was clamped at 0 passes no gradient.
@@ -296,19 +335,17 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
     const float gc1 = rgbz.y > 0.f ? g1.w : 0.f;
     const float gc2 = rgbz.z > 0.f ? g2.x : 0.f;
     float d[3], dinv;
-    view_dir<float>(f.R, t, mu, d, dinv);
+    view_dir<float>(f.R, f.t, mu, d, dinv);
     float gx = 0.f, gy = 0.f, gz = 0.f;
-    constexpr int NB = (DEG + 1) * (DEG + 1);
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
+    for (int k = 0; k < GParams<DEG>::NB; ++k) {
       float Y, ax, ay, az;
       sh_term<float>(k, d[0], d[1], d[2], Y, ax, ay, az);
-      const int64_t o0 = (int64_t)(k * 3) * n + i;
-      ba.gsh[o0] += gc0 * Y;
-      ba.gsh[o0 + n] += gc1 * Y;
-      ba.gsh[o0 + 2 * n] += gc2 * Y;
+      acc.gsh[k * 3] += gc0 * Y;
+      acc.gsh[k * 3 + 1] += gc1 * Y;
+      acc.gsh[k * 3 + 2] += gc2 * Y;
       if (DEG > 0) {
-        const float wk = gc0 * a.sh[o0] + gc1 * a.sh[o0 + n] + gc2 * a.sh[o0 + 2 * n];
+        const float wk = gc0 * P.sh[k * 3] + gc1 * P.sh[k * 3 + 1] + gc2 * P.sh[k * 3 + 2];
         gx += wk * ax;
         gy += wk * ay;
         gz += wk * az;
@@ -316,15 +353,15 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
     }
     if (DEG > 0) {
       const float radial = gx * d[0] + gy * d[1] + gz * d[2];
-      gmu[0] += (gx - radial * d[0]) * dinv;
-      gmu[1] += (gy - radial * d[1]) * dinv;
-      gmu[2] += (gz - radial * d[2]) * dinv;
+      acc.gm[0] += (gx - radial * d[0]) * dinv;
+      acc.gm[1] += (gy - radial * d[1]) * dinv;
+      acc.gm[2] += (gz - radial * d[2]) * dinv;
     }
   }
 
   {
-    const float o = real_rcp(1.0f + __expf(-a.opac[i]));
-    ba.go[i] += g1.y * o * (1.0f - o);
+    const float o = real_rcp(1.0f + __expf(-P.logit));
+    acc.go += g1.y * o * (1.0f - o);
   }
 
   // conic -> Sigma2: dL/dSigma2 = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
@@ -361,7 +398,7 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
       gRq[3 * r + c] = gM * f.s[c];
       gs += gM * f.Rq[3 * r + c];
     }
-    ba.gl[c * n + i] += gs * f.s[c];
+    acc.gl[c] += gs * f.s[c];
   }
   {
     const float w = f.qn[0], x = f.qn[1], y = f.qn[2], z = f.qn[3];
@@ -372,10 +409,10 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
     const float dy = 2.0f * (x * (G1 + G3) + w * (G2 - G6) + z * (G5 + G7)) - 4.0f * y * (G0 + G8);
     const float dz = 2.0f * (w * (G3 - G1) + x * (G2 + G6) + y * (G5 + G7)) - 4.0f * z * (G0 + G4);
     const float proj = dw * w + dx * x + dy * y + dz * z;
-    ba.gq[i] += (dw - proj * w) * f.qinv;
-    ba.gq[n + i] += (dx - proj * x) * f.qinv;
-    ba.gq[2 * n + i] += (dy - proj * y) * f.qinv;
-    ba.gq[3 * n + i] += (dz - proj * z) * f.qinv;
+    acc.gq[0] += (dw - proj * w) * f.qinv;
+    acc.gq[1] += (dx - proj * x) * f.qinv;
+    acc.gq[2] += (dy - proj * y) * f.qinv;
+    acc.gq[3] += (dz - proj * z) * f.qinv;
   }
 
   // T = J R: gJ = gT R^T (entries 00, 02, 11, 12); gR from the covariance = J^T gT
@@ -385,7 +422,7 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
   const float gJ12 = gT[3] * f.R[6] + gT[4] * f.R[7] + gT[5] * f.R[8];
 
   // camera-space point: mean2d, depth and the Jacobian entries
-  const float fx = (float)a.fx, fy = (float)a.fy;
+  const float fx = v.fx, fy = v.fy;
   const float gmx = g0.x, gmy = g0.y;
   const float iz2 = f.iz * f.iz;
   float gp0 = gmx * fx * f.iz;
@@ -405,12 +442,9 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
   }
 
   // p = R mu + t
-  gmu[0] += f.R[0] * gp0 + f.R[3] * gp1 + f.R[6] * gp2;
-  gmu[1] += f.R[1] * gp0 + f.R[4] * gp1 + f.R[7] * gp2;
-  gmu[2] += f.R[2] * gp0 + f.R[5] * gp1 + f.R[8] * gp2;
-  ba.gm[i] += gmu[0];
-  ba.gm[n + i] += gmu[1];
-  ba.gm[2 * n + i] += gmu[2];
+  acc.gm[0] += f.R[0] * gp0 + f.R[3] * gp1 + f.R[6] * gp2;
+  acc.gm[1] += f.R[1] * gp0 + f.R[4] * gp1 + f.R[7] * gp2;
+  acc.gm[2] += f.R[2] * gp0 + f.R[5] * gp1 + f.R[8] * gp2;
 
   // pose: dL/dR = J^T gT (covariance) + gp mu^T; dL/dt = gp
   const float gp[3] = {gp0, gp1, gp2};
@@ -424,45 +458,82 @@ __device__ __forceinline__ void backward_one(const BwdArgs &ba, int64_t i, int n
 }
 
 template <int DEG>
-__global__ __launch_bounds__(kBlock) void k_project_bwd(BwdArgs ba, const int32_t *tiles) {
-  float term[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) term[k] = 0.f;
+__global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int nt = i < ba.p.n ? tiles[i] : 0;
-  if (nt > 0) backward_one<DEG>(ba, i, nt, term);
-  double acc[12];
+  const bool valid = i < m.n;
+  GParams<DEG> P;
+  GAcc<DEG> acc;
+  if (valid) load_params<DEG>(m, i, P);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) acc[k] = (double)term[k];
-
-  // block reduction of the 12 pose partials (fixed order: deterministic)
+  for (int k = 0; k < 3; ++k) acc.gm[k] = acc.gl[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc.gq[k] = 0.f;
+  acc.go = 0.f;
+#pragma unroll
+  for (int k = 0; k < GParams<DEG>::NB * 3; ++k) acc.gsh[k] = 0.f;
+  bool any = false;
   __shared__ double red[kBlock / 64][12];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int vi = 0; vi < m.nv; ++vi) {
+    const ViewArgs &v = m.v[vi];
+    float term[12];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    double v = acc[k];
+    for (int k = 0; k < 12; ++k) term[k] = 0.f;
+    const int nt = valid ? v.tiles[i] : 0;
+    if (nt > 0) {
+      backward_view<DEG>(m, v, i, nt, P, acc, term);
+      any = true;
+    }
+    // block reduction of this view's 12 pose partials (fixed order: deterministic)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) red[wv][k] = v;
+    for (int k = 0; k < 12; ++k) {
+      double x = (double)term[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) red[wv][k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+      double x = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) x += red[w][threadIdx.x];
+      m.partials[((int64_t)vi * gridDim.x + blockIdx.x) * 12 + threadIdx.x] = x;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x < 12) {
-    double v = 0.0;
+  if (!any) return;
+  const int64_t n = m.n;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) v += red[w][threadIdx.x];
-    ba.partials[(int64_t)blockIdx.x * 12 + threadIdx.x] = v;
+  for (int k = 0; k < 3; ++k) {
+    m.gm[k * n + i] += acc.gm[k];
+    m.gl[k * n + i] += acc.gl[k];
   }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m.gq[k * n + i] += acc.gq[k];
+  m.go[i] += acc.go;
+#pragma unroll
+  for (int k = 0; k < GParams<DEG>::NB * 3; ++k) m.gsh[(int64_t)k * n + i] += acc.gsh[k];
 }
 
-// Sum of the block partials (fixed order) into dL/d[R|t] and the left twist.
-__global__ __launch_bounds__(256) void k_pose_reduce(const double *partials, int64_t nparts, const float *pose,
-                                                     double *d_pose, double *d_twist) {
+struct PoseOut {
+  const float *pose;
+  double *d_pose, *d_twist;
+};
+struct PoseOuts {
+  PoseOut v[kMaxViews];
+};
+
+// Block v: sum of view v's block partials (fixed order) into dL/d[R|t] and
+// the left twist.
+__global__ __launch_bounds__(256) void k_pose_reduce(const double *partials, int64_t nparts, PoseOuts outs) {
+  const PoseOut &po = outs.v[blockIdx.x];
+  const double *part = partials + (int64_t)blockIdx.x * nparts * 12;
   double acc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) acc[k] = 0.0;
   for (int64_t b = threadIdx.x; b < nparts; b += 256)
 #pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] += partials[b * 12 + k];
+    for (int k = 0; k < 12; ++k) acc[k] += part[b * 12 + k];
   __shared__ double red[4][12];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -476,24 +547,24 @@ __global__ __launch_bounds__(256) void k_pose_reduce(const double *partials, int
   if (threadIdx.x != 0) return;
   double g[12];
   for (int k = 0; k < 12; ++k) g[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
-  if (d_pose)
-    for (int k = 0; k < 12; ++k) d_pose[k] += g[k];
-  if (d_twist) {
+  if (po.d_pose)
+    for (int k = 0; k < 12; ++k) po.d_pose[k] += g[k];
+  if (po.d_twist) {
     double R[9], t[3];
-    for (int k = 0; k < 9; ++k) R[k] = pose[k];
-    for (int k = 0; k < 3; ++k) t[k] = pose[9 + k];
+    for (int k = 0; k < 9; ++k) R[k] = po.pose[k];
+    for (int k = 0; k < 3; ++k) t[k] = po.pose[9 + k];
     // M = dL/dR R^T + dL/dt t^T; rho = dL/dt; phi = (M21 - M12, M02 - M20, M10 - M01)
     double M[9];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c)
         M[3 * r + c] = g[3 * r] * R[3 * c] + g[3 * r + 1] * R[3 * c + 1] + g[3 * r + 2] * R[3 * c + 2] +
                        g[9 + r] * t[c];
-    d_twist[0] += g[9];
-    d_twist[1] += g[10];
-    d_twist[2] += g[11];
-    d_twist[3] += M[7] - M[5];
-    d_twist[4] += M[2] - M[6];
-    d_twist[5] += M[3] - M[1];
+    po.d_twist[0] += g[9];
+    po.d_twist[1] += g[10];
+    po.d_twist[2] += g[11];
+    po.d_twist[3] += M[7] - M[5];
+    po.d_twist[4] += M[2] - M[6];
+    po.d_twist[5] += M[3] - M[1];
   }
 }
 
@@ -515,20 +586,73 @@ gs_status check_gaussians(const gs_gaussians *g, const char *fn) {
   return GS_OK;
 }
 
-ProjArgs make_args(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g) {
-  ProjArgs a;
-  a.n = g->n;
-  a.W = cam->width;
-  a.H = cam->height;
-  a.fx = cam->fx; a.fy = cam->fy; a.cx = cam->cx; a.cy = cam->cy;
-  a.near_plane = cam->near_plane;
-  a.eps2d = rp->eps2d;
-  a.alpha_min = rp->alpha_min;
-  a.guard = rp->guard;
-  a.pose = cam->pose;
-  a.means = g->means; a.log_scales = g->log_scales; a.quats = g->quats; a.opac = g->opacity_logits; a.sh = g->sh;
-  a.rec = nullptr; a.radius = nullptr; a.tiles = nullptr;
-  return a;
+gs_status check_params(const gs_raster_params *rp, const char *fn) {
+  GS_REQUIRE(rp, "%s: params is NULL", fn);
+  GS_REQUIRE(rp->alpha_min > 0.f && rp->alpha_min < 1.f && rp->eps2d >= 0.f && rp->guard > 0.f,
+             "%s: raster params out of range", fn);
+  return GS_OK;
+}
+
+MultiArgs multi_args(const gs_raster_params *rp, const gs_gaussians *g) {
+  MultiArgs m;
+  m.n = g->n;
+  m.nv = 0;
+  m.eps2d = rp->eps2d;
+  m.alpha_min = rp->alpha_min;
+  m.guard = rp->guard;
+  m.means = g->means; m.log_scales = g->log_scales; m.quats = g->quats; m.opac = g->opacity_logits; m.sh = g->sh;
+  m.gm = m.gl = m.gq = m.go = m.gsh = nullptr;
+  m.partials = nullptr;
+  return m;
+}
+
+ViewArgs view_args(const gs_camera *cam, const gs_projected *proj) {
+  ViewArgs v;
+  v.pose = cam->pose;
+  v.fx = cam->fx; v.fy = cam->fy; v.cx = cam->cx; v.cy = cam->cy;
+  v.near_plane = cam->near_plane;
+  v.W = cam->width;
+  v.H = cam->height;
+  v.rec = proj ? proj->rec : nullptr;
+  v.radius = proj ? proj->radius : nullptr;
+  v.tiles = proj ? proj->tiles_touched : nullptr;
+  v.pair_grad = nullptr;
+  v.first_slot = nullptr;
+  v.d_pose = v.d_twist = nullptr;
+  return v;
+}
+
+int64_t proj_blocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
+
+gs_status launch_project(const MultiArgs &m, int deg, hipStream_t s) {
+  const int64_t blocks = proj_blocks(m.n);
+  switch (deg) {
+    case 0: GS_LAUNCH("project", k_project_views<0>, blocks, kBlock, 0, s, m); break;
+    case 1: GS_LAUNCH("project", k_project_views<1>, blocks, kBlock, 0, s, m); break;
+    case 2: GS_LAUNCH("project", k_project_views<2>, blocks, kBlock, 0, s, m); break;
+    default: GS_LAUNCH("project", k_project_views<3>, blocks, kBlock, 0, s, m); break;
+  }
+  return GS_OK;
+}
+
+gs_status launch_project_bwd(const MultiArgs &m, int deg, hipStream_t s) {
+  const int64_t blocks = proj_blocks(m.n);
+  switch (deg) {
+    case 0: GS_LAUNCH("project_bwd", k_project_bwd_views<0>, blocks, kBlock, 0, s, m); break;
+    case 1: GS_LAUNCH("project_bwd", k_project_bwd_views<1>, blocks, kBlock, 0, s, m); break;
+    case 2: GS_LAUNCH("project_bwd", k_project_bwd_views<2>, blocks, kBlock, 0, s, m); break;
+    default: GS_LAUNCH("project_bwd", k_project_bwd_views<3>, blocks, kBlock, 0, s, m); break;
+  }
+  bool pose = false;
+  PoseOuts outs;
+  for (int v = 0; v < kMaxViews; ++v) {
+    outs.v[v].pose = v < m.nv ? m.v[v].pose : nullptr;
+    outs.v[v].d_pose = v < m.nv ? m.v[v].d_pose : nullptr;
+    outs.v[v].d_twist = v < m.nv ? m.v[v].d_twist : nullptr;
+    pose = pose || outs.v[v].d_pose || outs.v[v].d_twist;
+  }
+  if (pose) GS_LAUNCH("pose_reduce", k_pose_reduce, m.nv, 256, 0, s, (const double *)m.partials, blocks, outs);
+  return GS_OK;
 }
 
 }  // namespace
@@ -543,23 +667,82 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
   gs_status st = check_camera(cam, "gs_project");
   if (st != GS_OK) return st;
   if ((st = check_gaussians(g, "gs_project")) != GS_OK) return st;
-  GS_REQUIRE(rp, "gs_project: params is NULL");
-  GS_REQUIRE(rp->alpha_min > 0.f && rp->alpha_min < 1.f && rp->eps2d >= 0.f && rp->guard > 0.f,
-             "gs_project: raster params out of range");
+  if ((st = check_params(rp, "gs_project")) != GS_OK) return st;
   GS_REQUIRE(out, "gs_project: output struct is NULL");
   if (g->n == 0) return GS_OK;
   GS_REQUIRE(out->rec && out->radius && out->tiles_touched, "gs_project: NULL output plane");
-  ProjArgs a = make_args(cam, rp, g);
-  a.rec = out->rec;
-  a.radius = out->radius;
-  a.tiles = out->tiles_touched;
-  const int64_t blocks = (g->n + kBlock - 1) / kBlock;
-  hipStream_t s = (hipStream_t)stream;
-  switch (g->sh_degree) {
-    case 0: GS_LAUNCH("project", k_project<0>, blocks, kBlock, 0, s, a); break;
-    case 1: GS_LAUNCH("project", k_project<1>, blocks, kBlock, 0, s, a); break;
-    case 2: GS_LAUNCH("project", k_project<2>, blocks, kBlock, 0, s, a); break;
-    default: GS_LAUNCH("project", k_project<3>, blocks, kBlock, 0, s, a); break;
+  MultiArgs m = multi_args(rp, g);
+  m.nv = 1;
+  m.v[0] = view_args(cam, out);
+  return launch_project(m, g->sh_degree, (hipStream_t)stream);
+}
+
+gs_status gs_project_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                           const gs_gaussians *g, void *stream) {
+  GS_REQUIRE(n_views >= 0 && (n_views == 0 || views), "gs_project_views: bad view list");
+  gs_status st = check_gaussians(g, "gs_project_views");
+  if (st != GS_OK) return st;
+  if ((st = check_params(rp, "gs_project_views")) != GS_OK) return st;
+  for (int v = 0; v < n_views; ++v) {
+    if ((st = check_camera(&views[v].cam, "gs_project_views")) != GS_OK) return st;
+    if (g->n > 0)
+      GS_REQUIRE(views[v].proj.rec && views[v].proj.radius && views[v].proj.tiles_touched,
+                 "gs_project_views: view %d has a NULL output plane", v);
+  }
+  if (g->n == 0) return GS_OK;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
+    MultiArgs m = multi_args(rp, g);
+    m.nv = std::min(kMaxViews, n_views - v0);
+    for (int k = 0; k < m.nv; ++k) m.v[k] = view_args(&views[v0 + k].cam, &views[v0 + k].proj);
+    if ((st = launch_project(m, g->sh_degree, (hipStream_t)stream)) != GS_OK) return st;
+  }
+  return GS_OK;
+}
+
+gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *bytes) {
+  GS_REQUIRE(bytes && n >= 0 && n_views >= 0, "gs_project_bwd_views_workspace: bad argument");
+  const int64_t blocks = proj_blocks(n);
+  const int nv = std::max(1, std::min(kMaxViews, (int)n_views));
+  *bytes = align_up(sizeof(double) * 12 * (size_t)nv * (size_t)(blocks > 0 ? blocks : 1));
+  return GS_OK;
+}
+
+gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                               const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream) {
+  GS_REQUIRE(n_views >= 0 && (n_views == 0 || views), "gs_project_bwd_views: bad view list");
+  gs_status st = check_gaussians(g, "gs_project_bwd_views");
+  if (st != GS_OK) return st;
+  if ((st = check_gaussians(grads, "gs_project_bwd_views(grads)")) != GS_OK) return st;
+  GS_REQUIRE(grads->n == g->n && grads->sh_degree == g->sh_degree, "gs_project_bwd_views: grads shape differs");
+  if ((st = check_params(rp, "gs_project_bwd_views")) != GS_OK) return st;
+  for (int v = 0; v < n_views; ++v) {
+    if ((st = check_camera(&views[v].cam, "gs_project_bwd_views")) != GS_OK) return st;
+    if (g->n > 0)
+      GS_REQUIRE(views[v].proj.rec && views[v].proj.tiles_touched && views[v].first_slot && views[v].pair_grad,
+                 "gs_project_bwd_views: view %d has a NULL input", v);
+  }
+  size_t need = 0;
+  gs_project_bwd_views_workspace(g->n, n_views, &need);
+  if (ws_bytes < need || !ws) {
+    set_error("gs_project_bwd_views: workspace %zu bytes < %zu", ws_bytes, need);
+    return GS_ERR_WORKSPACE;
+  }
+  if (g->n == 0) return GS_OK;
+  for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
+    MultiArgs m = multi_args(rp, g);
+    m.gm = grads->means; m.gl = grads->log_scales; m.gq = grads->quats; m.go = grads->opacity_logits;
+    m.gsh = grads->sh;
+    m.partials = (double *)ws;
+    m.nv = std::min(kMaxViews, n_views - v0);
+    for (int k = 0; k < m.nv; ++k) {
+      const gs_view &gv = views[v0 + k];
+      m.v[k] = view_args(&gv.cam, &gv.proj);
+      m.v[k].pair_grad = gv.pair_grad;
+      m.v[k].first_slot = gv.first_slot;
+      m.v[k].d_pose = gv.dL_dpose;
+      m.v[k].d_twist = gv.dL_dtwist;
+    }
+    if ((st = launch_project_bwd(m, g->sh_degree, (hipStream_t)stream)) != GS_OK) return st;
   }
   return GS_OK;
 }
@@ -567,38 +750,6 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
 }  // extern "C"
 
 namespace gsmi {
-
-size_t project_bwd_workspace(int64_t n) {
-  const int64_t blocks = (n + kBlock - 1) / kBlock;
-  return align_up(sizeof(double) * 12 * (size_t)(blocks > 0 ? blocks : 1));
-}
-
-gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
-                      const gs_projected *proj, const float *pair_grad, const uint32_t *first_slot,
-                      gs_gaussians *grads, double *d_pose, double *d_twist, void *ws, hipStream_t s) {
-  if (g->n == 0) return GS_OK;
-  BwdArgs ba;
-  ba.p = make_args(cam, rp, g);
-  ba.p.rec = proj->rec;
-  ba.pair_grad = pair_grad;
-  ba.first_slot = first_slot;
-  ba.gm = grads->means;
-  ba.gl = grads->log_scales;
-  ba.gq = grads->quats;
-  ba.go = grads->opacity_logits;
-  ba.gsh = grads->sh;
-  ba.partials = (double *)ws;
-  const int64_t blocks = (g->n + kBlock - 1) / kBlock;
-  switch (g->sh_degree) {
-    case 0: GS_LAUNCH("project_bwd", k_project_bwd<0>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
-    case 1: GS_LAUNCH("project_bwd", k_project_bwd<1>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
-    case 2: GS_LAUNCH("project_bwd", k_project_bwd<2>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
-    default: GS_LAUNCH("project_bwd", k_project_bwd<3>, blocks, kBlock, 0, s, ba, proj->tiles_touched); break;
-  }
-  if (d_pose || d_twist)
-    GS_LAUNCH("pose_reduce", k_pose_reduce, 1, 256, 0, s, (const double *)ws, blocks, cam->pose, d_pose, d_twist);
-  return GS_OK;
-}
 
 gs_status validate_camera(const gs_camera *cam, const char *fn) { return check_camera(cam, fn); }
 gs_status validate_gaussians(const gs_gaussians *g, const char *fn) { return check_gaussians(g, fn); }

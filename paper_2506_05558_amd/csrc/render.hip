@@ -399,10 +399,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
 
 gs_status validate_camera(const gs_camera *cam, const char *fn);
 gs_status validate_gaussians(const gs_gaussians *g, const char *fn);
-size_t project_bwd_workspace(int64_t n);
-gs_status project_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,
-                      const gs_projected *proj, const float *pair_grad, const uint32_t *first_slot,
-                      gs_gaussians *grads, double *d_pose, double *d_twist, void *ws, hipStream_t s);
 
 static RenderArgs render_args(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                               const uint32_t *values, const uint32_t *ranges) {
@@ -449,9 +445,28 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
   return GS_OK;
 }
 
+gs_status gs_render_bwd_pairs(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                              const uint32_t *values, const uint32_t *slots, const uint32_t *ranges,
+                              int64_t n_instances, const float *image, const float *depth, const float *final_t,
+                              const int32_t *n_contrib, const float *dL_dimage, const float *dL_ddepth,
+                              const float *dL_dalpha, float *pair_grad, void *stream) {
+  gs_status st = validate_camera(cam, "gs_render_bwd_pairs");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(rp && proj && ranges && image && depth && final_t && n_contrib && dL_dimage,
+             "gs_render_bwd_pairs: NULL argument");
+  GS_REQUIRE(n_instances >= 0, "gs_render_bwd_pairs: n_instances < 0");
+  if (n_instances > 0) GS_REQUIRE(values && slots && pair_grad, "gs_render_bwd_pairs: NULL list argument");
+  RenderArgs a = render_args(cam, rp, proj, values, ranges);
+  BwdIn bi{image, depth, final_t, n_contrib, dL_dimage, dL_ddepth, dL_dalpha, slots, pair_grad};
+  GS_LAUNCH("render_bwd", k_render_bwd, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, bi);
+  return GS_OK;
+}
+
 gs_status gs_render_bwd_workspace(int64_t n, int64_t n_instances, size_t *bytes) {
   GS_REQUIRE(bytes && n >= 0 && n_instances >= 0, "gs_render_bwd_workspace: bad argument");
-  *bytes = align_up(sizeof(float) * 12 * (size_t)n_instances) + project_bwd_workspace(n);
+  size_t pose = 0;
+  gs_project_bwd_views_workspace(n, 1, &pose);
+  *bytes = align_up(sizeof(float) * 12 * (size_t)n_instances) + pose;
   return GS_OK;
 }
 
@@ -476,14 +491,26 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
     set_error("gs_render_bwd: workspace %zu bytes < %zu", ws_bytes, need);
     return GS_ERR_WORKSPACE;
   }
-  hipStream_t s = (hipStream_t)stream;
   Carve cv(ws);
   float *pair_grad = cv.take<float>(12 * (size_t)n_instances);
-  void *pose_ws = cv.take<char>(project_bwd_workspace(g->n));
-  RenderArgs a = render_args(cam, rp, proj, values, ranges);
-  BwdIn bi{image, depth, final_t, n_contrib, dL_dimage, dL_ddepth, dL_dalpha, slots, pair_grad};
-  GS_LAUNCH("render_bwd", k_render_bwd, padded_grid(a.ntiles), 256, 0, s, a, bi);
-  return project_bwd(cam, rp, g, proj, pair_grad, first_slot, grads, dL_dpose, dL_dtwist, pose_ws, s);
+  size_t pose_bytes = 0;
+  gs_project_bwd_views_workspace(g->n, 1, &pose_bytes);
+  void *pose_ws = cv.take<char>(pose_bytes);
+  if ((st = gs_render_bwd_pairs(cam, rp, proj, values, slots, ranges, n_instances, image, depth, final_t,
+                                n_contrib, dL_dimage, dL_ddepth, dL_dalpha, pair_grad, stream)) != GS_OK)
+    return st;
+  if (g->n == 0) return GS_OK;
+  gs_view view;
+  view.cam = *cam;
+  view.proj = *proj;
+  view.pair_grad = pair_grad;
+  view.first_slot = first_slot;
+  view.dL_dpose = dL_dpose;
+  view.dL_dtwist = dL_dtwist;
+  static const uint32_t kNoSlot = 0;
+  if (n_instances == 0) view.first_slot = &kNoSlot;  // never read: no Gaussian touches a tile
+  if (n_instances == 0) view.pair_grad = (const float *)&kNoSlot;
+  return gs_project_bwd_views(1, &view, rp, g, grads, pose_ws, pose_bytes, stream);
 }
 
 }  // extern "C"

@@ -56,6 +56,11 @@ class _Proj(C.Structure):
     _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles_touched", C.c_void_p)]
 
 
+class _View(C.Structure):
+    _fields_ = [("cam", _Camera), ("proj", _Proj), ("pair_grad", C.c_void_p), ("first_slot", C.c_void_p),
+                ("dL_dpose", C.c_void_p), ("dL_dtwist", C.c_void_p)]
+
+
 class _SpawnParams(C.Structure):
     _fields_ = [("sigma", C.c_float), ("mode", C.c_int32), ("k", C.c_int64), ("seed", C.c_uint64),
                 ("opacity", C.c_float), ("min_prob", C.c_float)]
@@ -75,6 +80,11 @@ _sig = {
     "gs_render_bwd_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
     "gs_render_bwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp, _vp, _vp, _vp, _i64, _vp,
                                 _vp, _vp, _vp, _vp, _vp, _vp, _P(_Gauss), _vp, _vp, _vp, _sz, _vp]),
+    "gs_project_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _vp]),
+    "gs_render_bwd_pairs": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, _vp, _vp]),
+    "gs_project_bwd_views_workspace": (C.c_int, [_i64, _i32, _P(_sz)]),
+    "gs_project_bwd_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
     "gs_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _i64, _vp]),
@@ -273,7 +283,9 @@ class BinSorter:
                           first_slot=torch.empty(max(n, 1), dtype=torch.int32, device=dev))
         self._key = (n, T, self.capacity)
 
-    def __call__(self, cam: Camera, proj: Projected) -> Binned:
+    def __call__(self, cam: Camera, proj: Projected, first_slot: Optional[torch.Tensor] = None) -> Binned:
+        """first_slot: an (N,) int32 tensor of the caller's to receive the first
+        slots (kept per view by a multi-view adjoint); default: a held buffer."""
         n = int(proj.tiles_touched.shape[0])
         T = cam.tiles_x * cam.tiles_y
         dev = proj.rec.device
@@ -281,16 +293,19 @@ class BinSorter:
             if self._key != (n, T, self.capacity) or self._bufs is None:
                 self._alloc(n, T, dev)
             b = self._bufs
+            fs = b["first_slot"] if first_slot is None else first_slot
+            if first_slot is not None:
+                _require(first_slot, torch.int32, (n,), "first_slot")
             m = C.c_int64()
             st = _lib.gs_bin_sort(C.byref(cam.c()), C.byref(proj.c()), n, self.capacity, b["ws"].data_ptr(),
                                   b["ws"].numel(), b["tile_ids"].data_ptr(), b["values"].data_ptr(),
-                                  b["slots"].data_ptr(), b["ranges"].data_ptr(), b["first_slot"].data_ptr(),
-                                  C.byref(m), _stream())
+                                  b["slots"].data_ptr(), b["ranges"].data_ptr(), fs.data_ptr(), C.byref(m),
+                                  _stream())
             if st == GS_ERR_CAPACITY:
                 self.capacity = int(m.value * self.growth) + 1024
                 continue
             _check(st)
-            return Binned(b["tile_ids"], b["values"], b["slots"], b["ranges"], b["first_slot"], int(m.value))
+            return Binned(b["tile_ids"], b["values"], b["slots"], b["ranges"], fs, int(m.value))
         raise GsError(GS_ERR_CAPACITY, "bin_sort: capacity did not converge")
 
 
@@ -360,6 +375,68 @@ def render_bwd(cam: Camera, g: Gaussians, proj: Projected, binned: Binned, frame
                               frame.depth.data_ptr(), frame.final_t.data_ptr(), frame.n_contrib.data_ptr(),
                               dL_dimage.data_ptr(), _ptr(dL_ddepth), _ptr(dL_dalpha), C.byref(grads.c()),
                               _ptr(dL_dpose), _ptr(dL_dtwist), ws.data_ptr(), ws.numel(), _stream()))
+    return grads
+
+
+# -------------------------------------------------------- several views
+@dataclass
+class View:
+    """One view of a window: its camera, its projection buffers, and the
+    adjoint's per-view inputs (pair gradients, first slots) and outputs."""
+    cam: Camera
+    proj: Projected
+    pair_grad: Optional[torch.Tensor] = None  # (capacity, 12) float32
+    first_slot: Optional[torch.Tensor] = None  # (N,) int32
+    dL_dpose: Optional[torch.Tensor] = None  # (12,) float64
+    dL_dtwist: Optional[torch.Tensor] = None  # (6,) float64
+
+    def c(self):
+        return _View(self.cam.c(), self.proj.c(), _ptr(self.pair_grad), _ptr(self.first_slot), _ptr(self.dL_dpose),
+                     _ptr(self.dL_dtwist))
+
+
+def _views_c(views):
+    arr = (_View * max(len(views), 1))()
+    for k, v in enumerate(views):
+        arr[k] = v.c()
+    return arr
+
+
+def project_views(views, g: Gaussians, params: Params = Params()):
+    """Projects g into every view's proj buffers (parameters read once)."""
+    _check(_lib.gs_project_views(len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()), _stream()))
+
+
+def render_bwd_pairs(cam: Camera, proj: Projected, binned: Binned, frame: Frame, dL_dimage: torch.Tensor,
+                     pair_grad: torch.Tensor, dL_ddepth: Optional[torch.Tensor] = None,
+                     dL_dalpha: Optional[torch.Tensor] = None, params: Params = Params()):
+    """The compositing adjoint of one view into pair_grad (capacity, 12)."""
+    H, W = cam.height, cam.width
+    _require(dL_dimage, torch.float32, (3, H, W), "dL_dimage")
+    if pair_grad.shape[0] < binned.n_instances or pair_grad.dtype != torch.float32:
+        raise ValueError("pair_grad: need float32 (>= n_instances, 12)")
+    _check(_lib.gs_render_bwd_pairs(C.byref(cam.c()), C.byref(params.c()), C.byref(proj.c()),
+                                    binned.values.data_ptr(), binned.slots.data_ptr(), binned.ranges.data_ptr(),
+                                    binned.n_instances, frame.image.data_ptr(), frame.depth.data_ptr(),
+                                    frame.final_t.data_ptr(), frame.n_contrib.data_ptr(), dL_dimage.data_ptr(),
+                                    _ptr(dL_ddepth), _ptr(dL_dalpha), pair_grad.data_ptr(), _stream()))
+
+
+def project_bwd_views_workspace(n: int, n_views: int) -> int:
+    need = C.c_size_t()
+    _check(_lib.gs_project_bwd_views_workspace(n, n_views, C.byref(need)))
+    return int(need.value)
+
+
+def project_bwd_views(views, g: Gaussians, grads: Gaussians, params: Params = Params(),
+                      ws: Optional[torch.Tensor] = None):
+    """Chains every view's pair gradients to the parameters (summed over the
+    views into grads) and to each view's pose gradient."""
+    need = project_bwd_views_workspace(g.n, len(views))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.means.device)
+    _check(_lib.gs_project_bwd_views(len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()),
+                                     C.byref(grads.c()), ws.data_ptr(), ws.numel(), _stream()))
     return grads
 
 
