@@ -8,13 +8,14 @@
 // order of a stable sort of (tile << 32 | depth bits) over pairs emitted in
 // Gaussian-index order, at about a third of the key traffic.
 //
-// Radix pass layout: every wave owns a contiguous chunk of kChunk keys.  The
-// histogram kernel counts each chunk's digits; an exclusive scan over the
-// digit-major table [digit][chunk] gives every (digit, chunk) its output
-// base; the scatter kernel walks its chunk 64 keys at a time in order, finds
-// the lanes holding the same digit with one ballot per digit bit, and places
-// each key at base + running count + rank among its peers.  All of this is
-// wave-private, so the scatter needs no workgroup barriers and is stable.
+// Radix pass layout: every workgroup owns 4096 consecutive keys, each of its
+// waves a contiguous quarter.  The histogram kernel counts each block's
+// digits; an exclusive scan over the digit-major table [digit][block] gives
+// every (digit, block) its output base.  The scatter kernel ranks each
+// wave's keys in order (the lanes holding the same digit are found with one
+// ballot per digit bit), combines the waves' digit counts into block-local
+// positions, reorders the block in LDS and writes each digit's keys as one
+// contiguous run -- stable, and with coalesced stores.
 #include "common.h"
 
 namespace gsmi {
@@ -23,9 +24,10 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;  // 4096
-constexpr int kChunk = 1024;                        // keys per wave in a radix pass
 constexpr int kRadixBlock = 256;                    // 4 waves
 constexpr int kWaves = kRadixBlock / 64;
+constexpr int kWaveKeys = 1024;                     // keys per wave in a radix pass
+constexpr int kBlockKeys = kWaves * kWaveKeys;      // keys per workgroup
 
 // ------------------------------------------------------------------- scan
 template <class T>
@@ -121,77 +123,122 @@ __global__ void k_fill(T *p, int64_t count, T value) {
 
 // ------------------------------------------------------------- radix sort
 __device__ __forceinline__ uint64_t peers_of(uint32_t digit, int bits, bool valid) {
-  uint64_t peers = __ballot(valid);
+  uint64_t peers = ballot(valid);
   for (int b = 0; b < bits; ++b) {
     const bool bit = (digit >> b) & 1u;
-    const uint64_t m = __ballot(bit);
+    const uint64_t m = ballot(bit);
     peers &= bit ? m : ~m;
   }
   return peers;
 }
 
+// Pass layout: each workgroup owns kBlockKeys consecutive keys, each of its
+// four waves a contiguous quarter (kWaveKeys).  The count kernel gives the
+// digit histogram of every block, hist[digit][block]; an exclusive scan over
+// that digit-major table gives every (digit, block) its first output index.
 __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(const uint32_t *keys, const uint32_t *count_dev,
                                                             uint32_t count_max, int shift, int bits,
-                                                            int64_t nchunks, uint32_t *hist) {
+                                                            int64_t nblocks, uint32_t *hist) {
   __shared__ uint32_t cnt[kWaves][256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t chunk = (int64_t)blockIdx.x * kWaves + w;
   const int ndig = 1 << bits;
-  for (int d = lane; d < 256; d += 64) cnt[w][d] = 0;
-  if (chunk >= nchunks) return;  // wave-uniform; no workgroup barriers below
+  for (int d = lane; d < 256; d += 64) cnt[w][d] = 0;  // each wave owns its row
   const uint32_t count = count_dev ? min(*count_dev, count_max) : count_max;
-  const int64_t c0 = chunk * kChunk;
+  const int64_t c0 = (int64_t)blockIdx.x * kBlockKeys + (int64_t)w * kWaveKeys;
   const uint32_t mask = (uint32_t)ndig - 1u;
   const uint64_t lt = lanemask_lt();
-  for (int it = 0; it < kChunk / 64; ++it) {
+  for (int it = 0; it < kWaveKeys / 64; ++it) {
     const int64_t i = c0 + it * 64 + lane;
     const bool valid = i < (int64_t)count;
-    if (__ballot(valid) == 0) break;
+    if (ballot(valid) == 0) break;  // wave-uniform
     const uint32_t d = valid ? (keys[i] >> shift) & mask : 0u;
     const uint64_t peers = peers_of(d, bits, valid);
     const uint64_t higher = peers & ~(lt | (1ull << lane));
     if (valid && higher == 0) cnt[w][d] += (uint32_t)__popcll(peers);  // highest lane of the group
   }
-  for (int d = lane; d < ndig; d += 64) hist[(int64_t)d * nchunks + chunk] = cnt[w][d];
+  __syncthreads();
+  for (int d = threadIdx.x; d < ndig; d += kRadixBlock)
+    hist[(int64_t)d * nblocks + blockIdx.x] = (cnt[0][d] + cnt[1][d]) + (cnt[2][d] + cnt[3][d]);
 }
 
+// Stable scatter of one block: each wave ranks its quarter in key order with
+// ballot peer matching (rank = earlier keys of the same digit), the block
+// turns per-wave digit counts into local positions (digit-major, then wave,
+// then rank), the keys are reordered in LDS, and consecutive lanes then
+// write consecutive local positions, so each digit's keys leave as one
+// contiguous run at offsets[digit][block].
 template <bool TWO>
 __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
                                                                const uint32_t *win, uint32_t *kout, uint32_t *vout,
                                                                uint32_t *wout, const uint32_t *count_dev,
                                                                uint32_t count_max, int shift, int bits,
-                                                               int64_t nchunks, const uint32_t *offsets) {
+                                                               int64_t nblocks, const uint32_t *offsets) {
+  constexpr int kIt = kWaveKeys / 64;
   __shared__ uint32_t run[kWaves][256];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t sk[kBlockKeys];
+  __shared__ uint32_t sv[kBlockKeys];
+  __shared__ uint32_t sw[TWO ? kBlockKeys : 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t chunk = (int64_t)blockIdx.x * kWaves + w;
-  if (chunk >= nchunks) return;
   const int ndig = 1 << bits;
-  for (int d = lane; d < ndig; d += 64) run[w][d] = offsets[(int64_t)d * nchunks + chunk];
-  const uint32_t count = count_dev ? min(*count_dev, count_max) : count_max;
-  const int64_t c0 = chunk * kChunk;
   const uint32_t mask = (uint32_t)ndig - 1u;
+  for (int d = lane; d < 256; d += 64) run[w][d] = 0;
+  const uint32_t count = count_dev ? min(*count_dev, count_max) : count_max;
+  const int64_t b0 = (int64_t)blockIdx.x * kBlockKeys;
+  const int64_t c0 = b0 + (int64_t)w * kWaveKeys;
   const uint64_t lt = lanemask_lt();
-  for (int it = 0; it < kChunk / 64; ++it) {
+  uint32_t key[kIt], val[kIt], val2[kIt], rk[kIt];
+#pragma unroll
+  for (int it = 0; it < kIt; ++it) {
     const int64_t i = c0 + it * 64 + lane;
     const bool valid = i < (int64_t)count;
-    if (__ballot(valid) == 0) break;
-    uint32_t key = 0, val = 0, val2 = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-      if (TWO) val2 = win[i];
-    }
-    const uint32_t d = (key >> shift) & mask;
+    key[it] = valid ? kin[i] : 0u;
+    val[it] = valid ? vin[i] : 0u;
+    val2[it] = (TWO && valid) ? win[i] : 0u;
+    const uint32_t d = (key[it] >> shift) & mask;
     const uint64_t peers = peers_of(d, bits, valid);
+    rk[it] = 0xffffffffu;
     if (valid) {
       const uint32_t base = run[w][d];
-      const uint32_t pos = base + (uint32_t)__popcll(peers & lt);
-      kout[pos] = key;
-      vout[pos] = val;
-      if (TWO) wout[pos] = val2;
+      rk[it] = (base + (uint32_t)__popcll(peers & lt)) | (d << 16);  // rank < 2^16
       const uint64_t higher = peers & ~(lt | (1ull << lane));
       if (higher == 0) run[w][d] = base + (uint32_t)__popcll(peers);
     }
+  }
+  __syncthreads();
+  // local digit starts (exclusive scan of the block's digit totals) and the
+  // per-wave starts within each digit; run[] turns into local positions
+  {
+    const int d = threadIdx.x;  // one digit per lane (kRadixBlock == 256)
+    const uint32_t n0 = run[0][d], n1 = run[1][d], n2 = run[2][d], n3 = run[3][d];
+    uint32_t tot;
+    const uint32_t start = block_excl_scan<uint32_t>(n0 + n1 + n2 + n3, &tot);
+    gbase[d] = (d < ndig ? offsets[(int64_t)d * nblocks + blockIdx.x] : 0u) - start;
+    __syncthreads();
+    run[0][d] = start;
+    run[1][d] = start + n0;
+    run[2][d] = start + n0 + n1;
+    run[3][d] = start + n0 + n1 + n2;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < kIt; ++it) {
+    if (rk[it] != 0xffffffffu) {
+      const uint32_t lp = run[w][rk[it] >> 16] + (rk[it] & 0xffffu);
+      sk[lp] = key[it];
+      sv[lp] = val[it];
+      if (TWO) sw[lp] = val2[it];
+    }
+  }
+  __syncthreads();
+  const int64_t nvalid64 = (int64_t)count - b0;
+  const int nvalid = nvalid64 <= 0 ? 0 : (nvalid64 >= kBlockKeys ? kBlockKeys : (int)nvalid64);
+  for (int idx = threadIdx.x; idx < nvalid; idx += kRadixBlock) {
+    const uint32_t k = sk[idx];
+    const uint32_t pos = gbase[(k >> shift) & mask] + (uint32_t)idx;
+    kout[pos] = k;
+    vout[pos] = sv[idx];
+    if (TWO) wout[pos] = sw[idx];
   }
 }
 
@@ -201,13 +248,20 @@ __global__ void k_visible_flags(const int32_t *tiles, int64_t n, uint32_t *flags
   if (i < n) flags[i] = tiles[i] > 0 ? 1u : 0u;
 }
 
-__global__ void k_compact(const uint32_t *flags, const uint32_t *pos, const float *rec, int64_t n, uint32_t *keys,
-                          uint32_t *vals) {
+// Visible Gaussians in index order: depth key, index, and the tile rect
+// packed as (tx0 | ty0 << 16, tx1 | ty1 << 16) for the pair emission, which
+// then gathers 8 bytes per Gaussian instead of a record and two radii.
+__global__ void k_compact(const uint32_t *flags, const uint32_t *pos, const float *rec, const int32_t *radius,
+                          int64_t n, int W, int H, uint32_t *keys, uint32_t *vals, uint2 *rect) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !flags[i]) return;
   const uint32_t p = pos[i];
+  const float4 r0 = *(const float4 *)(rec + i * GS_REC_FLOATS);
   keys[p] = __float_as_uint(rec[i * GS_REC_FLOATS + 11]);  // depth > 0: bits order like values
   vals[p] = (uint32_t)i;
+  int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
+  tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[i], radius[n + i], W, H, tx0, ty0, tx1, ty1);
+  rect[i] = make_uint2((uint32_t)tx0 | (uint32_t)ty0 << 16, (uint32_t)tx1 | (uint32_t)ty1 << 16);
 }
 
 __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev, const int32_t *tiles, int64_t n,
@@ -220,18 +274,15 @@ __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev
 // Emits the pairs of the j-th Gaussian in depth order at its offset: tile
 // id, Gaussian index and the pair's emission index ("slot"); the pairs of a
 // Gaussian occupy slots [first_slot[g], first_slot[g] + tiles_touched[g]).
-__global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const float *rec,
-                            const int32_t *radius, int64_t n, int W, int H, int tiles_x, uint32_t capacity,
-                            uint32_t *tile_keys, uint32_t *vals, uint32_t *slots, uint32_t *first_slot) {
+__global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const uint2 *rect,
+                            int tiles_x, uint32_t capacity, uint32_t *tile_keys, uint32_t *vals, uint32_t *slots,
+                            uint32_t *first_slot) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= (int64_t)*count_dev) return;
   const uint32_t g = order[j];
   first_slot[g] = offs[j];
-  const float4 r0 = *(const float4 *)(rec + (size_t)g * GS_REC_FLOATS);
-  int tx0, ty0, tx1, ty1;
-  if (!tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[g], radius[n + g], W, H, tx0, ty0, tx1,
-                 ty1))
-    return;
+  const uint2 r = rect[g];
+  const int tx0 = (int)(r.x & 0xffffu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xffffu), ty1 = (int)(r.y >> 16);
   uint32_t o = offs[j];
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
@@ -252,7 +303,7 @@ __global__ void k_ranges(const uint32_t *tile_keys, uint32_t M, uint32_t *ranges
   if (i == (int64_t)M - 1 || tile_keys[i + 1] != t) ranges[2 * t + 1] = (uint32_t)(i + 1);
 }
 
-inline int64_t nchunks_of(int64_t count) { return (count + kChunk - 1) / kChunk; }
+inline int64_t nblocks_of(int64_t count) { return (count + kBlockKeys - 1) / kBlockKeys; }
 inline int64_t grid1(int64_t count, int block = 256) { return (count + block - 1) / block; }
 
 // Passes of at most 8 bits covering [0, total_bits), as equal as possible.
@@ -270,11 +321,11 @@ int plan_passes(int total_bits, int shifts[8], int widths[8]) {
 }
 
 struct RadixWs {
-  uint32_t *hist;  // [256][nchunks(count_max)]
+  uint32_t *hist;  // [256][nblocks(count_max)]
   void *scan_ws;
 };
 
-size_t radix_hist_elems(int64_t count_max) { return 256 * (size_t)nchunks_of(count_max); }
+size_t radix_hist_elems(int64_t count_max) { return 256 * (size_t)nblocks_of(count_max); }
 
 // Sorts (k[0], v[0]) by the given passes, ping-ponging with (k[1], v[1]).
 // Returns the index (0 or 1) of the buffer pair holding the result.
@@ -282,21 +333,20 @@ gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], uint32_t *v2[2], const uint
                      int npasses, const int *shifts, const int *widths, const RadixWs &rw, hipStream_t s,
                      int *result) {
   int cur = 0;
-  const int64_t nch = nchunks_of(count_max);
-  const int64_t blocks = (nch + kWaves - 1) / kWaves;
+  const int64_t blocks = nblocks_of(count_max);
   for (int p = 0; p < npasses; ++p) {
     if (count_max == 0) break;
     GS_LAUNCH("radix_hist", k_radix_hist, blocks, kRadixBlock, 0, s, k[cur], count_dev, (uint32_t)count_max,
-              shifts[p], widths[p], nch, rw.hist);
-    gs_status st = scan_exclusive(rw.hist, rw.hist, (int64_t)(1 << widths[p]) * nch, nullptr, rw.scan_ws, s);
+              shifts[p], widths[p], blocks, rw.hist);
+    gs_status st = scan_exclusive(rw.hist, rw.hist, (int64_t)(1 << widths[p]) * blocks, nullptr, rw.scan_ws, s);
     if (st != GS_OK) return st;
     if (v2)
       GS_LAUNCH("radix_scatter", k_radix_scatter<true>, blocks, kRadixBlock, 0, s, k[cur], v[cur], v2[cur],
-                k[1 - cur], v[1 - cur], v2[1 - cur], count_dev, (uint32_t)count_max, shifts[p], widths[p], nch,
+                k[1 - cur], v[1 - cur], v2[1 - cur], count_dev, (uint32_t)count_max, shifts[p], widths[p], blocks,
                 rw.hist);
     else
       GS_LAUNCH("radix_scatter", k_radix_scatter<false>, blocks, kRadixBlock, 0, s, k[cur], v[cur], nullptr,
-                k[1 - cur], v[1 - cur], nullptr, count_dev, (uint32_t)count_max, shifts[p], widths[p], nch,
+                k[1 - cur], v[1 - cur], nullptr, count_dev, (uint32_t)count_max, shifts[p], widths[p], blocks,
                 rw.hist);
     cur = 1 - cur;
   }
@@ -343,6 +393,7 @@ namespace {
 
 struct BinLayout {
   uint32_t *flags, *pos, *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *scalars, *ktmp, *vtmp, *stmp;
+  uint2 *rect;
   void *scan_ws;
   size_t bytes;
 };
@@ -360,6 +411,7 @@ BinLayout bin_layout(void *ws, int64_t n, int64_t capacity) {
   L.vB = cv.take<uint32_t>(nn);
   L.cnt = cv.take<uint32_t>(nn);
   L.offs = cv.take<uint32_t>(nn);
+  L.rect = cv.take<uint2>(nn);
   const int64_t big = n > capacity ? n : capacity;
   L.hist = cv.take<uint32_t>(radix_hist_elems(big));
   L.scan_ws = cv.take<char>(scan_workspace((int64_t)radix_hist_elems(big) > big ? (int64_t)radix_hist_elems(big) : big));
@@ -416,7 +468,8 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
     // 1. compact the visible Gaussians with their depth keys
     GS_LAUNCH("bin_flags", k_visible_flags, grid1(n), 256, 0, s, proj->tiles_touched, n, L.flags);
     if ((st = scan_exclusive(L.flags, L.pos, n, V, L.scan_ws, s)) != GS_OK) return st;
-    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, L.flags, L.pos, proj->rec, n, L.kA, L.vA);
+    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, L.flags, L.pos, proj->rec, proj->radius, n, W, H,
+              L.kA, L.vA, L.rect);
     // 2. stable sort by depth (31 significant bits of a positive float)
     int shifts[8], widths[8];
     const int np = plan_passes(31, shifts, widths);
@@ -450,8 +503,8 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
     kk[0] = L.ktmp; vv[0] = L.vtmp; ss[0] = L.stmp; kk[1] = tile_ids; vv[1] = values; ss[1] = slots;
   }
   const uint32_t *order = order_buf ? L.vB : L.vA;
-  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, proj->rec, proj->radius, n, W, H, tx,
-            (uint32_t)capacity, kk[0], vv[0], ss[0], first_slot);
+  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, L.rect, tx, (uint32_t)capacity,
+            kk[0], vv[0], ss[0], first_slot);
   int res = 0;
   if ((st = radix_sort(kk, vv, ss, nullptr, M, np, shifts, widths, rw, s, &res)) != GS_OK) return st;
   GS_LAUNCH("bin_ranges", k_ranges, grid1(M), 256, 0, s, tile_ids, M, ranges);
