@@ -115,6 +115,56 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, 
   }
 }
 
+// Single-workgroup exclusive scan for arrays of up to one workgroup tile
+// (8192 elements): one launch instead of three.  Longer arrays take the
+// three-kernel path: one workgroup streaming 100k+ elements is slower than
+// two extra launches.
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallItems = 8;
+constexpr int64_t kSmallScan = kSmallBlock * kSmallItems;
+
+template <class T>
+__device__ __forceinline__ T big_block_excl_scan(T x, T *total) {
+  __shared__ T wsum[kSmallBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T inc = wave_incl_scan<T>(x);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    const T v = lane < kSmallBlock / 64 ? wsum[lane] : (T)0;
+    const T vi = wave_incl_scan<T>(v);
+    if (lane < kSmallBlock / 64) wsum[lane] = vi - v;  // exclusive wave offsets
+    if (lane == kSmallBlock / 64 - 1) wsum[kSmallBlock / 64 - 1] = vi - v, *total = vi;
+  }
+  __syncthreads();
+  const T before = wsum[w];
+  __syncthreads();
+  return before + inc - x;
+}
+
+template <class T>
+__global__ __launch_bounds__(kSmallBlock) void k_scan_small(const T *in, T *out, int64_t count, T *total) {
+  __shared__ T tot;
+  T carry = 0;
+  for (int64_t base = 0; base < count; base += (int64_t)kSmallBlock * kSmallItems) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kSmallItems;
+    T v[kSmallItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+      v[k] = (i0 + k < count) ? in[i0 + k] : (T)0;
+      sum += v[k];
+    }
+    T run = carry + big_block_excl_scan<T>(sum, &tot);
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+      if (i0 + k < count) out[i0 + k] = run;
+      run += v[k];
+    }
+    carry += tot;  // tot is read after the scan's last barrier and rewritten only after the next one
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
 template <class T>
 __global__ void k_fill(T *p, int64_t count, T value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -365,6 +415,10 @@ template <class T>
 static gs_status scan_exclusive_t(const T *in, T *out, int64_t count, T *total, void *ws, hipStream_t s) {
   if (count <= 0) {
     if (total) GS_LAUNCH("fill", k_fill<T>, 1, 64, 0, s, total, 1, (T)0);
+    return GS_OK;
+  }
+  if (count <= kSmallScan) {
+    GS_LAUNCH("scan", k_scan_small<T>, 1, kSmallBlock, 0, s, in, out, count, total);
     return GS_OK;
   }
   const int64_t nparts = (count + kScanTile - 1) / kScanTile;

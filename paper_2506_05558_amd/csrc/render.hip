@@ -13,9 +13,11 @@
 //
 // The 2D Gaussian is evaluated in the log2 domain: with d = pixel - mean,
 //   s  = -(A dx^2 + 2 B dx dy + C dy^2) / 2,       alpha = o exp(s)
-//   s2 = s log2(e) = ca dx^2 + cb dx dy + cc dy^2,  exp(s) = 2^s2
-// with (ca, cb, cc) = -log2(e) (A/2, B, C/2) folded in at staging, so one
-// v_exp_f32 per pair.  The forward and the adjoint stage, cull and evaluate
+//   s2 = s log2(e) = ca dx^2 + cb dx dy + cc dy^2,  o exp(s) = 2^(s2 + log2 o)
+// with (ca, cb, cc) = -log2(e) (A/2, B, C/2) and log2 o folded in at
+// staging.  The skip test alpha >= alpha_min is taken on the exponent,
+// s2 + log2 o >= log2 alpha_min, so a pair that no pixel of the wave keeps
+// costs seven vector operations and no v_exp_f32.  The forward and the adjoint stage, cull and evaluate
 // with the same code and explicit operation order, so the adjoint retraces
 // the forward's decisions exactly.
 #include "common.h"
@@ -26,6 +28,7 @@ namespace {
 constexpr int kBatch = 256;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kFar = 1e30f;  // pixel coordinate of a stopped pixel
 
 struct RenderArgs {
   int W, H, tiles_x, ntiles;
@@ -36,7 +39,7 @@ struct RenderArgs {
 
 struct Stage {
   float4 a[kBatch];         // mean x, y relative to the tile origin, ca, cb
-  float4 b[kBatch];         // cc, opacity, depth, colour r
+  float4 b[kBatch];         // cc, log2 opacity, depth, colour r
   float2 c[kBatch];         // colour g, b
   uint8_t list[4][kBatch];  // per quadrant: batch entries whose box meets it, in order
   int cnt[4][4];            // [entry wave][quadrant] entries
@@ -57,7 +60,7 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
     const float mx = __fadd_rn(__fsub_rn(r0.x, ox), r0.z);
     const float my = __fadd_rn(__fsub_rn(r0.y, oy), r0.w);
     S.a[t] = make_float4(mx, my, __fmul_rn(-0.5f * kLog2e, r1.x), __fmul_rn(-kLog2e, r1.y));
-    S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), r1.w, r2.w, r2.x);
+    S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), __builtin_amdgcn_logf(r1.w), r2.w, r2.x);
     S.c[t] = make_float2(r2.y, r2.z);
     if (gid_out) gid_out[t] = gid;
     // support box, widened so that FP32 rounding can never cull a pixel the
@@ -73,7 +76,7 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
   int rank[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const uint64_t bal = __ballot((mask >> q) & 1u);
+    const uint64_t bal = ballot((mask >> q) & 1u);
     rank[q] = __popcll(bal & lt);
     if (lane == 0) S.cnt[ew][q] = __popcll(bal);
   }
@@ -135,20 +138,23 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
   const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
-  const float fpx = (float)P.px, fpy = (float)P.py;
+  // a pixel that has stopped (or lies outside the image) is moved far away:
+  // its exponent is then -inf and it takes nothing more
+  float fpx = P.inside ? (float)P.px : kFar;
+  const float fpy = (float)P.py;
+  const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
   __shared__ Stage S;
 
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
   int last = 0, nev = 0, nsup = 0, ncomp = 0;
   int ntile = (int)(e - s);  // tile-list entries up to and including the stop
-  bool done = !P.inside;
 
   for (uint32_t base = s; base < e; base += kBatch) {
-    if (__syncthreads_count(done) == kBatch) break;
+    if (__syncthreads_count(fpx == kFar) == kBatch) break;
     stage_batch(a, base, e, ox, oy, S, nullptr);
     const int cnt = list_count(S, w);
-    if (__ballot(!done) == 0) continue;
+    if (ballot(fpx != kFar) == 0) continue;
     const int idx0 = (int)(base - s);
     int kn = list_entry(S, w, 0);  // the next index is read one iteration ahead
     for (int i = 0; i < cnt; ++i) {
@@ -157,14 +163,14 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
       const float4 A = S.a[k];
       const float4 B = S.b[k];
       const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-      const float ex = exp2_fast(splat_s2(A.z, A.w, B.x, dx, dy));
-      const float alpha = fminf(a.alpha_max, __fmul_rn(B.y, ex));
-      if (STATS) nev += done ? 0 : 1;
-      const bool take = !done && alpha >= a.alpha_min;
-      if (__ballot(take) == 0) continue;
+      const float lg = __fadd_rn(splat_s2(A.z, A.w, B.x, dx, dy), B.y);  // log2 of o exp(s)
+      if (STATS) nev += fpx != kFar ? 1 : 0;
+      const bool take = lg >= l2min;
+      if (ballot(take) == 0) continue;
+      const float alpha = fminf(a.alpha_max, exp2_fast(lg));
       const float2 C = S.c[k];
       const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
-      const bool stop = take && Tn < a.t_min;
+      const bool stop = (take ? Tn : 1.0f) < a.t_min;
       const bool comp = take && !stop;
       const float wgt = comp ? __fmul_rn(alpha, T) : 0.0f;
       c0 = __fmaf_rn(B.w, wgt, c0);
@@ -178,9 +184,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
         ncomp += comp ? 1 : 0;
         ntile = stop ? idx0 + k + 1 : ntile;
       }
-      if (__ballot(stop) != 0) {
-        done = done || stop;
-        if (__ballot(!done) == 0) break;
+      if (ballot(stop) != 0) {
+        fpx = stop ? kFar : fpx;
+        if (ballot(fpx != kFar) == 0) break;
       }
     }
   }
@@ -217,12 +223,15 @@ __device__ __forceinline__ int wave_max(int x) {
 }
 
 constexpr int kChunk = 8;    // entries per wave handed from phase 1 to phase 2
-constexpr int kPad = kChunk + 1;  // row stride of the per-pixel chunk table (bank-conflict free)
 
+// Per-wave chunk table, slot-major with the pixel index XOR-ed by the slot:
+// phase 1 (all lanes, one slot) writes a permutation of one row, phase 2
+// (lane = slot e, row r) reads [e][(8 r + i) ^ e] with at most two lanes per
+// bank, and without padding the workgroup's LDS (39 KB) lets four tiles
+// share a compute unit.
 struct BwdShared {
-  float gs[4][64][kPad];    // per wave, pixel, chunk slot: d L / d s  (natural-log exponent)
-  float wt[4][64][kPad];    // per wave, pixel, chunk slot: blending weight alpha T
-  float G[4][4][64];        // per wave: upstream colour (3) and depth gradient per pixel
+  float gs[4][kChunk][64];  // per wave, chunk slot, pixel p ^ slot: d L / d s  (natural-log exponent)
+  float wt[4][kChunk][64];  // per wave, chunk slot, pixel p ^ slot: blending weight alpha T
   uint8_t slot[4][kChunk];  // per wave: batch entry of each chunk slot
 };
 
@@ -236,30 +245,33 @@ struct BwdShared {
 //   d alpha / d o = gs / o); sum w G_c and sum w G_depth the colour and
 //   depth gradients.
 __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, int nslots,
-                                           float (*acc)[kBatch]) {
+                                           float (*acc)[kBatch], const float (&Gr)[4][8]) {
   const int lane = threadIdx.x & 63, e = lane & 7, r = lane >> 3;
   float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
   int k = 0;
   if (e < nslots) {
     k = B.slot[w][e];
     const float4 A = S.a[k];
-    const float dy = (float)((w >> 1) * 8 + r) - A.y;  // pixels p = 8 r + i share the row r
+    // the lane's pixels p = 8 r + i share the row (dy) and have dx = x0 + i:
+    // the dx moments follow from sum gs, sum gs i and sum gs i^2
+    const float dy = (float)((w >> 1) * 8 + r) - A.y;
     const float x0 = (float)((w & 1) * 8) - A.x;
+    float mi = 0.f, mii = 0.f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int p = r * 8 + i;
-      const float gs = B.gs[w][p][e], wt = B.wt[w][p][e];
-      const float dx = x0 + (float)i;
-      const float gdx = gs * dx;
+      const float gs = B.gs[w][e][p ^ e], wt = B.wt[w][e][p ^ e];
       m0 += gs;
-      mx += gdx;
-      mxx = __fmaf_rn(gdx, dx, mxx);
-      mxy = __fmaf_rn(gdx, dy, mxy);
-      s0 = __fmaf_rn(wt, B.G[w][0][p], s0);
-      s1 = __fmaf_rn(wt, B.G[w][1][p], s1);
-      s2 = __fmaf_rn(wt, B.G[w][2][p], s2);
-      sd = __fmaf_rn(wt, B.G[w][3][p], sd);
+      mi = __fmaf_rn(gs, (float)i, mi);
+      mii = __fmaf_rn(gs, (float)(i * i), mii);
+      s0 = __fmaf_rn(wt, Gr[0][i], s0);
+      s1 = __fmaf_rn(wt, Gr[1][i], s1);
+      s2 = __fmaf_rn(wt, Gr[2][i], s2);
+      sd = __fmaf_rn(wt, Gr[3][i], sd);
     }
+    mx = __fmaf_rn(x0, m0, mi);                                // sum gs dx
+    mxx = __fmaf_rn(x0, __fmaf_rn(x0, m0, 2.0f * mi), mii);    // sum gs dx^2
+    mxy = mx * dy;
     my = m0 * dy;
     myy = my * dy;
   }
@@ -280,7 +292,7 @@ __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, 
     g[2] = -0.5f * v[3];
     g[3] = -v[4];
     g[4] = -0.5f * v[5];
-    g[5] = v[0] / Bb.y;
+    g[5] = v[0] / exp2_fast(Bb.y);  // d alpha / d o = alpha / o
     g[6] = v[6];
     g[7] = v[7];
     g[8] = v[8];
@@ -320,12 +332,19 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     GI = G0 * bi.image[pix] + G1 * bi.image[np + pix] + G2 * bi.image[2 * np + pix] + GD * bi.depth[pix];
     Tf = bi.final_t[pix];
   }
-  B.G[w][0][lane] = G0;
-  B.G[w][1][lane] = G1;
-  B.G[w][2][lane] = G2;
-  B.G[w][3][lane] = GD;
+  B.gs[w][0][lane] = G0;  // staged in the (not yet used) chunk table
+  B.gs[w][1][lane] = G1;
+  B.gs[w][2][lane] = G2;
+  B.gs[w][3][lane] = GD;
   if (t == 0) sMax = 0;
   __syncthreads();
+  // phase 2 lane (slot e, row r) sums over the pixels 8 r .. 8 r + 7 of its
+  // wave: their upstream gradients stay in registers for the whole tile
+  float Gr[4][8];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Gr[c][i] = B.gs[w][c][(lane >> 3) * 8 + i];
   const int wmax = __builtin_amdgcn_readfirstlane(wave_max(ncon));
   if (lane == 0 && wmax > 0) atomicMax(&sMax, wmax);
   __syncthreads();
@@ -336,6 +355,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   // with G . suffix_k = GI - GP_k (GP_k includes entry k).
   float T = 1.0f, GP = 0.f;
   const float GAT = GA * Tf;
+  const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
   for (uint32_t base = s; base < stop; base += kBatch) {
     __syncthreads();  // every wave is done with the previous batch's stage and accumulator
@@ -354,11 +374,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       const float4 A = S.a[k];
       const float4 Bv = S.b[k];
       const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-      const float ex = exp2_fast(splat_s2(A.z, A.w, Bv.x, dx, dy));
-      const float raw = __fmul_rn(Bv.y, ex);
+      const float lg = __fadd_rn(splat_s2(A.z, A.w, Bv.x, dx, dy), Bv.y);
+      const bool take = idx0 + k < ncon && lg >= l2min;
+      if (ballot(take) == 0) continue;
+      const float raw = exp2_fast(lg);
       const float alpha = fminf(a.alpha_max, raw);
-      const bool take = idx0 + k < ncon && alpha >= a.alpha_min;
-      if (__ballot(take) == 0) continue;
       const float2 C = S.c[k];
       const float wgt = take ? __fmul_rn(alpha, T) : 0.0f;
       const float gc = G0 * Bv.w + G1 * C.x + G2 * C.y + GD * Bv.z;
@@ -366,16 +386,16 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
       const float dalpha = T * gc + (GAT - GI + GP) * inv;
       const bool live = take && raw < a.alpha_max;  // the clamp passes no gradient
-      B.gs[w][lane][nslots] = live ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
-      B.wt[w][lane][nslots] = wgt;
+      B.gs[w][nslots][lane ^ nslots] = live ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
+      B.wt[w][nslots][lane ^ nslots] = wgt;
       if (lane == 0) B.slot[w][nslots] = (uint8_t)k;
       T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
       if (++nslots == kChunk) {
-        bwd_phase2(S, B, w, nslots, sAcc);
+        bwd_phase2(S, B, w, nslots, sAcc, Gr);
         nslots = 0;
       }
     }
-    if (nslots > 0) bwd_phase2(S, B, w, nslots, sAcc);
+    if (nslots > 0) bwd_phase2(S, B, w, nslots, sAcc, Gr);
     __syncthreads();
     // one plain store per (tile, entry): the pair's slot is owned by this tile
     if (base + t < stop) {
