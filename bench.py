@@ -120,7 +120,13 @@ def main():
 
     # ---- optimised state
     g = gsmi.Gaussians.from_arrays(start.arrays())
-    grads = g.zeros_like()
+    # gradients in one flat buffer, cleared by one launch per iteration
+    gflat = torch.zeros(sum(t.numel() for t in g.tensors()), dtype=torch.float32, device=dev)
+    parts, o = [], 0
+    for t in g.tensors():
+        parts.append(gflat[o:o + t.numel()].view(t.shape))
+        o += t.numel()
+    grads = gsmi.Gaussians(*parts)
     m1 = g.zeros_like()
     m2 = g.zeros_like()
     rng = np.random.default_rng(SEED)
@@ -150,6 +156,10 @@ def main():
               pose=1e-4)
     state = dict(step=0)
     pairs = []
+    m_seen = [0] * N_VIEWS
+    n_pairs = torch.zeros(N_VIEWS, dtype=torch.int32, device=dev)
+    n_pairs_max = torch.zeros(N_VIEWS, dtype=torch.int32, device=dev)
+    new_sorter = gsmi.BinSorter(capacity=12 * PER_VIEW * N_VIEWS)
 
     # ---- spawn state: P~ render of the new view, spawn buffer, MLP
     z = lambda *sh: torch.zeros(sh, dtype=torch.float32, device=dev)
@@ -169,30 +179,33 @@ def main():
 
     def spawn_new_frame():
         gsmi.project(cam_new, g, params, out=proj)
-        b = sorter(cam_new, proj)
+        b = new_sorter(cam_new, proj)
         fr = gsmi.Frame(rendered_new, frame.depth, frame.alpha, frame.final_t, frame.n_contrib)
         gsmi.render_fwd(cam_new, proj, b, params, out=fr)
         n_spawned.append(gsmi.spawn_init(cam_new, new_image, new_depth, spawned, 0, rendered=rendered_new, sp=sp,
                                          mlp_packed=packed, ws=spawn_ws))
 
-    def keyframe_step(iters):
+    def keyframe_step(iters, use_async=False):
         spawn_new_frame()
         for _ in range(iters):
-            step()
+            step(use_async=use_async)
         trainer.step(train_x, train_y)
 
-    def step(count_pairs=False):
+    def step(count_pairs=False, use_async=False):
         state["step"] += 1
         k = state["step"]
-        for t in grads.tensors():
-            gsmi.zero_(t)
+        gsmi.zero_(gflat)
         gsmi.zero_(d_pose)
         gsmi.zero_(dx6)
         gsmi.zero_(visible)
         gsmi.pose_from_6d(x6, poses)
         gsmi.project_views(wviews, g, params)
         for i, (cam, vw) in enumerate(zip(cams, wviews)):
-            b = sorter(cam, vw.proj, first_slot=vw.first_slot)
+            if use_async:  # no host synchronisation: the pair count stays on the device
+                b = sorter.sort_async(cam, vw.proj, n_pairs[i:i + 1], first_slot=vw.first_slot)
+            else:
+                b = sorter(cam, vw.proj, first_slot=vw.first_slot)
+                m_seen[i] = max(m_seen[i], b.n_instances)
             fr = frame
             if count_pairs:
                 fr = gsmi.Frame(frame.image, frame.depth, frame.alpha, frame.final_t, frame.n_contrib,
@@ -208,6 +221,8 @@ def main():
                 pairs.append((int(st[0]), int(st[1]), int(st[2]), int(st[3]),
                               int(fr.n_contrib.to(torch.int64).sum()), b.n_instances))
         gsmi.project_bwd_views(wviews, g, grads, params, ws=pbwd_ws)
+        if use_async:
+            torch.maximum(n_pairs_max, n_pairs, out=n_pairs_max)
         gsmi.pose_6d_bwd(x6, d_pose, dx6)
         for name in ["means", "log_scales", "quats", "opacity_logits"]:
             gsmi.adam_step(getattr(g, name), getattr(grads, name), getattr(m1, name), getattr(m2, name), lr[name],
@@ -218,28 +233,52 @@ def main():
 
     for _ in range(args.warmup):
         keyframe_step(args.iters)
+    # the timed iterations sort without host synchronisation, into lists 15 % larger than the
+    # largest pair count seen; one asynchronous keyframe step settles the buffers
+    sorter.capacity = int(max(m_seen) * 1.15) + 4096
+    keyframe_step(args.iters, use_async=True)
     torch.cuda.synchronize()
     psnr0 = [10 * math.log10(3 * H * W / float(s)) for s in sums[:, 1].cpu()]
 
+    names = ["project", "bin_flags", "bin_compact", "radix_hist", "radix_scatter", "scan", "bin_counts",
+             "bin_duplicate", "bin_ranges", "bin_fill", "render_fwd", "loss_l1", "loss_final", "render_bwd",
+             "project_bwd", "pose_reduce", "adam", "zero", "mark_visible", "pose_6d", "pose_6d_bwd",
+             "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
+
+    def read_profile():
+        out = {}
+        for name in names:
+            ms, cnt = gsmi.profile_read(name)
+            if cnt:
+                out[name] = dict(ms_total=ms, launches=cnt, ms_per_launch=ms / cnt)
+        gsmi.profile_reset()
+        return out
+
+    # timed region: HIP events bracket only the kernels whose rooflines are reported
     gsmi.profile_reset()
+    gsmi.profile_select(["render_fwd", "render_bwd", "project", "project_bwd"])
     gsmi.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        keyframe_step(args.iters)
+        keyframe_step(args.iters, use_async=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if int(n_pairs_max.max()) > sorter.capacity:
+        print(json.dumps({"error": "pair count exceeded the list capacity during the timed run",
+                          "max_pairs": int(n_pairs_max.max()), "capacity": sorter.capacity}))
+        sys.exit(3)
     gsmi.profile_enable(False)
-    kernels = {}
-    for name in ["project", "bin_flags", "bin_compact", "radix_hist", "radix_scatter", "scan", "bin_counts",
-                 "bin_duplicate", "bin_ranges", "bin_fill", "render_fwd", "loss_l1", "loss_final", "render_bwd",
-                 "project_bwd", "pose_reduce", "adam", "zero", "mark_visible", "pose_6d", "pose_6d_bwd",
-                 "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]:
-        ms, cnt = gsmi.profile_read(name)
-        if cnt:
-            kernels[name] = dict(ms_total=ms, launches=cnt, ms_per_launch=ms / cnt)
-    gsmi.profile_reset()
+    kernels = read_profile()
     psnr1 = [10 * math.log10(3 * H * W / float(s)) for s in sums[:, 1].cpu()]
+
+    # one more keyframe step (not timed) with every kernel bracketed, for the breakdown
+    gsmi.profile_select(None)
+    gsmi.profile_enable(True)
+    keyframe_step(args.iters, use_async=True)
+    torch.cuda.synchronize()
+    gsmi.profile_enable(False)
+    breakdown = read_profile()
 
     # one extra step (not timed) with pair counters for the algorithmic work
     step(count_pairs=True)
@@ -309,7 +348,7 @@ def main():
         "spawned_per_keyframe": n_spawned[-1] if n_spawned else None,
         "roofline": roofline,
         "kernel_rooflines": others,
-        "kernels_ms_per_step": {k: round(v["ms_total"] / args.steps, 4) for k, v in kernels.items()},
+        "kernels_ms_per_step": {k: round(v["ms_total"], 4) for k, v in breakdown.items()},
         "ms_per_joint_iteration": round(ms_step / args.iters, 3),
         "pairs_per_view": {"tile_list_to_stop": tile_pairs, "evaluated": evaluated, "support": support,
                            "composited": comp, "tile_list_walked_bwd": walked, "instances": M},

@@ -157,6 +157,20 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
                       size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots, uint32_t *ranges,
                       uint32_t *first_slot, int64_t *n_instances, void *stream);
 
+/* The same without any host synchronisation: the pair count M goes to
+ * *n_instances_dev (DEVICE uint32) and every later kernel reads it there.
+ * If M > capacity the lists hold an unspecified subset of the pairs (every
+ * index stays below capacity; a Gaussian whose pairs do not all fit gets
+ * first_slot 0xffffffff and no gradient) and *n_instances_dev still reports
+ * M: the caller checks it (whenever it next synchronises) and repeats the
+ * work with more capacity.  For loops whose
+ * pair counts are known to fit, e.g. the iterations of an optimisation
+ * after the first. */
+gs_status gs_bin_sort_async(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
+                            size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots,
+                            uint32_t *ranges, uint32_t *first_slot, uint32_t *n_instances_dev, void *stream);
+
+
 /* ---- gs_render_fwd ------------------------------------------------------
  * Front-to-back compositing per pixel over its tile's list: with
  * d = pixel - mean, alpha = min(alpha_max, o exp(-d^T conic d / 2));
@@ -411,6 +425,10 @@ gs_status gs_spawn_init(const gs_camera *cam, const float *image, const float *d
  * the named kernel since the last reset (synchronising on its events).
  * Not thread-safe. */
 void gs_profile_enable(int on);
+/* Restricts the bracketing to the kernels named in a comma-separated list
+ * (HOST string; NULL or "" = every kernel), so that a timed run pays for
+ * the events of the kernels it reports only. */
+void gs_profile_select(const char *names);
 void gs_profile_reset(void);
 gs_status gs_profile_read(const char *kernel, double *total_ms, int64_t *launches);
 

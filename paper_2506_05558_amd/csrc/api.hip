@@ -30,6 +30,7 @@ struct ProfRecord {
   hipEvent_t start, stop;
 };
 static bool g_prof_on = false;
+static std::vector<std::string> g_prof_sel;  // empty: every kernel
 static std::vector<ProfRecord> g_prof;
 static std::vector<hipEvent_t> g_free_events;
 
@@ -44,8 +45,15 @@ static hipEvent_t take_event() {
   return e;
 }
 
+static bool selected(const char *n) {
+  if (g_prof_sel.empty()) return true;
+  for (const auto &x : g_prof_sel)
+    if (x == n) return true;
+  return false;
+}
+
 ProfScope::ProfScope(const char *n, hipStream_t s) : name(n), stream(s), slot(-1) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || !selected(n)) return;
   ProfRecord r{n, take_event(), take_event()};
   if (!r.start || !r.stop) return;
   (void)hipEventRecord(r.start, s);
@@ -75,6 +83,21 @@ void gs_default_params(gs_raster_params *p) {
 }
 
 void gs_profile_enable(int on) { g_prof_on = on != 0; }
+
+void gs_profile_select(const char *names) {
+  g_prof_sel.clear();
+  if (!names) return;
+  std::string cur;
+  for (const char *c = names;; ++c) {
+    if (*c == ',' || *c == 0) {
+      if (!cur.empty()) g_prof_sel.push_back(cur);
+      cur.clear();
+      if (*c == 0) break;
+    } else {
+      cur.push_back(*c);
+    }
+  }
+}
 
 void gs_profile_reset(void) {
   for (auto &r : g_prof) {

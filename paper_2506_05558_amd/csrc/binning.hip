@@ -321,6 +321,8 @@ __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev
   cnt[j] = j < (int64_t)*count_dev ? (uint32_t)tiles[order[j]] : 0u;
 }
 
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
 // Emits the pairs of the j-th Gaussian in depth order at its offset: tile
 // id, Gaussian index and the pair's emission index ("slot"); the pairs of a
 // Gaussian occupy slots [first_slot[g], first_slot[g] + tiles_touched[g]).
@@ -330,10 +332,13 @@ __global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, co
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= (int64_t)*count_dev) return;
   const uint32_t g = order[j];
-  first_slot[g] = offs[j];
   const uint2 r = rect[g];
   const int tx0 = (int)(r.x & 0xffffu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xffffu), ty1 = (int)(r.y >> 16);
   uint32_t o = offs[j];
+  // a Gaussian whose pairs do not all fit (an asynchronous call short of
+  // capacity) gets no first slot: its adjoint then reads no pair
+  const uint32_t npairs = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  first_slot[g] = (uint64_t)o + npairs <= capacity ? o : kNoSlot;
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
       if (o >= capacity) return;
@@ -345,8 +350,10 @@ __global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, co
 }
 
 
-__global__ void k_ranges(const uint32_t *tile_keys, uint32_t M, uint32_t *ranges) {
+__global__ void k_ranges(const uint32_t *tile_keys, const uint32_t *count_dev, uint32_t count_max,
+                         uint32_t *ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t M = count_dev ? min(*count_dev, count_max) : count_max;
   if (i >= M) return;
   const uint32_t t = tile_keys[i];
   if (i == 0 || tile_keys[i - 1] != t) ranges[2 * t] = (uint32_t)i;
@@ -492,29 +499,33 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t *bytes) {
   return GS_OK;
 }
 
-gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
-                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots, uint32_t *ranges,
-                      uint32_t *first_slot, int64_t *n_instances, void *stream) {
-  gs_status st = validate_camera(cam, "gs_bin_sort");
+// The binning pipeline.  With n_dev == NULL the pair count M is read back
+// (one stream synchronisation) and checked against capacity before the
+// pairs are emitted; with n_dev it is left on the device (*n_dev) and every
+// later kernel takes its count from there, clamped to capacity.
+static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
+                               size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots,
+                               uint32_t *ranges, uint32_t *first_slot, int64_t *n_instances, uint32_t *n_dev,
+                               hipStream_t s, const char *fn) {
+  gs_status st = validate_camera(cam, fn);
   if (st != GS_OK) return st;
-  GS_REQUIRE(proj && ranges && n_instances, "gs_bin_sort: NULL argument");
-  GS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "gs_bin_sort: n out of range");
-  GS_REQUIRE(capacity >= 0 && capacity < (int64_t(1) << 32) - 1, "gs_bin_sort: capacity out of range");
-  if (n > 0) GS_REQUIRE(proj->rec && proj->radius && proj->tiles_touched, "gs_bin_sort: NULL projection plane");
-  if (capacity > 0) GS_REQUIRE(tile_ids && values && slots, "gs_bin_sort: NULL list output");
-  if (n > 0) GS_REQUIRE(first_slot, "gs_bin_sort: NULL first_slot");
+  GS_REQUIRE(proj && ranges && (n_instances || n_dev), "%s: NULL argument", fn);
+  GS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "%s: n out of range", fn);
+  GS_REQUIRE(capacity >= 0 && capacity < (int64_t(1) << 32) - 1, "%s: capacity out of range", fn);
+  if (n > 0) GS_REQUIRE(proj->rec && proj->radius && proj->tiles_touched, "%s: NULL projection plane", fn);
+  if (capacity > 0) GS_REQUIRE(tile_ids && values && slots, "%s: NULL list output", fn);
+  if (n > 0) GS_REQUIRE(first_slot, "%s: NULL first_slot", fn);
   size_t need = 0;
   gs_bin_sort_workspace(n, capacity, &need);
   if (ws_bytes < need || !ws) {
-    set_error("gs_bin_sort: workspace %zu bytes < %zu", ws_bytes, need);
+    set_error("%s: workspace %zu bytes < %zu", fn, ws_bytes, need);
     return GS_ERR_WORKSPACE;
   }
-  hipStream_t s = (hipStream_t)stream;
   const int W = cam->width, H = cam->height;
   const int tx = tiles_x_of(W), T = tx * tiles_y_of(H);
   BinLayout L = bin_layout(ws, n, capacity);
   RadixWs rw{L.hist, L.scan_ws};
-  uint32_t *V = L.scalars, *Mdev = L.scalars + 1;
+  uint32_t *V = L.scalars, *Mdev = n_dev ? n_dev : L.scalars + 1;
 
   uint32_t M = 0;
   int order_buf = 0;
@@ -533,16 +544,24 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
     // 3. pair offsets in depth order
     GS_LAUNCH("bin_counts", k_gather_counts, grid1(n), 256, 0, s, order, V, proj->tiles_touched, n, L.cnt);
     if ((st = scan_exclusive(L.cnt, L.offs, n, Mdev, L.scan_ws, s)) != GS_OK) return st;
-    GS_CHECK_HIP(hipMemcpyAsync(&M, Mdev, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read M");
-    GS_CHECK_HIP(hipStreamSynchronize(s), "sync M");
+    if (!n_dev) {
+      GS_CHECK_HIP(hipMemcpyAsync(&M, Mdev, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read M");
+      GS_CHECK_HIP(hipStreamSynchronize(s), "sync M");
+    }
+  } else if (n_dev) {
+    GS_LAUNCH("bin_fill", k_fill<uint32_t>, 1, 64, 0, s, n_dev, 1, 0u);
   }
-  *n_instances = M;
-  if ((int64_t)M > capacity) {
-    set_error("gs_bin_sort: %u pairs exceed capacity %lld", M, (long long)capacity);
-    return GS_ERR_CAPACITY;
+  if (!n_dev) {
+    *n_instances = M;
+    if ((int64_t)M > capacity) {
+      set_error("%s: %u pairs exceed capacity %lld", fn, M, (long long)capacity);
+      return GS_ERR_CAPACITY;
+    }
   }
   GS_LAUNCH("bin_fill", k_fill<uint32_t>, grid1(2 * (int64_t)T), 256, 0, s, ranges, 2 * (int64_t)T, 0u);
-  if (M == 0) return GS_OK;
+  // the number of pairs the later kernels size their grids for
+  const int64_t mmax = n_dev ? capacity : (int64_t)M;
+  if (n == 0 || mmax == 0) return GS_OK;
 
   // 4. emit pairs in depth order, 5. stable sort by tile, 6. ranges
   int tb = 0;
@@ -560,9 +579,25 @@ gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n,
   GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, L.rect, tx, (uint32_t)capacity,
             kk[0], vv[0], ss[0], first_slot);
   int res = 0;
-  if ((st = radix_sort(kk, vv, ss, nullptr, M, np, shifts, widths, rw, s, &res)) != GS_OK) return st;
-  GS_LAUNCH("bin_ranges", k_ranges, grid1(M), 256, 0, s, tile_ids, M, ranges);
+  const uint32_t *mcount = n_dev ? n_dev : nullptr;
+  if ((st = radix_sort(kk, vv, ss, mcount, mmax, np, shifts, widths, rw, s, &res)) != GS_OK) return st;
+  GS_LAUNCH("bin_ranges", k_ranges, grid1(mmax), 256, 0, s, tile_ids, mcount, (uint32_t)mmax, ranges);
   return GS_OK;
+}
+
+gs_status gs_bin_sort(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
+                      size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots, uint32_t *ranges,
+                      uint32_t *first_slot, int64_t *n_instances, void *stream) {
+  return bin_sort_impl(cam, proj, n, capacity, ws, ws_bytes, tile_ids, values, slots, ranges, first_slot,
+                       n_instances, nullptr, (hipStream_t)stream, "gs_bin_sort");
+}
+
+gs_status gs_bin_sort_async(const gs_camera *cam, const gs_projected *proj, int64_t n, int64_t capacity, void *ws,
+                            size_t ws_bytes, uint32_t *tile_ids, uint32_t *values, uint32_t *slots,
+                            uint32_t *ranges, uint32_t *first_slot, uint32_t *n_instances_dev, void *stream) {
+  GS_REQUIRE(n_instances_dev, "gs_bin_sort_async: NULL n_instances_dev");
+  return bin_sort_impl(cam, proj, n, capacity, ws, ws_bytes, tile_ids, values, slots, ranges, first_slot, nullptr,
+                       n_instances_dev, (hipStream_t)stream, "gs_bin_sort_async");
 }
 
 }  // extern "C"

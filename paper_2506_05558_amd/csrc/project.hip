@@ -479,7 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
     float term[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) term[k] = 0.f;
-    const int nt = valid ? v.tiles[i] : 0;
+    // no first slot: the pairs did not fit the lists (see gs_bin_sort_async)
+    const int nt = valid && v.first_slot[i] != 0xffffffffu ? v.tiles[i] : 0;
     if (nt > 0) {
       backward_view<DEG>(m, v, i, nt, P, acc, term);
       any = true;

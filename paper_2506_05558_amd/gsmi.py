@@ -75,6 +75,8 @@ _sig = {
     "gs_bin_sort_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
     "gs_bin_sort": (C.c_int, [_P(_Camera), _P(_Proj), _i64, _i64, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _P(_i64),
                               _vp]),
+    "gs_bin_sort_async": (C.c_int, [_P(_Camera), _P(_Proj), _i64, _i64, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp,
+                                    _vp]),
     "gs_render_fwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),
     "gs_render_bwd_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
@@ -112,6 +114,7 @@ _sig = {
                                 _sz, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
     "gs_profile_reset": (None, []),
+    "gs_profile_select": (None, [C.c_char_p]),
     "gs_profile_read": (C.c_int, [C.c_char_p, _P(C.c_double), _P(_i64)]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -307,6 +310,26 @@ class BinSorter:
             _check(st)
             return Binned(b["tile_ids"], b["values"], b["slots"], b["ranges"], fs, int(m.value))
         raise GsError(GS_ERR_CAPACITY, "bin_sort: capacity did not converge")
+
+
+    def sort_async(self, cam: Camera, proj: Projected, n_dev: torch.Tensor,
+                   first_slot: Optional[torch.Tensor] = None) -> Binned:
+        """gs_bin_sort_async: no host synchronisation; the pair count goes to
+        n_dev (a one-element int32 device tensor).  The lists are valid only if
+        n_dev <= self.capacity, which the caller checks later; n_instances of
+        the result is the capacity (an upper bound)."""
+        n = int(proj.tiles_touched.shape[0])
+        T = cam.tiles_x * cam.tiles_y
+        if self._key != (n, T, self.capacity) or self._bufs is None:
+            self._alloc(n, T, proj.rec.device)
+        b = self._bufs
+        fs = b["first_slot"] if first_slot is None else first_slot
+        _require(n_dev, torch.int32, (1,), "n_dev")
+        _check(_lib.gs_bin_sort_async(C.byref(cam.c()), C.byref(proj.c()), n, self.capacity, b["ws"].data_ptr(),
+                                      b["ws"].numel(), b["tile_ids"].data_ptr(), b["values"].data_ptr(),
+                                      b["slots"].data_ptr(), b["ranges"].data_ptr(), fs.data_ptr(),
+                                      n_dev.data_ptr(), _stream()))
+        return Binned(b["tile_ids"], b["values"], b["slots"], b["ranges"], fs, self.capacity)
 
 
 def bin_sort(cam: Camera, proj: Projected, sorter: Optional[BinSorter] = None) -> Binned:
@@ -673,6 +696,11 @@ class MlpTrainer:
 
 def profile_enable(on: bool = True):
     _lib.gs_profile_enable(1 if on else 0)
+
+
+def profile_select(names=None):
+    """Bracket only the named kernels (an iterable of names); None: all."""
+    _lib.gs_profile_select(None if names is None else ",".join(names).encode())
 
 
 def profile_reset():

@@ -386,3 +386,51 @@ def test_multi_view_ten_views_equal_single_view_sum():
         assert torch.allclose(dp, vs[k].dL_dpose, rtol=1e-4, atol=1e-6 * float(dp.abs().max()))
     for a, b in zip(grads.tensors(), ref.tensors()):
         assert torch.allclose(a, b, rtol=1e-4, atol=1e-6 * float(b.abs().max()))
+
+
+def test_async_sort_equals_sync_and_reports_overflow():
+    """gs_bin_sort_async gives the lists of gs_bin_sort when they fit; short
+    of capacity (forced from the host) it still reports the pair count, keeps
+    every index inside the lists, and the adjoint over the truncated lists
+    reads only complete Gaussians."""
+    gs = gc.gpu()
+    view, scene = synth.single_view(3, 320, 200, 20_000)
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj = gs.project(cam, g)
+    ref = gs.BinSorter(0)(cam, proj)
+    M = ref.n_instances
+    n_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    fs = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    b = gs.BinSorter(M + 100).sort_async(cam, proj, n_dev, first_slot=fs)
+    torch.cuda.synchronize()
+    assert int(n_dev) == M
+    for a, r in ((b.values, ref.values), (b.tile_ids, ref.tile_ids), (b.slots, ref.slots)):
+        assert torch.equal(a[:M], r[:M])
+    assert torch.equal(b.ranges, ref.ranges)
+    vis = proj.tiles_touched > 0
+    assert torch.equal(fs[vis], ref.first_slot[vis])
+
+    cap = M // 2
+    b3 = gs.BinSorter(cap).sort_async(cam, proj, n_dev, first_slot=fs)
+    torch.cuda.synchronize()
+    assert int(n_dev) == M
+    vals = b3.values[:cap].cpu().numpy().view(np.uint32)
+    slots = b3.slots[:cap].cpu().numpy().view(np.uint32)
+    rng = b3.ranges.cpu().numpy().view(np.uint32)
+    assert vals.max() < g.n and slots.max() < cap and rng.max() <= cap
+    first = fs.cpu().numpy().view(np.uint32)[vis.cpu().numpy()]
+    tiles = proj.tiles_touched.cpu().numpy()[vis.cpu().numpy()]
+    kept = first != 0xFFFFFFFF
+    assert kept.any() and (~kept).any()
+    assert (first[kept].astype(np.int64) + tiles[kept] <= cap).all()
+    frame = gs.render_fwd(cam, proj, b3)
+    gimg = torch.full((3, view.height, view.width), 1e-3, device="cuda")
+    pg = torch.zeros((cap, 12), device="cuda")
+    gs.render_bwd_pairs(cam, proj, b3, frame, gimg, pg)
+    grads = g.zeros_like()
+    vw = gs.View(cam, proj, pg, fs)
+    gs.project_bwd_views([vw], g, grads)
+    torch.cuda.synchronize()
+    dropped = np.nonzero(vis.cpu().numpy())[0][~kept]
+    assert (grads.means.cpu().numpy()[:, dropped] == 0).all()
