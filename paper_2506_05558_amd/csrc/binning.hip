@@ -73,32 +73,25 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const T *in, int64_t
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// One workgroup: exclusive scan of the partials in place, total -> *total.
+// Applies the scan to one tile.  The tile's offset is the sum of the tile
+// totals before it, which every workgroup adds up itself from the (few,
+// cached) partials -- no separate spine launch.  The last workgroup also
+// writes the grand total.
 template <class T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_spine(T *partials, int64_t nparts, T *total) {
-  T carry = 0;
-  for (int64_t base = 0; base < nparts; base += kScanTile) {
-    const int64_t i0 = base + (int64_t)threadIdx.x * kScanItems;
-    T v[kScanItems], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      v[k] = (i0 + k < nparts) ? partials[i0 + k] : (T)0;
-      sum += v[k];
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, int64_t count, const T *partials,
+                                                           T *total) {
+  __shared__ T s_off;
+  {
+    T part = 0;
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanBlock) part += partials[b];
+    T all;
+    block_excl_scan<T>(part, &all);
+    if (threadIdx.x == 0) {
+      s_off = all;
+      if (total && blockIdx.x == gridDim.x - 1) *total = all + partials[blockIdx.x];
     }
-    T tot;
-    T run = carry + block_excl_scan<T>(sum, &tot);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      if (i0 + k < nparts) partials[i0 + k] = run;
-      run += v[k];
-    }
-    carry += tot;
+    __syncthreads();
   }
-  if (threadIdx.x == 0 && total) *total = carry;
-}
-
-template <class T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, int64_t count, const T *partials) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   T v[kScanItems], sum = 0;
 #pragma unroll
@@ -107,7 +100,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, 
     sum += v[k];
   }
   T tot;
-  T run = partials[blockIdx.x] + block_excl_scan<T>(sum, &tot);
+  T run = s_off + block_excl_scan<T>(sum, &tot);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < count) out[base + k] = run;
@@ -431,8 +424,7 @@ static gs_status scan_exclusive_t(const T *in, T *out, int64_t count, T *total, 
   const int64_t nparts = (count + kScanTile - 1) / kScanTile;
   T *partials = (T *)ws;
   GS_LAUNCH("scan", k_scan_reduce<T>, nparts, kScanBlock, 0, s, in, count, partials);
-  GS_LAUNCH("scan", k_scan_spine<T>, 1, kScanBlock, 0, s, partials, nparts, total);
-  GS_LAUNCH("scan", k_scan_apply<T>, nparts, kScanBlock, 0, s, in, out, count, (const T *)partials);
+  GS_LAUNCH("scan", k_scan_apply<T>, nparts, kScanBlock, 0, s, in, out, count, (const T *)partials, total);
   return GS_OK;
 }
 

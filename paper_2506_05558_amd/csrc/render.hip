@@ -236,17 +236,18 @@ struct BwdShared {
 };
 
 // Phase 2 of the adjoint for one wave: the chunk's entries are spread over
-// the lanes as (slot e = lane & 7, pixel eighth r = lane >> 3); each lane
-// sums its 8 pixels, the eight partial sums are combined with three
-// shuffles, and the slot's lane r = 0 turns the sums into the ten 2D
-// gradients and adds them to the tile's LDS accumulator of that entry.
+// the lanes as (slot e = lane >> 3, pixel row r = lane & 7); each lane sums
+// its row's 8 pixels, the eight rows of a slot (eight adjacent lanes) are
+// combined with three in-row DPP adds, and the slot's lane r = 0 turns the
+// sums into the ten 2D gradients and adds them to the tile's LDS accumulator
+// of that entry.
 //   sum gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2 and sum gs give the mean,
 //   conic and opacity gradients (d s / d mean = (A dx + B dy, B dx + C dy),
 //   d alpha / d o = gs / o); sum w G_c and sum w G_depth the colour and
 //   depth gradients.
 __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, int nslots,
                                            float (*acc)[kBatch], const float (&Gr)[4][8]) {
-  const int lane = threadIdx.x & 63, e = lane & 7, r = lane >> 3;
+  const int lane = threadIdx.x & 63, e = lane >> 3, r = lane & 7;
   float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
   int k = 0;
   if (e < nslots) {
@@ -276,11 +277,13 @@ __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, 
     myy = my * dy;
   }
   float v[10] = {m0, mx, my, mxx, mxy, myy, s0, s1, s2, sd};
+  // sum over the 8 lanes of a slot: mirror within the half row (i + (7 - i)),
+  // then swap neighbours and pairs (quad_perm [1,0,3,2], [2,3,0,1])
 #pragma unroll
   for (int q = 0; q < 10; ++q) {
-    v[q] += __shfl_xor(v[q], 8, 64);
-    v[q] += __shfl_xor(v[q], 16, 64);
-    v[q] += __shfl_xor(v[q], 32, 64);
+    v[q] += dpp_mov<0x141, 0xf>(v[q]);
+    v[q] += dpp_mov<0xb1, 0xf>(v[q]);
+    v[q] += dpp_mov<0x4e, 0xf>(v[q]);
   }
   if (r == 0 && e < nslots) {
     const float4 A = S.a[k];
@@ -344,7 +347,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Gr[c][i] = B.gs[w][c][(lane >> 3) * 8 + i];
+    for (int i = 0; i < 8; ++i) Gr[c][i] = B.gs[w][c][(lane & 7) * 8 + i];
   const int wmax = __builtin_amdgcn_readfirstlane(wave_max(ncon));
   if (lane == 0 && wmax > 0) atomicMax(&sMax, wmax);
   __syncthreads();
