@@ -99,13 +99,15 @@ __device__ __forceinline__ float splat_s2(float ca, float cb, float cc, float dx
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// Entry i of wave w's quadrant list and the list's length: the same for
-// every lane, so they live in scalar registers and the loops stay uniform.
-__device__ __forceinline__ int list_entry(const Stage &S, int w, int i) {
-  return __builtin_amdgcn_readfirstlane((int)S.list[w][i]);
-}
+// The length of wave w's quadrant list and its entries i and i + 1 (i even,
+// one 16-bit read): the same for every lane, so they live in scalar
+// registers and the loops stay uniform.  The loops take two entries per
+// turn, so both exponents are in flight before either entry's body.
 __device__ __forceinline__ int list_count(const Stage &S, int w) {
   return __builtin_amdgcn_readfirstlane(S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w]);
+}
+__device__ __forceinline__ int list_pair(const Stage &S, int w, int i) {
+  return __builtin_amdgcn_readfirstlane((int)*(const uint16_t *)&S.list[w][i]);
 }
 
 struct Pixel {
@@ -156,17 +158,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
     const int cnt = list_count(S, w);
     if (ballot(fpx != kFar) == 0) continue;
     const int idx0 = (int)(base - s);
-    int kn = list_entry(S, w, 0);  // the next index is read one iteration ahead
-    for (int i = 0; i < cnt; ++i) {
-      const int k = kn;
-      if (i + 1 < cnt) kn = list_entry(S, w, i + 1);
-      const float4 A = S.a[k];
-      const float4 B = S.b[k];
-      const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-      const float lg = __fadd_rn(splat_s2(A.z, A.w, B.x, dx, dy), B.y);  // log2 of o exp(s)
-      if (STATS) nev += fpx != kFar ? 1 : 0;
-      const bool take = lg >= l2min;
-      if (ballot(take) == 0) continue;
+    // returns true once every pixel of the wave has stopped
+    auto body = [&](int k, const float4 &B, float lg, bool take) -> bool {
       const float alpha = fminf(a.alpha_max, exp2_fast(lg));
       const float2 C = S.c[k];
       const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
@@ -186,8 +179,27 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
       }
       if (ballot(stop) != 0) {
         fpx = stop ? kFar : fpx;
-        if (ballot(fpx != kFar) == 0) break;
+        if (ballot(fpx != kFar) == 0) return true;
       }
+      return false;
+    };
+    // two entries per turn: both exponents are evaluated before either body
+    for (int i = 0; i < cnt; i += 2) {
+      const int pr = list_pair(S, w, i);
+      const int k0 = pr & 255;
+      const int k1 = i + 1 < cnt ? pr >> 8 : k0;
+      const bool has1 = i + 1 < cnt;
+      const float4 A0 = S.a[k0], B0 = S.b[k0];
+      const float4 A1 = S.a[k1], B1 = S.b[k1];
+      const float lg0 = __fadd_rn(splat_s2(A0.z, A0.w, B0.x, __fsub_rn(fpx, A0.x), __fsub_rn(fpy, A0.y)), B0.y);
+      const float lg1 = __fadd_rn(splat_s2(A1.z, A1.w, B1.x, __fsub_rn(fpx, A1.x), __fsub_rn(fpy, A1.y)), B1.y);
+      if (STATS) nev += fpx != kFar ? 1 : 0;
+      const bool t0 = lg0 >= l2min;
+      if (ballot(t0) != 0 && body(k0, B0, lg0, t0)) break;
+      if (!has1) break;
+      if (STATS) nev += fpx != kFar ? 1 : 0;
+      const bool t1 = fpx != kFar && lg1 >= l2min;  // a pixel that stopped at k0 takes nothing more
+      if (ballot(t1) != 0 && body(k1, B1, lg1, t1)) break;
     }
   }
   if (!P.inside) return;
@@ -369,17 +381,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     const int cnt = list_count(S, w);
     const int idx0 = (int)(base - s);
     int nslots = 0;
-    int kn = list_entry(S, w, 0);  // the next index is read one iteration ahead
-    for (int i = 0; i < cnt; ++i) {
-      const int k = kn;
-      if (idx0 + k >= wmax) break;  // lists ascend: no pixel of this wave reaches further
-      if (i + 1 < cnt) kn = list_entry(S, w, i + 1);
-      const float4 A = S.a[k];
-      const float4 Bv = S.b[k];
-      const float dx = __fsub_rn(fpx, A.x), dy = __fsub_rn(fpy, A.y);
-      const float lg = __fadd_rn(splat_s2(A.z, A.w, Bv.x, dx, dy), Bv.y);
-      const bool take = idx0 + k < ncon && lg >= l2min;
-      if (ballot(take) == 0) continue;
+    auto body = [&](int k, const float4 &Bv, float lg, bool take) {
       const float raw = exp2_fast(lg);
       const float alpha = fminf(a.alpha_max, raw);
       const float2 C = S.c[k];
@@ -397,6 +399,22 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
         bwd_phase2(S, B, w, nslots, sAcc, Gr);
         nslots = 0;
       }
+    };
+    // two entries per turn: both exponents are evaluated before either body
+    for (int i = 0; i < cnt; i += 2) {
+      const int pr = list_pair(S, w, i);
+      const int k0 = pr & 255;
+      if (idx0 + k0 >= wmax) break;  // lists ascend: no pixel of this wave reaches further
+      const int k1 = i + 1 < cnt ? pr >> 8 : k0;
+      const bool has1 = i + 1 < cnt;
+      const float4 A0 = S.a[k0], B0 = S.b[k0];
+      const float4 A1 = S.a[k1], B1 = S.b[k1];
+      const float lg0 = __fadd_rn(splat_s2(A0.z, A0.w, B0.x, __fsub_rn(fpx, A0.x), __fsub_rn(fpy, A0.y)), B0.y);
+      const float lg1 = __fadd_rn(splat_s2(A1.z, A1.w, B1.x, __fsub_rn(fpx, A1.x), __fsub_rn(fpy, A1.y)), B1.y);
+      const bool t0 = idx0 + k0 < ncon && lg0 >= l2min;
+      const bool t1 = has1 && idx0 + k1 < ncon && lg1 >= l2min;
+      if (ballot(t0) != 0) body(k0, B0, lg0, t0);
+      if (ballot(t1) != 0) body(k1, B1, lg1, t1);
     }
     if (nslots > 0) bwd_phase2(S, B, w, nslots, sAcc, Gr);
     __syncthreads();
