@@ -58,12 +58,15 @@ __global__ __launch_bounds__(64) void k_loss_final(const double *partials, int n
   }
 }
 
+// Grid (plane chunks, planes): element i = plane * n_stride + j belongs to
+// Gaussian j, so the visibility test needs no division.
 __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
                                               float b1, float b2, float eps, float c1, float c2,
                                               const int32_t *visible, int64_t n_stride) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= count) return;
-  if (visible && !visible[i % n_stride]) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.y * n_stride + j;
+  if (j >= n_stride || i >= count) return;
+  if (visible && !visible[j]) return;
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.f - b1) * gi;
   const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -199,8 +202,13 @@ gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int6
   if (visible) GS_REQUIRE(n_stride > 0, "gs_adam_step: n_stride must be positive with a visibility mask");
   const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
   const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
-  GS_LAUNCH("adam", k_adam, (count + 255) / 256, 256, 0, (hipStream_t)stream, param, grad, m, v, count, lr, beta1,
-            beta2, eps, c1, c2, visible, n_stride);
+  // without a mask the whole array is one "plane"
+  const int64_t stride = visible ? n_stride : count;
+  const int64_t planes = (count + stride - 1) / stride;
+  GS_REQUIRE(planes <= 65535, "gs_adam_step: count / n_stride exceeds 65535 planes");
+  const dim3 grid((unsigned)((stride + 255) / 256), (unsigned)planes);
+  GS_LAUNCH("adam", k_adam, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, count, lr, beta1, beta2, eps, c1,
+            c2, visible, stride);
   return GS_OK;
 }
 

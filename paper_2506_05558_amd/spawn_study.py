@@ -251,7 +251,9 @@ def summarise(rows, arm, boot=2000, seed=0):
     rng = np.random.default_rng(seed)
     meds = np.array([np.median(rng.choice(r, r.size)) for _ in range(boot)])
     fin = lambda v: None if not np.isfinite(v) else round(float(v), 3)
-    return dict(median_ratio=fin(np.median(r)), ci95=[fin(np.percentile(meds, 2.5)), fin(np.percentile(meds, 97.5))],
+    # "nearest" percentiles: the medians may be infinite, which interpolation turns into NaN
+    return dict(median_ratio=fin(np.median(r)), ci95=[fin(np.percentile(meds, 2.5, method="nearest")),
+                                                      fin(np.percentile(meds, 97.5, method="nearest"))],
                 n=int(r.size), not_reached=int(sum(not x[arm]["reached"] for x in rows)),
                 median_steps=float(np.median([np.inf if x[arm]["steps"] is None else x[arm]["steps"] for x in rows])),
                 median_steps_to_final_rule=float(np.median([np.inf if x[arm]["steps_to_final_rule"] is None
