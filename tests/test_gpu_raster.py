@@ -87,7 +87,7 @@ def _check_binning(view, proj, binned):
     return M
 
 
-def _check_image(name, gpu_frame, ref, crop=None):
+def _check_image(name, gpu_frame, ref, crop=None, max_flagged=MAX_FLAGGED):
     sl = (slice(None), slice(None)) if crop is None else (slice(crop[1], crop[1] + crop[3]),
                                                             slice(crop[0], crop[0] + crop[2]))
     ok = ref["flags"] == 0
@@ -103,7 +103,7 @@ def _check_image(name, gpu_frame, ref, crop=None):
     e_t = np.abs(ft - ref["final_t"])[ok].max(initial=0)
     print(f"{name}: flagged {frac:.2e}, max err image {e_img:.2e} depth/zmax {e_dep:.2e} alpha {e_alp:.2e} "
           f"T {e_t:.2e}")
-    assert frac <= MAX_FLAGGED
+    assert frac <= max_flagged
     assert e_img <= IMG_TOL and e_dep <= IMG_TOL and e_alp <= IMG_TOL and e_t <= IMG_TOL
 
 
@@ -434,3 +434,70 @@ def test_async_sort_equals_sync_and_reports_overflow():
     torch.cuda.synchronize()
     dropped = np.nonzero(vis.cpu().numpy())[0][~kept]
     assert (grads.means.cpu().numpy()[:, dropped] == 0).all()
+
+
+def test_benchmark_configuration_window_sampled():
+    """The benchmark's exact launch configuration: the 8-keyframe 1920x1080
+    window over its 2M-Gaussian start state, one projection launch for all
+    views, asynchronous sorts, per-view forward and pair adjoint, one
+    projection-adjoint launch.  Upstream gradients are non-zero on one 40x40
+    crop per view (zero at flagged pixels), so the oracle computes every
+    view's crop image, pose gradient and the parameter gradient summed over
+    the views exactly."""
+    gs = gc.gpu()
+    seed = 2506
+    views = synth.trajectory(seed, 8, 1920, 1080)
+    scene = synth.perturb_scene(seed, synth.window_scene(seed, views, 250_000, 3))
+    g = gc.gpu_gauss(scene)
+    n = scene.n
+    crops = [(200 + 190 * k, 120 + 100 * k, 40, 40) for k in range(8)]
+    keys = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    sorter = gs.BinSorter(0)
+    vs = []
+    for v in views:
+        vs.append(gs.View(gc.gpu_camera(v), gs.alloc_projected(n),
+                          first_slot=torch.empty(n, dtype=torch.int32, device="cuda"),
+                          dL_dpose=torch.zeros(12, dtype=torch.float64, device="cuda"),
+                          dL_dtwist=torch.zeros(6, dtype=torch.float64, device="cuda")))
+    gs.project_views(vs, g)
+    cap = max(sorter(vw.cam, vw.proj).n_instances for vw in vs)  # synchronous sorts size the lists
+    sorter.capacity = int(cap * 1.15) + 4096
+    n_pairs = torch.zeros(8, dtype=torch.int32, device="cuda")
+    full = (1080, 1920)
+    total, pose_refs, flagged = None, [], 0
+    for k, (v, vw) in enumerate(zip(views, vs)):
+        ocam, og = gc.oracle_inputs(v, scene)
+        op = orc.project(ocam, og)
+        ref = orc.render(ocam, op, crop=crops[k], flag_rel=FLAG_REL)
+        gi, gd, ga = gc.flagged_upstream(crops[k][2:][::-1], ref["flags"], 60 + k)
+        b = sorter.sort_async(vw.cam, vw.proj, n_pairs[k:k + 1], first_slot=vw.first_slot)
+        fr = gs.render_fwd(vw.cam, vw.proj, b)
+        vw.pair_grad = torch.empty((b.n_instances, 12), dtype=torch.float32, device="cuda")
+        t = lambda a: torch.tensor(gc.embed(a, full, crops[k]), device="cuda")
+        gs.render_bwd_pairs(vw.cam, vw.proj, b, fr, t(gi), vw.pair_grad, t(gd), t(ga))
+        torch.cuda.synchronize()
+        # the window's start state has ~36 support pairs per pixel, so one or two of a
+        # crop's 1600 pixels sit within 1e-5 of a threshold: the flagged share is
+        # bounded over all eight crops together
+        flagged += int((ref["flags"] != 0).sum())
+        _check_image(f"benchmark view {k}", fr, ref, crops[k], max_flagged=1.0)
+        rg = orc.backward(ocam, og, op, gi, gd, ga, crop=crops[k])
+        pose_refs.append((rg["R"].reshape(9), rg["t"], rg["twist"]))
+        if total is None:
+            total = {key: rg[key].copy() for key in keys}
+        else:
+            for key in keys:
+                total[key] += rg[key]
+        del rg, op
+    assert flagged <= 2e-3 * 8 * 40 * 40, flagged
+    grads = g.zeros_like()
+    gs.project_bwd_views(vs, g, grads)
+    torch.cuda.synchronize()
+    assert int(n_pairs.max()) <= sorter.capacity
+    for k, vw in enumerate(vs):
+        dp = vw.dL_dpose.cpu().numpy()
+        gc.assert_grad_close(f"view {k} dR", dp[:9], pose_refs[k][0])
+        gc.assert_grad_close(f"view {k} dt", dp[9:], pose_refs[k][1])
+        gc.assert_grad_close(f"view {k} twist", vw.dL_dtwist.cpu().numpy(), pose_refs[k][2])
+    for key in keys:
+        gc.assert_grad_close(f"window {key}", getattr(grads, key).cpu().numpy(), total[key])
