@@ -142,9 +142,12 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
  * radix sort of the emitted pairs by tile.
  *   tile_ids   [capacity] out: tile id of each sorted pair
  *   values     [capacity] out: Gaussian index of each sorted pair
- *   slots      [capacity] out: emission index of each sorted pair; the pairs
- *                         of Gaussian g have slots first_slot[g] ..
- *                         first_slot[g] + tiles_touched[g] - 1
+ *   slots      [capacity] out: slot of each sorted pair, a bijection onto
+ *                         [0, M) numbered by Gaussian index then row-major
+ *                         tile of its rect: the pairs of Gaussian g have
+ *                         slots first_slot[g] .. first_slot[g] +
+ *                         tiles_touched[g] - 1, first_slot being the
+ *                         exclusive prefix sum of tiles_touched
  *   ranges     [T][2]     out: [start, end) of each tile's run (0,0 if empty)
  *   first_slot [n]        out: first slot of each Gaussian (written where
  *                         tiles_touched > 0)

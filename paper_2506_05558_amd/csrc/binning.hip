@@ -286,25 +286,35 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *k
 }
 
 // ------------------------------------------------------------ binning steps
-__global__ void k_visible_flags(const int32_t *tiles, int64_t n, uint32_t *flags) {
+// One 64-bit value per Gaussian whose exclusive prefix sum gives both its
+// position among the visible Gaussians (low word: visibility flag) and its
+// first slot (high word: tiles touched).  Neither total can carry into the
+// high word: n < 2^31 and the pair count < 2^32.
+__global__ void k_visible_flags(const int32_t *tiles, int64_t n, uint64_t *flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = tiles[i] > 0 ? 1u : 0u;
+  if (i < n) {
+    const int32_t t = tiles[i];
+    flags[i] = t > 0 ? (1ull | (uint64_t)(uint32_t)t << 32) : 0ull;
+  }
 }
 
-// Visible Gaussians in index order: depth key, index, and the tile rect
-// packed as (tx0 | ty0 << 16, tx1 | ty1 << 16) for the pair emission, which
-// then gathers 8 bytes per Gaussian instead of a record and two radii.
-__global__ void k_compact(const uint32_t *flags, const uint32_t *pos, const float *rec, const int32_t *radius,
-                          int64_t n, int W, int H, uint32_t *keys, uint32_t *vals, uint2 *rect) {
+// Visible Gaussians in index order: depth key, index, and a 16-byte record
+// for the pair emission -- the tile rect packed as (tx0 | ty0 << 16,
+// tx1 | ty1 << 16) and the first slot -- which then gathers one record per
+// Gaussian instead of a render record, two radii and a slot.
+__global__ void k_compact(const uint64_t *flags, const uint64_t *pos, const float *rec, const int32_t *radius,
+                          int64_t n, int W, int H, uint32_t *keys, uint32_t *vals, uint4 *rect) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !flags[i]) return;
-  const uint32_t p = pos[i];
+  const uint64_t ps = pos[i];
+  const uint32_t p = (uint32_t)ps;
   const float4 r0 = *(const float4 *)(rec + i * GS_REC_FLOATS);
   keys[p] = __float_as_uint(rec[i * GS_REC_FLOATS + 11]);  // depth > 0: bits order like values
   vals[p] = (uint32_t)i;
   int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
   tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[i], radius[n + i], W, H, tx0, ty0, tx1, ty1);
-  rect[i] = make_uint2((uint32_t)tx0 | (uint32_t)ty0 << 16, (uint32_t)tx1 | (uint32_t)ty1 << 16);
+  rect[i] = make_uint4((uint32_t)tx0 | (uint32_t)ty0 << 16, (uint32_t)tx1 | (uint32_t)ty1 << 16,
+                       (uint32_t)(ps >> 32), 0u);
 }
 
 __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev, const int32_t *tiles, int64_t n,
@@ -317,27 +327,34 @@ __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
 // Emits the pairs of the j-th Gaussian in depth order at its offset: tile
-// id, Gaussian index and the pair's emission index ("slot"); the pairs of a
-// Gaussian occupy slots [first_slot[g], first_slot[g] + tiles_touched[g]).
-__global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const uint2 *rect,
+// id, Gaussian index and the pair's slot.  Slots are numbered in Gaussian
+// index order (islot = exclusive prefix sum of tiles_touched), so the
+// projection adjoint, one lane per Gaussian, reads the per-pair gradients
+// of a wave's Gaussians from one contiguous range.
+__global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const uint4 *rect,
                             int tiles_x, uint32_t capacity, uint32_t *tile_keys, uint32_t *vals, uint32_t *slots,
                             uint32_t *first_slot) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= (int64_t)*count_dev) return;
   const uint32_t g = order[j];
-  const uint2 r = rect[g];
+  const uint4 r = rect[g];
   const int tx0 = (int)(r.x & 0xffffu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xffffu), ty1 = (int)(r.y >> 16);
   uint32_t o = offs[j];
-  // a Gaussian whose pairs do not all fit (an asynchronous call short of
-  // capacity) gets no first slot: its adjoint then reads no pair
+  // a Gaussian whose slots do not all fit (an asynchronous call short of
+  // capacity) gets no first slot, so its adjoint reads no pair, and its
+  // pairs write to slot 0 (in bounds; such lists are to be redone anyway)
   const uint32_t npairs = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-  first_slot[g] = (uint64_t)o + npairs <= capacity ? o : kNoSlot;
+  const uint32_t s0 = r.z;
+  const bool fits = (uint64_t)s0 + npairs <= capacity;
+  first_slot[g] = fits ? s0 : kNoSlot;
+  uint32_t sl = fits ? s0 : 0u;
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
       if (o >= capacity) return;
       tile_keys[o] = (uint32_t)(ty * tiles_x + tx);
       vals[o] = g;
-      slots[o] = o;
+      slots[o] = sl;
+      sl += fits ? 1u : 0u;
       ++o;
     }
 }
@@ -445,8 +462,10 @@ using namespace gsmi;
 namespace {
 
 struct BinLayout {
-  uint32_t *flags, *pos, *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *scalars, *ktmp, *vtmp, *stmp;
-  uint2 *rect;
+  uint32_t *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *scalars, *ktmp, *vtmp, *stmp;
+  uint64_t *total64;
+  uint64_t *flags64, *pos64;
+  uint4 *rect;
   void *scan_ws;
   size_t bytes;
 };
@@ -456,19 +475,20 @@ BinLayout bin_layout(void *ws, int64_t n, int64_t capacity) {
   BinLayout L;
   const size_t nn = (size_t)(n > 0 ? n : 1);
   const size_t cc = (size_t)(capacity > 0 ? capacity : 1);
-  L.flags = cv.take<uint32_t>(nn);
-  L.pos = cv.take<uint32_t>(nn);
+  L.flags64 = cv.take<uint64_t>(nn);
+  L.pos64 = cv.take<uint64_t>(nn);
   L.kA = cv.take<uint32_t>(nn);
   L.vA = cv.take<uint32_t>(nn);
   L.kB = cv.take<uint32_t>(nn);
   L.vB = cv.take<uint32_t>(nn);
   L.cnt = cv.take<uint32_t>(nn);
   L.offs = cv.take<uint32_t>(nn);
-  L.rect = cv.take<uint2>(nn);
+  L.rect = cv.take<uint4>(nn);
   const int64_t big = n > capacity ? n : capacity;
   L.hist = cv.take<uint32_t>(radix_hist_elems(big));
   L.scan_ws = cv.take<char>(scan_workspace((int64_t)radix_hist_elems(big) > big ? (int64_t)radix_hist_elems(big) : big));
   L.scalars = cv.take<uint32_t>(4);
+  L.total64 = cv.take<uint64_t>(1);
   L.ktmp = cv.take<uint32_t>(cc);
   L.vtmp = cv.take<uint32_t>(cc);
   L.stmp = cv.take<uint32_t>(cc);
@@ -517,15 +537,18 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
   const int tx = tiles_x_of(W), T = tx * tiles_y_of(H);
   BinLayout L = bin_layout(ws, n, capacity);
   RadixWs rw{L.hist, L.scan_ws};
-  uint32_t *V = L.scalars, *Mdev = n_dev ? n_dev : L.scalars + 1;
+  // V: the visible count, the low word of the 64-bit scan total (little endian)
+  uint32_t *V = (uint32_t *)L.total64, *Mdev = n_dev ? n_dev : L.scalars + 1;
 
   uint32_t M = 0;
   int order_buf = 0;
   if (n > 0) {
     // 1. compact the visible Gaussians with their depth keys
-    GS_LAUNCH("bin_flags", k_visible_flags, grid1(n), 256, 0, s, proj->tiles_touched, n, L.flags);
-    if ((st = scan_exclusive(L.flags, L.pos, n, V, L.scan_ws, s)) != GS_OK) return st;
-    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, L.flags, L.pos, proj->rec, proj->radius, n, W, H,
+    //    (one 64-bit scan gives the visible positions and the index-order first slots;
+    //    the visible count V is the low word of its total)
+    GS_LAUNCH("bin_flags", k_visible_flags, grid1(n), 256, 0, s, proj->tiles_touched, n, L.flags64);
+    if ((st = scan_exclusive_u64(L.flags64, L.pos64, n, L.total64, L.scan_ws, s)) != GS_OK) return st;
+    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, L.flags64, L.pos64, proj->rec, proj->radius, n, W, H,
               L.kA, L.vA, L.rect);
     // 2. stable sort by depth (31 significant bits of a positive float)
     int shifts[8], widths[8];

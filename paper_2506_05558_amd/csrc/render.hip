@@ -99,15 +99,15 @@ __device__ __forceinline__ float splat_s2(float ca, float cb, float cc, float dx
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// The length of wave w's quadrant list and its entries i and i + 1 (i even,
-// one 16-bit read): the same for every lane, so they live in scalar
-// registers and the loops stay uniform.  The loops take two entries per
-// turn, so both exponents are in flight before either entry's body.
+// The length of wave w's quadrant list and its entries i .. i + 3 (i a
+// multiple of 4, one 32-bit read): the same for every lane, so they live in
+// scalar registers and the loops stay uniform.  The loops take four entries
+// per turn, so all four exponents are in flight before the first body.
 __device__ __forceinline__ int list_count(const Stage &S, int w) {
   return __builtin_amdgcn_readfirstlane(S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w]);
 }
-__device__ __forceinline__ int list_pair(const Stage &S, int w, int i) {
-  return __builtin_amdgcn_readfirstlane((int)*(const uint16_t *)&S.list[w][i]);
+__device__ __forceinline__ int list_quad(const Stage &S, int w, int i) {
+  return __builtin_amdgcn_readfirstlane(*(const int *)&S.list[w][i]);
 }
 
 struct Pixel {
@@ -183,23 +183,30 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
       }
       return false;
     };
-    // two entries per turn: both exponents are evaluated before either body
-    for (int i = 0; i < cnt; i += 2) {
-      const int pr = list_pair(S, w, i);
-      const int k0 = pr & 255;
-      const int k1 = i + 1 < cnt ? pr >> 8 : k0;
-      const bool has1 = i + 1 < cnt;
-      const float4 A0 = S.a[k0], B0 = S.b[k0];
-      const float4 A1 = S.a[k1], B1 = S.b[k1];
-      const float lg0 = __fadd_rn(splat_s2(A0.z, A0.w, B0.x, __fsub_rn(fpx, A0.x), __fsub_rn(fpy, A0.y)), B0.y);
-      const float lg1 = __fadd_rn(splat_s2(A1.z, A1.w, B1.x, __fsub_rn(fpx, A1.x), __fsub_rn(fpy, A1.y)), B1.y);
-      if (STATS) nev += fpx != kFar ? 1 : 0;
-      const bool t0 = lg0 >= l2min;
-      if (ballot(t0) != 0 && body(k0, B0, lg0, t0)) break;
-      if (!has1) break;
-      if (STATS) nev += fpx != kFar ? 1 : 0;
-      const bool t1 = fpx != kFar && lg1 >= l2min;  // a pixel that stopped at k0 takes nothing more
-      if (ballot(t1) != 0 && body(k1, B1, lg1, t1)) break;
+    // four entries per turn: all exponents are evaluated before the first body
+    bool all_done = false;
+    for (int i = 0; i < cnt && !all_done; i += 4) {
+      const int qd = list_quad(S, w, i);
+      int kk[4];
+      float4 BB[4];
+      float lg[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        kk[j] = i + j < cnt ? (qd >> (8 * j)) & 255 : (qd & 255);
+        const float4 A = S.a[kk[j]];
+        BB[j] = S.b[kk[j]];
+        lg[j] = __fadd_rn(splat_s2(A.z, A.w, BB[j].x, __fsub_rn(fpx, A.x), __fsub_rn(fpy, A.y)), BB[j].y);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (i + j >= cnt) break;
+        if (STATS) nev += fpx != kFar ? 1 : 0;
+        const bool tk = fpx != kFar && lg[j] >= l2min;  // a pixel that stopped earlier takes nothing more
+        if (ballot(tk) != 0 && body(kk[j], BB[j], lg[j], tk)) {
+          all_done = true;
+          break;
+        }
+      }
     }
   }
   if (!P.inside) return;
@@ -400,21 +407,25 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
         nslots = 0;
       }
     };
-    // two entries per turn: both exponents are evaluated before either body
-    for (int i = 0; i < cnt; i += 2) {
-      const int pr = list_pair(S, w, i);
-      const int k0 = pr & 255;
-      if (idx0 + k0 >= wmax) break;  // lists ascend: no pixel of this wave reaches further
-      const int k1 = i + 1 < cnt ? pr >> 8 : k0;
-      const bool has1 = i + 1 < cnt;
-      const float4 A0 = S.a[k0], B0 = S.b[k0];
-      const float4 A1 = S.a[k1], B1 = S.b[k1];
-      const float lg0 = __fadd_rn(splat_s2(A0.z, A0.w, B0.x, __fsub_rn(fpx, A0.x), __fsub_rn(fpy, A0.y)), B0.y);
-      const float lg1 = __fadd_rn(splat_s2(A1.z, A1.w, B1.x, __fsub_rn(fpx, A1.x), __fsub_rn(fpy, A1.y)), B1.y);
-      const bool t0 = idx0 + k0 < ncon && lg0 >= l2min;
-      const bool t1 = has1 && idx0 + k1 < ncon && lg1 >= l2min;
-      if (ballot(t0) != 0) body(k0, B0, lg0, t0);
-      if (ballot(t1) != 0) body(k1, B1, lg1, t1);
+    // four entries per turn: all exponents are evaluated before the first body
+    for (int i = 0; i < cnt; i += 4) {
+      const int qd = list_quad(S, w, i);
+      if (idx0 + (qd & 255) >= wmax) break;  // lists ascend: no pixel of this wave reaches further
+      int kk[4];
+      float4 BB[4];
+      float lg[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        kk[j] = i + j < cnt ? (qd >> (8 * j)) & 255 : (qd & 255);
+        const float4 A = S.a[kk[j]];
+        BB[j] = S.b[kk[j]];
+        lg[j] = __fadd_rn(splat_s2(A.z, A.w, BB[j].x, __fsub_rn(fpx, A.x), __fsub_rn(fpy, A.y)), BB[j].y);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool tk = i + j < cnt && idx0 + kk[j] < ncon && lg[j] >= l2min;
+        if (ballot(tk) != 0) body(kk[j], BB[j], lg[j], tk);
+      }
     }
     if (nslots > 0) bwd_phase2(S, B, w, nslots, sAcc, Gr);
     __syncthreads();

@@ -84,6 +84,10 @@ def _check_binning(view, proj, binned):
     t = tids.astype(np.int64)
     local = (t // tiles_x - ty0[g]) * (tx1[g] - tx0[g] + 1) + (t % tiles_x - tx0[g])
     assert np.array_equal(slots, first[g] + local)
+    # slots are numbered in Gaussian-index order: first_slot is the exclusive
+    # prefix sum of tiles_touched
+    ex = np.concatenate([[0], np.cumsum(tiles.astype(np.int64))[:-1]])
+    assert np.array_equal(first[tiles > 0], ex[tiles > 0])
     return M
 
 
