@@ -8,14 +8,15 @@
 // order of a stable sort of (tile << 32 | depth bits) over pairs emitted in
 // Gaussian-index order, at about a third of the key traffic.
 //
-// Radix pass layout: every workgroup owns 4096 consecutive keys, each of its
-// waves a contiguous quarter.  The histogram kernel counts each block's
-// digits; an exclusive scan over the digit-major table [digit][block] gives
-// every (digit, block) its output base.  The scatter kernel ranks each
-// wave's keys in order (the lanes holding the same digit are found with one
-// ballot per digit bit), combines the waves' digit counts into block-local
-// positions, reorders the block in LDS and writes each digit's keys as one
-// contiguous run -- stable, and with coalesced stores.
+// Radix pass layout: every workgroup (16 waves) owns 4096 consecutive keys,
+// each wave a contiguous run of 256.  The histogram kernel counts each
+// block's digits into the digit-major table [digit][block]; one workgroup
+// per digit scans its row in place and records the row total.  The scatter
+// kernel ranks each wave's keys in order (the lanes holding the same digit
+// are found with one ballot per digit bit), combines the waves' digit counts
+// into block-local positions, adds the row-total prefix to the row scan to
+// get each digit's output base, reorders the block in LDS and writes each
+// digit's keys as one contiguous run -- stable, and with coalesced stores.
 #include "common.h"
 
 namespace gsmi {
@@ -24,10 +25,10 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;  // 4096
-constexpr int kRadixBlock = 256;                    // 4 waves
+constexpr int kRadixBlock = 1024;                   // 16 waves
 constexpr int kWaves = kRadixBlock / 64;
-constexpr int kWaveKeys = 1024;                     // keys per wave in a radix pass
-constexpr int kBlockKeys = kWaves * kWaveKeys;      // keys per workgroup
+constexpr int kWaveKeys = 256;                      // keys per wave in a radix pass
+constexpr int kBlockKeys = kWaves * kWaveKeys;      // keys per workgroup (4096)
 
 // ------------------------------------------------------------------- scan
 template <class T>
@@ -176,9 +177,8 @@ __device__ __forceinline__ uint64_t peers_of(uint32_t digit, int bits, bool vali
 }
 
 // Pass layout: each workgroup owns kBlockKeys consecutive keys, each of its
-// four waves a contiguous quarter (kWaveKeys).  The count kernel gives the
-// digit histogram of every block, hist[digit][block]; an exclusive scan over
-// that digit-major table gives every (digit, block) its first output index.
+// waves a contiguous run of kWaveKeys.  The count kernel gives the digit
+// histogram of every block, hist[digit][block].
 __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(const uint32_t *keys, const uint32_t *count_dev,
                                                             uint32_t count_max, int shift, int bits,
                                                             int64_t nblocks, uint32_t *hist) {
@@ -200,25 +200,58 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(const uint32_t *keys
     if (valid && higher == 0) cnt[w][d] += (uint32_t)__popcll(peers);  // highest lane of the group
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < ndig; d += kRadixBlock)
-    hist[(int64_t)d * nblocks + blockIdx.x] = (cnt[0][d] + cnt[1][d]) + (cnt[2][d] + cnt[3][d]);
+  for (int d = threadIdx.x; d < ndig; d += kRadixBlock) {
+    uint32_t sum = 0;
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) sum += cnt[v][d];
+    hist[(int64_t)d * nblocks + blockIdx.x] = sum;
+  }
 }
 
-// Stable scatter of one block: each wave ranks its quarter in key order with
+// Exclusive scan of one digit's row hist[d][0 .. nblocks) in place (one
+// workgroup per digit); the row total goes to rowtot[d].
+constexpr int kRowItems = 4;
+__global__ __launch_bounds__(kScanBlock) void k_radix_rowscan(uint32_t *hist, int64_t nblocks, uint32_t *rowtot) {
+  uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nblocks; base += kScanBlock * kRowItems) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kRowItems;
+    uint32_t v[kRowItems], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) {
+      v[k] = i0 + k < nblocks ? row[i0 + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_excl_scan<uint32_t>(sum, &tot);
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) {
+      if (i0 + k < nblocks) row[i0 + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one block: each wave ranks its run in key order with
 // ballot peer matching (rank = earlier keys of the same digit), the block
 // turns per-wave digit counts into local positions (digit-major, then wave,
 // then rank), the keys are reordered in LDS, and consecutive lanes then
 // write consecutive local positions, so each digit's keys leave as one
-// contiguous run at offsets[digit][block].
+// contiguous run.  Digit d of block b starts at the exclusive prefix of the
+// row totals (rowtot) plus the row scan (rows[d][b]).
 template <bool TWO>
 __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
                                                                const uint32_t *win, uint32_t *kout, uint32_t *vout,
                                                                uint32_t *wout, const uint32_t *count_dev,
                                                                uint32_t count_max, int shift, int bits,
-                                                               int64_t nblocks, const uint32_t *offsets) {
+                                                               int64_t nblocks, const uint32_t *rows,
+                                                               const uint32_t *rowtot) {
   constexpr int kIt = kWaveKeys / 64;
   __shared__ uint32_t run[kWaves][256];
   __shared__ uint32_t gbase[256];
+  __shared__ uint32_t dsum[2][4];
   __shared__ uint32_t sk[kBlockKeys];
   __shared__ uint32_t sv[kBlockKeys];
   __shared__ uint32_t sw[TWO ? kBlockKeys : 1];
@@ -249,19 +282,32 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *k
     }
   }
   __syncthreads();
-  // local digit starts (exclusive scan of the block's digit totals) and the
-  // per-wave starts within each digit; run[] turns into local positions
-  {
-    const int d = threadIdx.x;  // one digit per lane (kRadixBlock == 256)
-    const uint32_t n0 = run[0][d], n1 = run[1][d], n2 = run[2][d], n3 = run[3][d];
-    uint32_t tot;
-    const uint32_t start = block_excl_scan<uint32_t>(n0 + n1 + n2 + n3, &tot);
-    gbase[d] = (d < ndig ? offsets[(int64_t)d * nblocks + blockIdx.x] : 0u) - start;
-    __syncthreads();
-    run[0][d] = start;
-    run[1][d] = start + n0;
-    run[2][d] = start + n0 + n1;
-    run[3][d] = start + n0 + n1 + n2;
+  // the first four waves, one digit per lane: local digit starts (exclusive
+  // scan of the block's digit totals), the digit's global start (exclusive
+  // scan of the row totals), and the per-wave starts within each digit
+  const int d = threadIdx.x;
+  uint32_t tot = 0, rt = 0, inc = 0, rinc = 0;
+  if (d < 256) {
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) tot += run[v][d];
+    rt = d < ndig ? rowtot[d] : 0u;
+    inc = wave_incl_scan<uint32_t>(tot);
+    rinc = wave_incl_scan<uint32_t>(rt);
+    if (lane == 63) dsum[0][w] = inc, dsum[1][w] = rinc;
+  }
+  __syncthreads();
+  if (d < 256) {
+    uint32_t before = 0, rbefore = 0;
+    for (int i = 0; i < w; ++i) before += dsum[0][i], rbefore += dsum[1][i];
+    const uint32_t start = before + inc - tot;
+    gbase[d] = (d < ndig ? rbefore + rinc - rt + rows[(int64_t)d * nblocks + blockIdx.x] : 0u) - start;
+    uint32_t acc = start;
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) {
+      const uint32_t n = run[v][d];
+      run[v][d] = acc;
+      acc += n;
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -326,39 +372,66 @@ __global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev
 
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
-// Emits the pairs of the j-th Gaussian in depth order at its offset: tile
-// id, Gaussian index and the pair's slot.  Slots are numbered in Gaussian
-// index order (islot = exclusive prefix sum of tiles_touched), so the
-// projection adjoint, one lane per Gaussian, reads the per-pair gradients
-// of a wave's Gaussians from one contiguous range.
-__global__ void k_duplicate(const uint32_t *order, const uint32_t *count_dev, const uint32_t *offs, const uint4 *rect,
-                            int tiles_x, uint32_t capacity, uint32_t *tile_keys, uint32_t *vals, uint32_t *slots,
-                            uint32_t *first_slot) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= (int64_t)*count_dev) return;
-  const uint32_t g = order[j];
-  const uint4 r = rect[g];
-  const int tx0 = (int)(r.x & 0xffffu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xffffu), ty1 = (int)(r.y >> 16);
-  uint32_t o = offs[j];
-  // a Gaussian whose slots do not all fit (an asynchronous call short of
-  // capacity) gets no first slot, so its adjoint reads no pair, and its
-  // pairs write to slot 0 (in bounds; such lists are to be redone anyway)
-  const uint32_t npairs = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-  const uint32_t s0 = r.z;
-  const bool fits = (uint64_t)s0 + npairs <= capacity;
-  first_slot[g] = fits ? s0 : kNoSlot;
-  uint32_t sl = fits ? s0 : 0u;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      if (o >= capacity) return;
-      tile_keys[o] = (uint32_t)(ty * tiles_x + tx);
-      vals[o] = g;
-      slots[o] = sl;
-      sl += fits ? 1u : 0u;
-      ++o;
+// Emits the pairs of the visible Gaussians in depth order: tile id,
+// Gaussian index and the pair's slot.  A workgroup takes 256 consecutive
+// Gaussians of the depth order, stages their offsets and tile rects in LDS,
+// and its lanes then walk the workgroup's pair range together, one pair per
+// lane (the owning Gaussian by binary search over the staged offsets), so
+// the stores are coalesced and a Gaussian with many tiles is spread over
+// many lanes.  Slots are numbered in Gaussian index order (islot = exclusive
+// prefix sum of tiles_touched), so the projection adjoint, one lane per
+// Gaussian, reads the per-pair gradients of a wave's Gaussians from one
+// contiguous range.
+constexpr int kDupBlock = 256;
+__global__ __launch_bounds__(kDupBlock) void k_duplicate(const uint32_t *order, const uint32_t *count_dev,
+                                                         const uint32_t *offs, const uint32_t *total,
+                                                         const uint4 *rect, int tiles_x, uint32_t capacity,
+                                                         uint32_t *tile_keys, uint32_t *vals, uint32_t *slots,
+                                                         uint32_t *first_slot) {
+  __shared__ uint32_t sOff[kDupBlock + 1];
+  __shared__ uint32_t sG[kDupBlock], sSlot[kDupBlock];
+  __shared__ uint32_t sX[kDupBlock], sY[kDupBlock];
+  const uint32_t V = *count_dev;
+  const int64_t j0 = (int64_t)blockIdx.x * kDupBlock;
+  if (j0 >= (int64_t)V) return;
+  const int nj = (int)min((int64_t)kDupBlock, (int64_t)V - j0);
+  const int t = threadIdx.x;
+  if (t < nj) {
+    const uint32_t g = order[j0 + t];
+    const uint4 r = rect[g];
+    const uint32_t npairs = ((r.y & 0xffffu) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
+    // a Gaussian whose slots do not all fit (an asynchronous call short of
+    // capacity) gets no first slot, so its adjoint reads no pair, and its
+    // pairs write to slot 0 (in bounds; such lists are to be redone anyway)
+    const bool fits = (uint64_t)r.z + npairs <= capacity;
+    first_slot[g] = fits ? r.z : kNoSlot;
+    sG[t] = g;
+    sSlot[t] = fits ? r.z : kNoSlot;
+    sX[t] = r.x;
+    sY[t] = r.y;
+    sOff[t] = offs[j0 + t];
+  }
+  if (t == 0) sOff[nj] = j0 + nj < (int64_t)V ? offs[j0 + nj] : *total;
+  __syncthreads();
+  const uint32_t p0 = sOff[0], p1 = min(sOff[nj], capacity);
+  for (uint32_t p = p0 + t; p < p1; p += kDupBlock) {
+    // the last Gaussian k with sOff[k] <= p (offsets ascend; a run of equal
+    // offsets ends at the Gaussian that owns the pairs)
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sOff[mid] <= p) lo = mid;
+      else hi = mid - 1;
     }
+    const uint32_t local = p - sOff[lo];
+    const uint32_t rx = sX[lo], ry = sY[lo];
+    const uint32_t tx0 = rx & 0xffffu, ty0 = rx >> 16, w = (ry & 0xffffu) - tx0 + 1u;
+    const uint32_t dy = local / w, dx = local - dy * w;
+    tile_keys[p] = (ty0 + dy) * (uint32_t)tiles_x + tx0 + dx;
+    vals[p] = sG[lo];
+    slots[p] = sSlot[lo] == kNoSlot ? 0u : sSlot[lo] + local;
+  }
 }
-
 
 __global__ void k_ranges(const uint32_t *tile_keys, const uint32_t *count_dev, uint32_t count_max,
                          uint32_t *ranges) {
@@ -388,8 +461,8 @@ int plan_passes(int total_bits, int shifts[8], int widths[8]) {
 }
 
 struct RadixWs {
-  uint32_t *hist;  // [256][nblocks(count_max)]
-  void *scan_ws;
+  uint32_t *hist;    // [256][nblocks(count_max)]
+  uint32_t *rowtot;  // [256]
 };
 
 size_t radix_hist_elems(int64_t count_max) { return 256 * (size_t)nblocks_of(count_max); }
@@ -405,16 +478,15 @@ gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], uint32_t *v2[2], const uint
     if (count_max == 0) break;
     GS_LAUNCH("radix_hist", k_radix_hist, blocks, kRadixBlock, 0, s, k[cur], count_dev, (uint32_t)count_max,
               shifts[p], widths[p], blocks, rw.hist);
-    gs_status st = scan_exclusive(rw.hist, rw.hist, (int64_t)(1 << widths[p]) * blocks, nullptr, rw.scan_ws, s);
-    if (st != GS_OK) return st;
+    GS_LAUNCH("scan", k_radix_rowscan, 1 << widths[p], kScanBlock, 0, s, rw.hist, blocks, rw.rowtot);
     if (v2)
       GS_LAUNCH("radix_scatter", k_radix_scatter<true>, blocks, kRadixBlock, 0, s, k[cur], v[cur], v2[cur],
                 k[1 - cur], v[1 - cur], v2[1 - cur], count_dev, (uint32_t)count_max, shifts[p], widths[p], blocks,
-                rw.hist);
+                rw.hist, rw.rowtot);
     else
       GS_LAUNCH("radix_scatter", k_radix_scatter<false>, blocks, kRadixBlock, 0, s, k[cur], v[cur], nullptr,
                 k[1 - cur], v[1 - cur], nullptr, count_dev, (uint32_t)count_max, shifts[p], widths[p], blocks,
-                rw.hist);
+                rw.hist, rw.rowtot);
     cur = 1 - cur;
   }
   *result = cur;
@@ -462,7 +534,7 @@ using namespace gsmi;
 namespace {
 
 struct BinLayout {
-  uint32_t *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *scalars, *ktmp, *vtmp, *stmp;
+  uint32_t *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *rowtot, *scalars, *ktmp, *vtmp, *stmp;
   uint64_t *total64;
   uint64_t *flags64, *pos64;
   uint4 *rect;
@@ -486,7 +558,8 @@ BinLayout bin_layout(void *ws, int64_t n, int64_t capacity) {
   L.rect = cv.take<uint4>(nn);
   const int64_t big = n > capacity ? n : capacity;
   L.hist = cv.take<uint32_t>(radix_hist_elems(big));
-  L.scan_ws = cv.take<char>(scan_workspace((int64_t)radix_hist_elems(big) > big ? (int64_t)radix_hist_elems(big) : big));
+  L.rowtot = cv.take<uint32_t>(256);
+  L.scan_ws = cv.take<char>(scan_workspace(big));
   L.scalars = cv.take<uint32_t>(4);
   L.total64 = cv.take<uint64_t>(1);
   L.ktmp = cv.take<uint32_t>(cc);
@@ -536,7 +609,7 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
   const int W = cam->width, H = cam->height;
   const int tx = tiles_x_of(W), T = tx * tiles_y_of(H);
   BinLayout L = bin_layout(ws, n, capacity);
-  RadixWs rw{L.hist, L.scan_ws};
+  RadixWs rw{L.hist, L.rowtot};
   // V: the visible count, the low word of the 64-bit scan total (little endian)
   uint32_t *V = (uint32_t *)L.total64, *Mdev = n_dev ? n_dev : L.scalars + 1;
 
@@ -591,8 +664,8 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
     kk[0] = L.ktmp; vv[0] = L.vtmp; ss[0] = L.stmp; kk[1] = tile_ids; vv[1] = values; ss[1] = slots;
   }
   const uint32_t *order = order_buf ? L.vB : L.vA;
-  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n), 256, 0, s, order, V, L.offs, L.rect, tx, (uint32_t)capacity,
-            kk[0], vv[0], ss[0], first_slot);
+  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n, kDupBlock), kDupBlock, 0, s, order, V, L.offs, Mdev, L.rect, tx,
+            (uint32_t)capacity, kk[0], vv[0], ss[0], first_slot);
   int res = 0;
   const uint32_t *mcount = n_dev ? n_dev : nullptr;
   if ((st = radix_sort(kk, vv, ss, mcount, mmax, np, shifts, widths, rw, s, &res)) != GS_OK) return st;

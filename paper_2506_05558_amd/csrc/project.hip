@@ -309,23 +309,14 @@ struct GAcc {
 // the parameter gradients to acc and writes this Gaussian's pose terms into
 // pose[12]: dL/dR (row-major) and dL/dt.
 template <int DEG>
-__device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs &v, int64_t i, int ntiles,
-                                              const GParams<DEG> &P, GAcc<DEG> &acc, float pose[12]) {
+__device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs &v, int64_t i, const float4 &g0,
+                                              const float4 &g1, const float4 &g2, const GParams<DEG> &P,
+                                              GAcc<DEG> &acc, float pose[12]) {
   Geo<float> f;
   geometry<float, DEG>(m, v, P, f);
   const float mu[3] = {P.mu[0], P.mu[1], P.mu[2]};
-  // the Gaussian's pairs are contiguous: sum their 2D gradients in slot order
-  float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f), g1 = g0, g2 = g0;
-  {
-    const float4 *gp4 = (const float4 *)(v.pair_grad + (size_t)v.first_slot[i] * 12);
-    for (int j = 0; j < ntiles; ++j) {
-      const float4 a0 = gp4[3 * j], a1 = gp4[3 * j + 1], a2 = gp4[3 * j + 2];
-      g0.x += a0.x; g0.y += a0.y; g0.z += a0.z; g0.w += a0.w;
-      g1.x += a1.x; g1.y += a1.y; g1.z += a1.z; g1.w += a1.w;
-      g2.x += a2.x; g2.y += a2.y;
-    }
-  }
-  // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -)
+  // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -):
+  // the sums of the Gaussian's per-pair 2D gradients
   const float4 rgbz = *(const float4 *)(v.rec + i * GS_REC_FLOATS + 8);
 
   // colour -> SH coefficients and view direction (no pose path, section 4.3).
@@ -457,6 +448,52 @@ __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs
   }
 }
 
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Sums of the per-pair 2D gradients of each lane's Gaussian in one view.
+// Slots are numbered in Gaussian index order, so the pairs of a wave's
+// Gaussians form one contiguous range: the wave reads it 64 pairs at a time
+// with coalesced loads, stages them in LDS, and each lane adds up its own
+// pairs from there in slot order.  (A Gaussian without a first slot did not
+// fit the lists; since slots ascend with the index, neither did any later
+// one, so the lanes that take part own consecutive ranges.)
+__device__ __forceinline__ void pair_sums(const float *pair_grad, uint32_t fs, int nt, float4 (*stage)[64],
+                                          float4 &g0, float4 &g1, float4 &g2) {
+  const int lane = threadIdx.x & 63;
+  g0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  g1 = g0;
+  g2 = g0;
+  const uint64_t act = ballot(nt > 0);
+  if (act == 0) return;
+  const int first = __builtin_ctzll(act), last = 63 - __builtin_clzll(act);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)fs, first);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(fs + (uint32_t)nt), last);
+  const uint32_t e = fs + (uint32_t)(nt > 0 ? nt : 0);
+  for (uint32_t base = lo; base < hi; base += 64) {
+    const uint32_t q = base + (uint32_t)lane;
+    if (q < hi) {
+      const float4 *src = (const float4 *)(pair_grad + (size_t)q * 12);
+      stage[0][lane] = src[0];
+      stage[1][lane] = src[1];
+      stage[2][lane] = src[2];
+    }
+    wave_lds_fence();
+    if (nt > 0) {
+      const uint32_t j0 = max(fs, base), j1 = min(e, base + 64u);
+      for (uint32_t j = j0; j < j1; ++j) {
+        const float4 a0 = stage[0][j - base], a1 = stage[1][j - base], a2 = stage[2][j - base];
+        g0.x += a0.x; g0.y += a0.y; g0.z += a0.z; g0.w += a0.w;
+        g1.x += a1.x; g1.y += a1.y; g1.z += a1.z; g1.w += a1.w;
+        g2.x += a2.x; g2.y += a2.y;
+      }
+    }
+    wave_lds_fence();
+  }
+}
+
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -472,35 +509,44 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
 #pragma unroll
   for (int k = 0; k < GParams<DEG>::NB * 3; ++k) acc.gsh[k] = 0.f;
   bool any = false;
-  __shared__ double red[kBlock / 64][12];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ float4 stage[kBlock / 64][3][64];
+  __shared__ float tb[12][kBlock];
+  const int t = threadIdx.x, wv = t >> 6;
   for (int vi = 0; vi < m.nv; ++vi) {
     const ViewArgs &v = m.v[vi];
     float term[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) term[k] = 0.f;
     // no first slot: the pairs did not fit the lists (see gs_bin_sort_async)
-    const int nt = valid && v.first_slot[i] != 0xffffffffu ? v.tiles[i] : 0;
+    const uint32_t fs = valid ? v.first_slot[i] : 0xffffffffu;
+    const int nt = fs != 0xffffffffu ? v.tiles[i] : 0;
+    float4 g0, g1, g2;
+    pair_sums(v.pair_grad, fs, nt, stage[wv], g0, g1, g2);
     if (nt > 0) {
-      backward_view<DEG>(m, v, i, nt, P, acc, term);
+      backward_view<DEG>(m, v, i, g0, g1, g2, P, acc, term);
       any = true;
     }
-    // block reduction of this view's 12 pose partials (fixed order: deterministic)
+    // block reduction of this view's 12 pose partials in a fixed order
+    // (deterministic): transposed through LDS, 16 lanes per component each
+    // add 16 terms in FP64, then a 16-lane tree
+    double* part = m.partials + ((int64_t)vi * gridDim.x + blockIdx.x) * 12;
+    if (__syncthreads_or(nt > 0)) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      double x = (double)term[k];
+      for (int k = 0; k < 12; ++k) tb[k][t] = term[k];
+      __syncthreads();
+      if (t < 192) {
+        const int c = t >> 4, seg = t & 15;
+        double x = 0.0;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-      if (lane == 0) red[wv][k] = x;
+        for (int k = 0; k < 16; ++k) x += (double)tb[c][seg * 16 + k];
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) x += __shfl_down(x, off, 16);
+        if (seg == 0) part[c] = x;
+      }
+      __syncthreads();
+    } else if (t < 12) {
+      part[t] = 0.0;
     }
-    __syncthreads();
-    if (threadIdx.x < 12) {
-      double x = 0.0;
-#pragma unroll
-      for (int w = 0; w < kBlock / 64; ++w) x += red[w][threadIdx.x];
-      m.partials[((int64_t)vi * gridDim.x + blockIdx.x) * 12 + threadIdx.x] = x;
-    }
-    __syncthreads();
   }
   if (!any) return;
   const int64_t n = m.n;

@@ -99,6 +99,11 @@ __device__ __forceinline__ float splat_s2(float ca, float cb, float cc, float dx
 
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// min(alpha_max, raw) for raw = 2^x >= 0 (never NaN): one v_med3_f32
+__device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
+  return __builtin_amdgcn_fmed3f(raw, 0.0f, alpha_max);
+}
+
 // The length of wave w's quadrant list and its entries i .. i + 3 (i a
 // multiple of 4, one 32-bit read): the same for every lane, so they live in
 // scalar registers and the loops stay uniform.  The loops take four entries
@@ -160,7 +165,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
     const int idx0 = (int)(base - s);
     // returns true once every pixel of the wave has stopped
     auto body = [&](int k, const float4 &B, float lg, bool take) -> bool {
-      const float alpha = fminf(a.alpha_max, exp2_fast(lg));
+      const float alpha = clamp_alpha(exp2_fast(lg), a.alpha_max);
       const float2 C = S.c[k];
       const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
       const bool stop = (take ? Tn : 1.0f) < a.t_min;
@@ -257,13 +262,13 @@ struct BwdShared {
 // Phase 2 of the adjoint for one wave: the chunk's entries are spread over
 // the lanes as (slot e = lane >> 3, pixel row r = lane & 7); each lane sums
 // its row's 8 pixels, the eight rows of a slot (eight adjacent lanes) are
-// combined with three in-row DPP adds, and the slot's lane r = 0 turns the
-// sums into the ten 2D gradients and adds them to the tile's LDS accumulator
-// of that entry.
-//   sum gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2 and sum gs give the mean,
-//   conic and opacity gradients (d s / d mean = (A dx + B dy, B dx + C dy),
-//   d alpha / d o = gs / o); sum w G_c and sum w G_depth the colour and
-//   depth gradients.
+// combined with three in-row DPP adds, and the slot's first lane adds the ten
+// sums to the tile's LDS accumulator of that entry:
+//   sum gs, gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2 (the mean, conic and
+//   opacity gradients are linear in these: d s / d mean = (A dx + B dy,
+//   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
+//   (the colour and depth gradients).
+template <bool DEPTH>
 __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, int nslots,
                                            float (*acc)[kBatch], const float (&Gr)[4][8]) {
   const int lane = threadIdx.x & 63, e = lane >> 3, r = lane & 7;
@@ -281,13 +286,21 @@ __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, 
     for (int i = 0; i < 8; ++i) {
       const int p = r * 8 + i;
       const float gs = B.gs[w][e][p ^ e], wt = B.wt[w][e][p ^ e];
+      if (i == 0) {  // the sums start at the first term (no add of zero)
+        m0 = gs;
+        s0 = wt * Gr[0][0];
+        s1 = wt * Gr[1][0];
+        s2 = wt * Gr[2][0];
+        if (DEPTH) sd = wt * Gr[3][0];
+        continue;
+      }
       m0 += gs;
-      mi = __fmaf_rn(gs, (float)i, mi);
-      mii = __fmaf_rn(gs, (float)(i * i), mii);
+      mi = i == 1 ? gs : __fmaf_rn(gs, (float)i, mi);
+      mii = i == 1 ? gs : __fmaf_rn(gs, (float)(i * i), mii);
       s0 = __fmaf_rn(wt, Gr[0][i], s0);
       s1 = __fmaf_rn(wt, Gr[1][i], s1);
       s2 = __fmaf_rn(wt, Gr[2][i], s2);
-      sd = __fmaf_rn(wt, Gr[3][i], sd);
+      if (DEPTH) sd = __fmaf_rn(wt, Gr[3][i], sd);
     }
     mx = __fmaf_rn(x0, m0, mi);                                // sum gs dx
     mxx = __fmaf_rn(x0, __fmaf_rn(x0, m0, 2.0f * mi), mii);    // sum gs dx^2
@@ -299,32 +312,25 @@ __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, 
   // sum over the 8 lanes of a slot: mirror within the half row (i + (7 - i)),
   // then swap neighbours and pairs (quad_perm [1,0,3,2], [2,3,0,1])
 #pragma unroll
-  for (int q = 0; q < 10; ++q) {
+  for (int q = 0; q < (DEPTH ? 10 : 9); ++q) {
     v[q] += dpp_mov<0x141, 0xf>(v[q]);
     v[q] += dpp_mov<0xb1, 0xf>(v[q]);
     v[q] += dpp_mov<0x4e, 0xf>(v[q]);
   }
-  if (r == 0 && e < nslots) {
-    const float4 A = S.a[k];
-    const float4 Bb = S.b[k];
-    // A = -2 ca ln2, B = -cb ln2, C = -2 cc ln2
-    float g[10];
-    g[0] = -kLn2 * (2.0f * A.z * v[1] + A.w * v[2]);
-    g[1] = -kLn2 * (A.w * v[1] + 2.0f * Bb.x * v[2]);
-    g[2] = -0.5f * v[3];
-    g[3] = -v[4];
-    g[4] = -0.5f * v[5];
-    g[5] = v[0] / exp2_fast(Bb.y);  // d alpha / d o = alpha / o
-    g[6] = v[6];
-    g[7] = v[7];
-    g[8] = v[8];
-    g[9] = v[9];
+  if (e < nslots) {
+    // the slot's lane r = 0 adds the ten sums (the quadrant waves of one tile
+    // meet in these LDS atomics); the sums are linear in the gradients, which
+    // are formed once per (tile, entry) when the batch is written out
+    if (r == 0) {
 #pragma unroll
-    for (int q = 0; q < 10; ++q)
-      if (g[q] != 0.f) atomicAdd(&acc[q][k], g[q]);  // the quadrant waves of one tile meet here
+      for (int q = 0; q < (DEPTH ? 10 : 9); ++q)
+        if (v[q] != 0.f) atomicAdd(&acc[q][k], v[q]);
+    }
   }
 }
 
+// DEPTH: a depth gradient is given (without one, the depth sums are skipped)
+template <bool DEPTH>
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;
@@ -348,10 +354,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     G0 = bi.g_image[pix];
     G1 = bi.g_image[np + pix];
     G2 = bi.g_image[2 * np + pix];
-    GD = bi.g_depth ? bi.g_depth[pix] : 0.f;
+    GD = DEPTH ? bi.g_depth[pix] : 0.f;
     GA = bi.g_alpha ? bi.g_alpha[pix] : 0.f;
     // G . (everything the pixel outputs): colour incl. background, and depth
-    GI = G0 * bi.image[pix] + G1 * bi.image[np + pix] + G2 * bi.image[2 * np + pix] + GD * bi.depth[pix];
+    GI = G0 * bi.image[pix] + G1 * bi.image[np + pix] + G2 * bi.image[2 * np + pix] + (DEPTH ? GD * bi.depth[pix] : 0.f);
     Tf = bi.final_t[pix];
   }
   B.gs[w][0][lane] = G0;  // staged in the (not yet used) chunk table
@@ -390,20 +396,22 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     int nslots = 0;
     auto body = [&](int k, const float4 &Bv, float lg, bool take) {
       const float raw = exp2_fast(lg);
-      const float alpha = fminf(a.alpha_max, raw);
+      const float alpha = clamp_alpha(raw, a.alpha_max);
       const float2 C = S.c[k];
       const float wgt = take ? __fmul_rn(alpha, T) : 0.0f;
-      const float gc = G0 * Bv.w + G1 * C.x + G2 * C.y + GD * Bv.z;
+      const float gc = DEPTH ? G0 * Bv.w + G1 * C.x + G2 * C.y + GD * Bv.z : G0 * Bv.w + G1 * C.x + G2 * C.y;
       GP = __fmaf_rn(wgt, gc, GP);
       const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
       const float dalpha = T * gc + (GAT - GI + GP) * inv;
       const bool live = take && raw < a.alpha_max;  // the clamp passes no gradient
-      B.gs[w][nslots][lane ^ nslots] = live ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
-      B.wt[w][nslots][lane ^ nslots] = wgt;
+      // row nslots, column lane ^ nslots: flat index lane ^ (65 nslots) (lane < 64, nslots < 8)
+      const int sw = lane ^ (nslots * 65);
+      (&B.gs[w][0][0])[sw] = live ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
+      (&B.wt[w][0][0])[sw] = wgt;
       if (lane == 0) B.slot[w][nslots] = (uint8_t)k;
       T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
       if (++nslots == kChunk) {
-        bwd_phase2(S, B, w, nslots, sAcc, Gr);
+        bwd_phase2<DEPTH>(S, B, w, nslots, sAcc, Gr);
         nslots = 0;
       }
     };
@@ -427,13 +435,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
         if (ballot(tk) != 0) body(kk[j], BB[j], lg[j], tk);
       }
     }
-    if (nslots > 0) bwd_phase2(S, B, w, nslots, sAcc, Gr);
+    if (nslots > 0) bwd_phase2<DEPTH>(S, B, w, nslots, sAcc, Gr);
     __syncthreads();
-    // one plain store per (tile, entry): the pair's slot is owned by this tile
+    // one plain store per (tile, entry): the pair's slot is owned by this tile.
+    // From the sums (gs, gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2, w G_c, w G_depth):
+    // with A = -2 ca ln2, B = -cb ln2, C = -2 cc ln2,
+    //   d mean = -(A sum gs dx + B sum gs dy, B sum gs dx + C sum gs dy)
+    //   d (A, B, C) = -(sum gs dx^2 / 2, sum gs dx dy, sum gs dy^2 / 2)
+    //   d o = sum gs / o   (d alpha / d o = alpha / o)
     if (base + t < stop) {
+      const float4 A = S.a[t], Bb = S.b[t];
+      const float v1 = sAcc[1][t], v2 = sAcc[2][t];
       float4 *dst = (float4 *)(bi.pair_grad + (size_t)sSlot[t] * 12);
-      dst[0] = make_float4(sAcc[0][t], sAcc[1][t], sAcc[2][t], sAcc[3][t]);
-      dst[1] = make_float4(sAcc[4][t], sAcc[5][t], sAcc[6][t], sAcc[7][t]);
+      dst[0] = make_float4(-kLn2 * (2.0f * A.z * v1 + A.w * v2), -kLn2 * (A.w * v1 + 2.0f * Bb.x * v2),
+                           -0.5f * sAcc[3][t], -sAcc[4][t]);
+      dst[1] = make_float4(-0.5f * sAcc[5][t], sAcc[0][t] * exp2_fast(-Bb.y), sAcc[6][t], sAcc[7][t]);
       dst[2] = make_float4(sAcc[8][t], sAcc[9][t], 0.f, 0.f);
     }
   }
@@ -510,7 +526,10 @@ gs_status gs_render_bwd_pairs(const gs_camera *cam, const gs_raster_params *rp, 
   if (n_instances > 0) GS_REQUIRE(values && slots && pair_grad, "gs_render_bwd_pairs: NULL list argument");
   RenderArgs a = render_args(cam, rp, proj, values, ranges);
   BwdIn bi{image, depth, final_t, n_contrib, dL_dimage, dL_ddepth, dL_dalpha, slots, pair_grad};
-  GS_LAUNCH("render_bwd", k_render_bwd, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, bi);
+  if (dL_ddepth)
+    GS_LAUNCH("render_bwd", k_render_bwd<true>, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, bi);
+  else
+    GS_LAUNCH("render_bwd", k_render_bwd<false>, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, bi);
   return GS_OK;
 }
 
