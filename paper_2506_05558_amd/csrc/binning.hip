@@ -344,12 +344,16 @@ __global__ void k_visible_flags(const int32_t *tiles, int64_t n, uint64_t *flags
   }
 }
 
-// Visible Gaussians in index order: depth key, index, and a 16-byte record
-// for the pair emission -- the tile rect packed as (tx0 | ty0 << 16,
-// tx1 | ty1 << 16) and the first slot -- which then gathers one record per
-// Gaussian instead of a render record, two radii and a slot.
+constexpr uint32_t kNoSlot = 0xffffffffu;
+
+// Visible Gaussians in index order: depth key, index, a 16-byte record for
+// the pair emission -- the tile rect packed as (tx0 | ty0 << 16,
+// tx1 | ty1 << 16) and the first slot -- and the first slot itself.  A
+// Gaussian whose slots do not all fit (an asynchronous call short of
+// capacity) gets no first slot, so its adjoint reads no pair.
 __global__ void k_compact(const uint64_t *flags, const uint64_t *pos, const float *rec, const int32_t *radius,
-                          int64_t n, int W, int H, uint32_t *keys, uint32_t *vals, uint4 *rect) {
+                          int64_t n, int W, int H, uint32_t capacity, uint32_t *keys, uint32_t *vals, uint4 *rect,
+                          uint32_t *first_slot) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !flags[i]) return;
   const uint64_t ps = pos[i];
@@ -359,59 +363,73 @@ __global__ void k_compact(const uint64_t *flags, const uint64_t *pos, const floa
   vals[p] = (uint32_t)i;
   int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
   tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[i], radius[n + i], W, H, tx0, ty0, tx1, ty1);
-  rect[i] = make_uint4((uint32_t)tx0 | (uint32_t)ty0 << 16, (uint32_t)tx1 | (uint32_t)ty1 << 16,
-                       (uint32_t)(ps >> 32), 0u);
+  const uint32_t s0 = (uint32_t)(ps >> 32);
+  rect[i] = make_uint4((uint32_t)tx0 | (uint32_t)ty0 << 16, (uint32_t)tx1 | (uint32_t)ty1 << 16, s0, 0u);
+  const uint32_t npairs = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  first_slot[i] = (uint64_t)s0 + npairs <= capacity ? s0 : kNoSlot;
 }
 
-__global__ void k_gather_counts(const uint32_t *order, const uint32_t *count_dev, const int32_t *tiles, int64_t n,
-                                uint32_t *cnt) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  cnt[j] = j < (int64_t)*count_dev ? (uint32_t)tiles[order[j]] : 0u;
+// The visible Gaussians' emission records in depth order: the index-order
+// record with the Gaussian index in its spare word, so the emission reads
+// coalesced records; and the pair count of every block of kDupBlock
+// consecutive Gaussians, whose exclusive scan gives each block its first
+// pair.
+constexpr int kDupBlock = 256;
+__global__ __launch_bounds__(kDupBlock) void k_depth_records(const uint32_t *order, const uint32_t *count_dev,
+                                                             const uint4 *rect, int64_t n, uint4 *drec,
+                                                             uint32_t *block_pairs) {
+  const int64_t j = (int64_t)blockIdx.x * kDupBlock + threadIdx.x;
+  uint32_t np = 0;
+  if (j < (int64_t)*count_dev) {
+    const uint32_t g = order[j];
+    uint4 r = rect[g];
+    np = ((r.y & 0xffffu) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
+    r.w = g;
+    drec[j] = r;
+  }
+  uint32_t total;
+  block_excl_scan<uint32_t>(np, &total);
+  if (threadIdx.x == 0) block_pairs[blockIdx.x] = total;
 }
-
-constexpr uint32_t kNoSlot = 0xffffffffu;
 
 // Emits the pairs of the visible Gaussians in depth order: tile id,
-// Gaussian index and the pair's slot.  A workgroup takes 256 consecutive
-// Gaussians of the depth order, stages their offsets and tile rects in LDS,
-// and its lanes then walk the workgroup's pair range together, one pair per
-// lane (the owning Gaussian by binary search over the staged offsets), so
-// the stores are coalesced and a Gaussian with many tiles is spread over
-// many lanes.  Slots are numbered in Gaussian index order (islot = exclusive
-// prefix sum of tiles_touched), so the projection adjoint, one lane per
-// Gaussian, reads the per-pair gradients of a wave's Gaussians from one
-// contiguous range.
-constexpr int kDupBlock = 256;
-__global__ __launch_bounds__(kDupBlock) void k_duplicate(const uint32_t *order, const uint32_t *count_dev,
-                                                         const uint32_t *offs, const uint32_t *total,
-                                                         const uint4 *rect, int tiles_x, uint32_t capacity,
-                                                         uint32_t *tile_keys, uint32_t *vals, uint32_t *slots,
-                                                         uint32_t *first_slot) {
+// Gaussian index and the pair's slot.  A workgroup takes kDupBlock
+// consecutive Gaussians of the depth order, scans their pair counts on top
+// of the block's first pair, stages offsets and rects in LDS, and its lanes
+// then walk the workgroup's pair range together, one pair per lane (the
+// owning Gaussian by binary search over the staged offsets), so the stores
+// are coalesced and a Gaussian with many tiles is spread over many lanes.
+// Slots are numbered in Gaussian index order (islot = exclusive prefix sum
+// of tiles_touched), so the projection adjoint, one lane per Gaussian,
+// reads the per-pair gradients of a wave's Gaussians from one contiguous
+// range.  Pairs at or past capacity are dropped; a Gaussian whose slots do
+// not all fit writes its pairs to slot 0 (in bounds; such lists are to be
+// redone anyway).
+__global__ __launch_bounds__(kDupBlock) void k_duplicate(const uint4 *drec, const uint32_t *count_dev,
+                                                         const uint32_t *block_first, int tiles_x,
+                                                         uint32_t capacity, uint32_t *tile_keys, uint32_t *vals,
+                                                         uint32_t *slots) {
   __shared__ uint32_t sOff[kDupBlock + 1];
   __shared__ uint32_t sG[kDupBlock], sSlot[kDupBlock];
   __shared__ uint32_t sX[kDupBlock], sY[kDupBlock];
   const uint32_t V = *count_dev;
   const int64_t j0 = (int64_t)blockIdx.x * kDupBlock;
-  if (j0 >= (int64_t)V) return;
+  if (j0 >= (int64_t)V) return;  // uniform over the workgroup
   const int nj = (int)min((int64_t)kDupBlock, (int64_t)V - j0);
   const int t = threadIdx.x;
+  uint32_t np = 0;
   if (t < nj) {
-    const uint32_t g = order[j0 + t];
-    const uint4 r = rect[g];
-    const uint32_t npairs = ((r.y & 0xffffu) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
-    // a Gaussian whose slots do not all fit (an asynchronous call short of
-    // capacity) gets no first slot, so its adjoint reads no pair, and its
-    // pairs write to slot 0 (in bounds; such lists are to be redone anyway)
-    const bool fits = (uint64_t)r.z + npairs <= capacity;
-    first_slot[g] = fits ? r.z : kNoSlot;
-    sG[t] = g;
-    sSlot[t] = fits ? r.z : kNoSlot;
+    const uint4 r = drec[j0 + t];
+    np = ((r.y & 0xffffu) - (r.x & 0xffffu) + 1u) * ((r.y >> 16) - (r.x >> 16) + 1u);
+    sG[t] = r.w;
+    sSlot[t] = (uint64_t)r.z + np <= capacity ? r.z : kNoSlot;
     sX[t] = r.x;
     sY[t] = r.y;
-    sOff[t] = offs[j0 + t];
   }
-  if (t == 0) sOff[nj] = j0 + nj < (int64_t)V ? offs[j0 + nj] : *total;
+  uint32_t total;
+  const uint32_t first = block_first[blockIdx.x];
+  sOff[t] = first + block_excl_scan<uint32_t>(np, &total);
+  if (t == 0) sOff[nj] = first + total;
   __syncthreads();
   const uint32_t p0 = sOff[0], p1 = min(sOff[nj], capacity);
   for (uint32_t p = p0 + t; p < p1; p += kDupBlock) {
@@ -534,10 +552,10 @@ using namespace gsmi;
 namespace {
 
 struct BinLayout {
-  uint32_t *kA, *vA, *kB, *vB, *cnt, *offs, *hist, *rowtot, *scalars, *ktmp, *vtmp, *stmp;
+  uint32_t *kA, *vA, *kB, *vB, *block_pairs, *hist, *rowtot, *scalars, *ktmp, *vtmp, *stmp;
   uint64_t *total64;
   uint64_t *flags64, *pos64;
-  uint4 *rect;
+  uint4 *rect, *drec;
   void *scan_ws;
   size_t bytes;
 };
@@ -553,9 +571,9 @@ BinLayout bin_layout(void *ws, int64_t n, int64_t capacity) {
   L.vA = cv.take<uint32_t>(nn);
   L.kB = cv.take<uint32_t>(nn);
   L.vB = cv.take<uint32_t>(nn);
-  L.cnt = cv.take<uint32_t>(nn);
-  L.offs = cv.take<uint32_t>(nn);
+  L.block_pairs = cv.take<uint32_t>((nn + kDupBlock - 1) / kDupBlock);
   L.rect = cv.take<uint4>(nn);
+  L.drec = cv.take<uint4>(nn);
   const int64_t big = n > capacity ? n : capacity;
   L.hist = cv.take<uint32_t>(radix_hist_elems(big));
   L.rowtot = cv.take<uint32_t>(256);
@@ -622,16 +640,17 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
     GS_LAUNCH("bin_flags", k_visible_flags, grid1(n), 256, 0, s, proj->tiles_touched, n, L.flags64);
     if ((st = scan_exclusive_u64(L.flags64, L.pos64, n, L.total64, L.scan_ws, s)) != GS_OK) return st;
     GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, L.flags64, L.pos64, proj->rec, proj->radius, n, W, H,
-              L.kA, L.vA, L.rect);
+              (uint32_t)capacity, L.kA, L.vA, L.rect, first_slot);
     // 2. stable sort by depth (31 significant bits of a positive float)
     int shifts[8], widths[8];
     const int np = plan_passes(31, shifts, widths);
     uint32_t *kk[2] = {L.kA, L.kB}, *vv[2] = {L.vA, L.vB};
     if ((st = radix_sort(kk, vv, nullptr, V, n, np, shifts, widths, rw, s, &order_buf)) != GS_OK) return st;
     const uint32_t *order = vv[order_buf];
-    // 3. pair offsets in depth order
-    GS_LAUNCH("bin_counts", k_gather_counts, grid1(n), 256, 0, s, order, V, proj->tiles_touched, n, L.cnt);
-    if ((st = scan_exclusive(L.cnt, L.offs, n, Mdev, L.scan_ws, s)) != GS_OK) return st;
+    // 3. emission records in depth order; the first pair of every block of them
+    const int64_t dblocks = grid1(n, kDupBlock);
+    GS_LAUNCH("bin_counts", k_depth_records, dblocks, kDupBlock, 0, s, order, V, L.rect, n, L.drec, L.block_pairs);
+    if ((st = scan_exclusive(L.block_pairs, L.block_pairs, dblocks, Mdev, L.scan_ws, s)) != GS_OK) return st;
     if (!n_dev) {
       GS_CHECK_HIP(hipMemcpyAsync(&M, Mdev, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "read M");
       GS_CHECK_HIP(hipStreamSynchronize(s), "sync M");
@@ -663,9 +682,8 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
   } else {
     kk[0] = L.ktmp; vv[0] = L.vtmp; ss[0] = L.stmp; kk[1] = tile_ids; vv[1] = values; ss[1] = slots;
   }
-  const uint32_t *order = order_buf ? L.vB : L.vA;
-  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n, kDupBlock), kDupBlock, 0, s, order, V, L.offs, Mdev, L.rect, tx,
-            (uint32_t)capacity, kk[0], vv[0], ss[0], first_slot);
+  GS_LAUNCH("bin_duplicate", k_duplicate, grid1(n, kDupBlock), kDupBlock, 0, s, L.drec, V, L.block_pairs, tx,
+            (uint32_t)capacity, kk[0], vv[0], ss[0]);
   int res = 0;
   const uint32_t *mcount = n_dev ? n_dev : nullptr;
   if ((st = radix_sort(kk, vv, ss, mcount, mmax, np, shifts, widths, rw, s, &res)) != GS_OK) return st;

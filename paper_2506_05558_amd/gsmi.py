@@ -312,6 +312,12 @@ class BinSorter:
         raise GsError(GS_ERR_CAPACITY, "bin_sort: capacity did not converge")
 
 
+    def reserve(self, n: int, tiles: int, device) -> None:
+        """Allocates the buffers for n Gaussians and `tiles` tiles at the
+        current capacity, so that later calls (on any stream) allocate nothing."""
+        if self._key != (n, tiles, self.capacity) or self._bufs is None:
+            self._alloc(n, tiles, device)
+
     def sort_async(self, cam: Camera, proj: Projected, n_dev: torch.Tensor,
                    first_slot: Optional[torch.Tensor] = None) -> Binned:
         """gs_bin_sort_async: no host synchronisation; the pair count goes to

@@ -208,6 +208,20 @@ def test_window_view_sampled_crop():
         _check_image(f"window {crop[:2]}", frame, ref, crop)
 
 
+def test_binning_above_two_million_gaussians():
+    """More than 2^21 Gaussians: the pair counts of the emission blocks (one
+    per 256 depth-ordered Gaussians) outnumber one scan workgroup's 8192
+    elements and take the multi-workgroup scan."""
+    views = synth.trajectory(12, 8, 1920, 1080)
+    scene = synth.window_scene(12, views, 290_000)
+    assert scene.n > 2 ** 21 + 8192
+    view = views[5]
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj, binned, frame = gc.run_forward(cam, g)
+    _check_binning(view, proj, binned)
+
+
 def test_empty_and_culled():
     gs = gc.gpu()
     view, scene, _ = synth.tiny_scene(5)
