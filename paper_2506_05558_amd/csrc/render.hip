@@ -25,7 +25,9 @@
 namespace gsmi {
 namespace {
 
-constexpr int kBatch = 256;
+constexpr int kThreads = 256;  // one workgroup per tile, one lane per pixel
+constexpr int kBatch = 256;    // forward: tile-list entries staged per round
+constexpr int kBwdBatch = 128; // adjoint: small enough for per-wave accumulators (no LDS atomics)
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kFar = 1e30f;  // pixel coordinate of a stopped pixel
@@ -37,22 +39,24 @@ struct RenderArgs {
   const uint32_t *values, *ranges;
 };
 
+template <int NB>
 struct Stage {
-  float4 a[kBatch];         // mean x, y relative to the tile origin, ca, cb
-  float4 b[kBatch];         // cc, log2 opacity, depth, colour r
-  float2 c[kBatch];         // colour g, b
-  uint8_t list[4][kBatch];  // per quadrant: batch entries whose box meets it, in order
-  int cnt[4][4];            // [entry wave][quadrant] entries
+  float4 a[NB];         // mean x, y relative to the tile origin, ca, cb
+  float4 b[NB];         // cc, log2 opacity, depth, colour r
+  float2 c[NB];         // colour g, b
+  uint8_t list[4][NB];  // per quadrant: batch entries whose box meets it, in order
+  int cnt[4][4];        // [entry wave][quadrant] entries
 };
 
-// Stages entries [base, end) of the tile list (at most kBatch) and builds the
+// Stages entries [base, end) of the tile list (at most NB) and builds the
 // per-quadrant lists.  Called by all 256 lanes; contains two barriers.
+template <int NB>
 __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, uint32_t end, float ox, float oy,
-                                            Stage &S, uint32_t *gid_out) {
+                                            Stage<NB> &S, uint32_t *gid_out) {
   const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
   const uint32_t j = base + t;
   unsigned mask = 0;
-  if (j < end) {
+  if (t < NB && j < end) {
     const uint32_t gid = a.values[j];
     const float4 *r = (const float4 *)(a.rec + (size_t)gid * GS_REC_FLOATS);
     const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
@@ -108,10 +112,12 @@ __device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
 // multiple of 4, one 32-bit read): the same for every lane, so they live in
 // scalar registers and the loops stay uniform.  The loops take four entries
 // per turn, so all four exponents are in flight before the first body.
-__device__ __forceinline__ int list_count(const Stage &S, int w) {
+template <int NB>
+__device__ __forceinline__ int list_count(const Stage<NB> &S, int w) {
   return __builtin_amdgcn_readfirstlane(S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w]);
 }
-__device__ __forceinline__ int list_quad(const Stage &S, int w, int i) {
+template <int NB>
+__device__ __forceinline__ int list_quad(const Stage<NB> &S, int w, int i) {
   return __builtin_amdgcn_readfirstlane(*(const int *)&S.list[w][i]);
 }
 
@@ -151,14 +157,14 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const float fpy = (float)P.py;
   const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
-  __shared__ Stage S;
+  __shared__ Stage<kBatch> S;
 
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
   int last = 0, nev = 0, nsup = 0, ncomp = 0;
   int ntile = (int)(e - s);  // tile-list entries up to and including the stop
 
   for (uint32_t base = s; base < e; base += kBatch) {
-    if (__syncthreads_count(fpx == kFar) == kBatch) break;
+    if (__syncthreads_count(fpx == kFar) == kThreads) break;
     stage_batch(a, base, e, ox, oy, S, nullptr);
     const int cnt = list_count(S, w);
     if (ballot(fpx != kFar) == 0) continue;
@@ -269,8 +275,8 @@ struct BwdShared {
 //   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
 //   (the colour and depth gradients).
 template <bool DEPTH>
-__device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, int nslots,
-                                           float (*acc)[kBatch], const float (&Gr)[4][8]) {
+__device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch> &S, BwdShared &B, int w, int nslots,
+                                           float (*acc)[kBwdBatch], const float (&Gr)[4][8]) {
   const int lane = threadIdx.x & 63, e = lane >> 3, r = lane & 7;
   float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
   int k = 0;
@@ -317,15 +323,13 @@ __device__ __forceinline__ void bwd_phase2(const Stage &S, BwdShared &B, int w, 
     v[q] += dpp_mov<0xb1, 0xf>(v[q]);
     v[q] += dpp_mov<0x4e, 0xf>(v[q]);
   }
-  if (e < nslots) {
-    // the slot's lane r = 0 adds the ten sums (the quadrant waves of one tile
-    // meet in these LDS atomics); the sums are linear in the gradients, which
-    // are formed once per (tile, entry) when the batch is written out
-    if (r == 0) {
+  if (e < nslots && r == 0) {
+    // the slot's lane r = 0 stores the sums in this wave's own accumulator
+    // (an entry occurs at most once in a wave's list, so no other lane or
+    // wave writes there); the sums are linear in the gradients, which are
+    // formed once per (tile, entry) when the batch is written out
 #pragma unroll
-      for (int q = 0; q < (DEPTH ? 10 : 9); ++q)
-        if (v[q] != 0.f) atomicAdd(&acc[q][k], v[q]);
-    }
+    for (int q = 0; q < (DEPTH ? 10 : 9); ++q) acc[q][k] = v[q];
   }
 }
 
@@ -340,9 +344,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
   const float fpx = (float)P.px, fpy = (float)P.py;
 
-  __shared__ Stage S;
-  __shared__ uint32_t sSlot[kBatch];
-  __shared__ float sAcc[10][kBatch];
+  constexpr int NQ = DEPTH ? 10 : 9;  // accumulated sums per entry
+  __shared__ Stage<kBwdBatch> S;
+  __shared__ float sAcc[4][NQ][kBwdBatch];  // per wave
   __shared__ BwdShared B;
   __shared__ int sMax;
 
@@ -385,11 +389,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const float GAT = GA * Tf;
   const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
-  for (uint32_t base = s; base < stop; base += kBatch) {
-    __syncthreads();  // every wave is done with the previous batch's stage and accumulator
-#pragma unroll
-    for (int q = 0; q < 10; ++q) sAcc[q][t] = 0.f;
-    if (base + t < stop) sSlot[t] = bi.slots[base + t];
+  for (uint32_t base = s; base < stop; base += kBwdBatch) {
+    __syncthreads();  // every wave is done with the previous batch's stage and accumulators
+    {
+      float4 *z = (float4 *)&sAcc[0][0][0];
+      for (int i = t; i < 4 * NQ * kBwdBatch / 4; i += kThreads) z[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     stage_batch(a, base, stop, ox, oy, S, nullptr);
     const int cnt = list_count(S, w);
     const int idx0 = (int)(base - s);
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       if (lane == 0) B.slot[w][nslots] = (uint8_t)k;
       T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
       if (++nslots == kChunk) {
-        bwd_phase2<DEPTH>(S, B, w, nslots, sAcc, Gr);
+        bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);
         nslots = 0;
       }
     };
@@ -435,7 +440,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
         if (ballot(tk) != 0) body(kk[j], BB[j], lg[j], tk);
       }
     }
-    if (nslots > 0) bwd_phase2<DEPTH>(S, B, w, nslots, sAcc, Gr);
+    if (nslots > 0) bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);
     __syncthreads();
     // one plain store per (tile, entry): the pair's slot is owned by this tile.
     // From the sums (gs, gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2, w G_c, w G_depth):
@@ -443,18 +448,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     //   d mean = -(A sum gs dx + B sum gs dy, B sum gs dx + C sum gs dy)
     //   d (A, B, C) = -(sum gs dx^2 / 2, sum gs dx dy, sum gs dy^2 / 2)
     //   d o = sum gs / o   (d alpha / d o = alpha / o)
-    if (base + t < stop) {
+    if (t < kBwdBatch && base + t < stop) {
+      float v[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q)
+        v[q] = q < NQ ? (sAcc[0][q][t] + sAcc[1][q][t]) + (sAcc[2][q][t] + sAcc[3][q][t]) : 0.f;
       const float4 A = S.a[t], Bb = S.b[t];
-      const float v1 = sAcc[1][t], v2 = sAcc[2][t];
-      float4 *dst = (float4 *)(bi.pair_grad + (size_t)sSlot[t] * 12);
-      dst[0] = make_float4(-kLn2 * (2.0f * A.z * v1 + A.w * v2), -kLn2 * (A.w * v1 + 2.0f * Bb.x * v2),
-                           -0.5f * sAcc[3][t], -sAcc[4][t]);
-      dst[1] = make_float4(-0.5f * sAcc[5][t], sAcc[0][t] * exp2_fast(-Bb.y), sAcc[6][t], sAcc[7][t]);
-      dst[2] = make_float4(sAcc[8][t], sAcc[9][t], 0.f, 0.f);
+      float4 *dst = (float4 *)(bi.pair_grad + (size_t)bi.slots[base + t] * 12);
+      dst[0] = make_float4(-kLn2 * (2.0f * A.z * v[1] + A.w * v[2]), -kLn2 * (A.w * v[1] + 2.0f * Bb.x * v[2]),
+                           -0.5f * v[3], -v[4]);
+      dst[1] = make_float4(-0.5f * v[5], v[0] * exp2_fast(-Bb.y), v[6], v[7]);
+      dst[2] = make_float4(v[8], v[9], 0.f, 0.f);
     }
   }
   // entries past the last contributor of every pixel receive nothing from this tile
-  for (uint32_t j = stop + t; j < e; j += kBatch) {
+  for (uint32_t j = stop + t; j < e; j += kThreads) {
     float4 *dst = (float4 *)(bi.pair_grad + (size_t)bi.slots[j] * 12);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     dst[0] = z;
