@@ -58,6 +58,37 @@ __global__ __launch_bounds__(64) void k_loss_final(const double *partials, int n
   }
 }
 
+// The same update, four consecutive elements of one plane per lane (16-byte
+// loads and stores); used when the planes hold a multiple of four elements
+// and every array is 16-byte aligned.  A quad with no visible Gaussian is
+// not touched; in a partly visible quad the hidden elements are stored back
+// unchanged.
+__device__ __forceinline__ void adam_one(float gi, float &mi, float &vi, float &pi, float lr, float b1, float b2,
+                                         float eps, float c1, float c2) {
+  mi = b1 * mi + (1.f - b1) * gi;
+  vi = b2 * vi + (1.f - b2) * gi * gi;
+  pi -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_adam4(float *p, const float *g, float *m, float *v, float lr, float b1,
+                                               float b2, float eps, float c1, float c2, const int32_t *visible,
+                                               int64_t n_stride) {
+  const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (j >= n_stride) return;
+  const int64_t i = (int64_t)blockIdx.y * n_stride + j;
+  const int4 vis = visible ? *(const int4 *)(visible + j) : make_int4(1, 1, 1, 1);
+  if ((vis.x | vis.y | vis.z | vis.w) == 0) return;
+  const float4 G = *(const float4 *)(g + i);
+  float4 M = *(const float4 *)(m + i), V = *(const float4 *)(v + i), P = *(const float4 *)(p + i);
+  if (vis.x) adam_one(G.x, M.x, V.x, P.x, lr, b1, b2, eps, c1, c2);
+  if (vis.y) adam_one(G.y, M.y, V.y, P.y, lr, b1, b2, eps, c1, c2);
+  if (vis.z) adam_one(G.z, M.z, V.z, P.z, lr, b1, b2, eps, c1, c2);
+  if (vis.w) adam_one(G.w, M.w, V.w, P.w, lr, b1, b2, eps, c1, c2);
+  *(float4 *)(m + i) = M;
+  *(float4 *)(v + i) = V;
+  *(float4 *)(p + i) = P;
+}
+
 // Grid (plane chunks, planes): element i = plane * n_stride + j belongs to
 // Gaussian j, so the visibility test needs no division.
 __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
@@ -67,12 +98,11 @@ __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m
   const int64_t i = (int64_t)blockIdx.y * n_stride + j;
   if (j >= n_stride || i >= count) return;
   if (visible && !visible[j]) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  float mi = m[i], vi = v[i], pi = p[i];
+  adam_one(g[i], mi, vi, pi, lr, b1, b2, eps, c1, c2);
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  p[i] = pi;
 }
 
 // R's columns from the two 3-vectors of the 6D representation.
@@ -206,6 +236,14 @@ gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int6
   const int64_t stride = visible ? n_stride : count;
   const int64_t planes = (count + stride - 1) / stride;
   GS_REQUIRE(planes <= 65535, "gs_adam_step: count / n_stride exceeds 65535 planes");
+  const auto a16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
+  if (stride % 4 == 0 && count % stride == 0 && a16(param) && a16(grad) && a16(m) && a16(v) &&
+      (!visible || a16(visible))) {
+    const dim3 grid((unsigned)((stride / 4 + 255) / 256), (unsigned)planes);
+    GS_LAUNCH("adam", k_adam4, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, lr, beta1, beta2, eps, c1, c2,
+              visible, stride);
+    return GS_OK;
+  }
   const dim3 grid((unsigned)((stride + 255) / 256), (unsigned)planes);
   GS_LAUNCH("adam", k_adam, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, count, lr, beta1, beta2, eps, c1,
             c2, visible, stride);

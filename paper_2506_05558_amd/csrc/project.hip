@@ -305,19 +305,20 @@ struct GAcc {
 };
 
 // Adjoint of Gaussian i in one view where it is visible, in FP32 (the
-// forward decided visibility; the adjoint only chains gradients).  Adds
-// the parameter gradients to acc and writes this Gaussian's pose terms into
-// pose[12]: dL/dR (row-major) and dL/dt.
+// forward decided visibility; the adjoint only chains gradients), from the
+// summed 2D gradients g0..g2 and the view's colour record rgbz (its clamps).
+// Adds the parameter gradients to acc and writes this Gaussian's pose terms
+// into pose[12]: dL/dR (row-major) and dL/dt.
 template <int DEG>
 __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs &v, int64_t i, const float4 &g0,
-                                              const float4 &g1, const float4 &g2, const GParams<DEG> &P,
+                                              const float4 &g1, const float4 &g2, const float4 &rgbz,
+                                              const GParams<DEG> &P,
                                               GAcc<DEG> &acc, float pose[12]) {
   Geo<float> f;
   geometry<float, DEG>(m, v, P, f);
   const float mu[3] = {P.mu[0], P.mu[1], P.mu[2]};
   // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -):
   // the sums of the Gaussian's per-pair 2D gradients
-  const float4 rgbz = *(const float4 *)(v.rec + i * GS_REC_FLOATS + 8);
 
   // colour -> SH coefficients and view direction (no pose path, section 4.3).
   // A channel whose colour was clamped at 0 passes no gradient.
@@ -512,18 +513,27 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   __shared__ float4 stage[kBlock / 64][3][64];
   __shared__ float tb[12][kBlock];
   const int t = threadIdx.x, wv = t >> 6;
+  // each view's first slot and tile count are loaded one view ahead, and its
+  // colour record before the pair sums, so their latency overlaps work
+  uint32_t fs_next = valid && m.nv > 0 ? m.v[0].first_slot[i] : 0xffffffffu;
+  int t_next = valid && m.nv > 0 ? m.v[0].tiles[i] : 0;
   for (int vi = 0; vi < m.nv; ++vi) {
     const ViewArgs &v = m.v[vi];
     float term[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) term[k] = 0.f;
     // no first slot: the pairs did not fit the lists (see gs_bin_sort_async)
-    const uint32_t fs = valid ? v.first_slot[i] : 0xffffffffu;
-    const int nt = fs != 0xffffffffu ? v.tiles[i] : 0;
+    const uint32_t fs = fs_next;
+    const int nt = fs != 0xffffffffu ? t_next : 0;
+    if (vi + 1 < m.nv) {
+      fs_next = valid ? m.v[vi + 1].first_slot[i] : 0xffffffffu;
+      t_next = valid ? m.v[vi + 1].tiles[i] : 0;
+    }
+    const float4 rgbz = nt > 0 ? *(const float4 *)(v.rec + i * GS_REC_FLOATS + 8) : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 g0, g1, g2;
     pair_sums(v.pair_grad, fs, nt, stage[wv], g0, g1, g2);
     if (nt > 0) {
-      backward_view<DEG>(m, v, i, g0, g1, g2, P, acc, term);
+      backward_view<DEG>(m, v, i, g0, g1, g2, rgbz, P, acc, term);
       any = true;
     }
     // block reduction of this view's 12 pose partials in a fixed order
