@@ -234,7 +234,8 @@ def main():
             if count_pairs:
                 st = fr.stats.view(4, -1).to(torch.int64).sum(1).cpu().numpy()
                 pairs.append((int(st[0]), int(st[1]), int(st[2]), int(st[3]),
-                              int(fr.n_contrib.to(torch.int64).sum()), b.n_instances))
+                              int(fr.n_contrib.to(torch.int64).sum()), b.n_instances,
+                              int((vw.proj.tiles_touched > 0).sum())))
         gsmi.project_bwd_views(wviews, g, grads, params, ws=pbwd_ws)
         if use_async:
             torch.maximum(n_pairs_max, n_pairs, out=n_pairs_max)
@@ -308,6 +309,7 @@ def main():
     comp = sum(p[3] for p in pairs) / N_VIEWS
     walked = sum(p[4] for p in pairs) / N_VIEWS
     M = sum(p[5] for p in pairs) / N_VIEWS
+    visible_per_view = sum(p[6] for p in pairs) / N_VIEWS
 
     ms_step = elapsed * 1e3 / args.steps
     mpix = args.iters * N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
@@ -370,7 +372,8 @@ def main():
         "kernels_ms_per_step": {k: round(v["ms_total"], 4) for k, v in breakdown.items()},
         "ms_per_joint_iteration": round(ms_step / args.iters, 3),
         "pairs_per_view": {"tile_list_to_stop": tile_pairs, "evaluated": evaluated, "support": support,
-                           "composited": comp, "tile_list_walked_bwd": walked, "instances": M},
+                           "composited": comp, "tile_list_walked_bwd": walked, "instances": M,
+                           "visible_gaussians": visible_per_view},
         "psnr_start_end": [round(sum(psnr0) / N_VIEWS, 3), round(sum(psnr1) / N_VIEWS, 3)],
     }
     if not args.no_study:

@@ -39,20 +39,23 @@ struct RenderArgs {
   const uint32_t *values, *ranges;
 };
 
-template <int NB>
+// NB staged entries; NL cull blocks: 4 (the 8x8 quadrants, block q at
+// (q & 1, q >> 1)) or 16 (4x4 sub-blocks, block 4 q + g: sub-block
+// (g & 1, g >> 1) of quadrant q)
+template <int NB, int NL>
 struct Stage {
-  float4 a[NB];         // mean x, y relative to the tile origin, ca, cb
-  float4 b[NB];         // cc, log2 opacity, depth, colour r
-  float2 c[NB];         // colour g, b
-  uint8_t list[4][NB];  // per quadrant: batch entries whose box meets it, in order
-  int cnt[4][4];        // [entry wave][quadrant] entries
+  float4 a[NB];          // mean x, y relative to the tile origin, ca, cb
+  float4 b[NB];          // cc, log2 opacity, depth, colour r
+  float2 c[NB];          // colour g, b
+  uint8_t list[NL][NB];  // per cull block: batch entries whose box meets it, in order
+  int cnt[4][NL];        // [entry wave][cull block] entries
 };
 
 // Stages entries [base, end) of the tile list (at most NB) and builds the
-// per-quadrant lists.  Called by all 256 lanes; contains two barriers.
-template <int NB>
+// per-block lists.  Called by all 256 lanes; contains two barriers.
+template <int NB, int NL>
 __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, uint32_t end, float ox, float oy,
-                                            Stage<NB> &S, uint32_t *gid_out) {
+                                            Stage<NB, NL> &S, uint32_t *gid_out) {
   const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
   const uint32_t j = base + t;
   unsigned mask = 0;
@@ -70,23 +73,38 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
     // support box, widened so that FP32 rounding can never cull a pixel the
     // per-pixel test would accept
     const float hx = r3.x * (1.0f + 1e-4f) + 1e-3f, hy = r3.y * (1.0f + 1e-4f) + 1e-3f;
-    const bool x0 = mx - hx <= 7.0f && mx + hx >= 0.0f;
-    const bool x1 = mx - hx <= 15.0f && mx + hx >= 8.0f;
-    const bool y0 = my - hy <= 7.0f && my + hy >= 0.0f;
-    const bool y1 = my - hy <= 15.0f && my + hy >= 8.0f;
-    mask = (unsigned)(x0 && y0) | (unsigned)(x1 && y0) << 1 | (unsigned)(x0 && y1) << 2 | (unsigned)(x1 && y1) << 3;
+    if (NL == 4) {
+      const bool x0 = mx - hx <= 7.0f && mx + hx >= 0.0f;
+      const bool x1 = mx - hx <= 15.0f && mx + hx >= 8.0f;
+      const bool y0 = my - hy <= 7.0f && my + hy >= 0.0f;
+      const bool y1 = my - hy <= 15.0f && my + hy >= 8.0f;
+      mask = (unsigned)(x0 && y0) | (unsigned)(x1 && y0) << 1 | (unsigned)(x0 && y1) << 2 | (unsigned)(x1 && y1) << 3;
+    } else {
+      // columns / rows of 4 pixels met by the box, then their products
+      unsigned cx = 0, cy = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        cx |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
+        cy |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << c;
+      }
+#pragma unroll
+      for (int bl = 0; bl < 16; ++bl) {
+        const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
+        mask |= ((cx >> bx) & (cy >> by) & 1u) << bl;
+      }
+    }
   }
   const uint64_t lt = lanemask_lt();
-  int rank[4];
+  int rank[NL];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NL; ++q) {
     const uint64_t bal = ballot((mask >> q) & 1u);
     rank[q] = __popcll(bal & lt);
     if (lane == 0) S.cnt[ew][q] = __popcll(bal);
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NL; ++q) {
     if ((mask >> q) & 1u) {
       const int off = rank[q] + (ew > 0 ? S.cnt[0][q] : 0) + (ew > 1 ? S.cnt[1][q] : 0) + (ew > 2 ? S.cnt[2][q] : 0);
       S.list[q][off] = (uint8_t)t;
@@ -113,11 +131,11 @@ __device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
 // scalar registers and the loops stay uniform.  The loops take four entries
 // per turn, so all four exponents are in flight before the first body.
 template <int NB>
-__device__ __forceinline__ int list_count(const Stage<NB> &S, int w) {
+__device__ __forceinline__ int list_count(const Stage<NB, 4> &S, int w) {
   return __builtin_amdgcn_readfirstlane(S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w]);
 }
 template <int NB>
-__device__ __forceinline__ int list_quad(const Stage<NB> &S, int w, int i) {
+__device__ __forceinline__ int list_quad(const Stage<NB, 4> &S, int w, int i) {
   return __builtin_amdgcn_readfirstlane(*(const int *)&S.list[w][i]);
 }
 
@@ -126,11 +144,15 @@ struct Pixel {
   bool inside;
 };
 
+// SUB = false: lane l of wave w is pixel (l & 7, l >> 3) of quadrant w;
+// SUB = true: the lanes 16 g .. 16 g + 15 of wave w are the 4x4 sub-block g
+// of quadrant w, lane l its pixel (l & 3, (l >> 2) & 3).
+template <bool SUB>
 __device__ __forceinline__ Pixel pixel_of(int tile, int tiles_x, int W, int H) {
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, g = l >> 4;
   Pixel p;
-  p.px = (w & 1) * 8 + (l & 7);
-  p.py = (w >> 1) * 8 + (l >> 3);
+  p.px = SUB ? (w & 1) * 8 + (g & 1) * 4 + (l & 3) : (w & 1) * 8 + (l & 7);
+  p.py = SUB ? (w >> 1) * 8 + (g >> 1) * 4 + ((l >> 2) & 3) : (w >> 1) * 8 + (l >> 3);
   p.u = (tile % tiles_x) * GS_TILE + p.px;
   p.v = (tile / tiles_x) * GS_TILE + p.py;
   p.inside = p.u < W && p.v < H;
@@ -148,7 +170,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;  // uniform over the workgroup
   const int w = threadIdx.x >> 6;
-  const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
+  const Pixel P = pixel_of<true>(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
   const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
   // a pixel that has stopped (or lies outside the image) is moved far away:
@@ -157,16 +179,18 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const float fpy = (float)P.py;
   const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
-  __shared__ Stage<kBatch> S;
+  __shared__ Stage<kBatch, 16> S;
 
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
   int last = 0, nev = 0, nsup = 0, ncomp = 0;
   int ntile = (int)(e - s);  // tile-list entries up to and including the stop
+  const int blk = w * 4 + (threadIdx.x & 63) / 16;  // this lane's 4x4 cull block
 
   for (uint32_t base = s; base < e; base += kBatch) {
     if (__syncthreads_count(fpx == kFar) == kThreads) break;
     stage_batch(a, base, e, ox, oy, S, nullptr);
-    const int cnt = list_count(S, w);
+    // the length of this lane's sub-block list (the same over its 16 lanes)
+    const int cnt = S.cnt[0][blk] + S.cnt[1][blk] + S.cnt[2][blk] + S.cnt[3][blk];
     if (ballot(fpx != kFar) == 0) continue;
     const int idx0 = (int)(base - s);
     // returns true once every pixel of the wave has stopped
@@ -194,10 +218,14 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
       }
       return false;
     };
-    // four entries per turn: all exponents are evaluated before the first body
+    // the four sub-blocks of a wave walk their own lists side by side, four
+    // entries per turn (all exponents before the first body); a sub-block
+    // whose list is done or whose pixels have all stopped sits out
     bool all_done = false;
-    for (int i = 0; i < cnt && !all_done; i += 4) {
-      const int qd = list_quad(S, w, i);
+    for (int i = 0; !all_done; i += 4) {
+      const bool act = i < cnt && fpx != kFar;
+      if (ballot(act) == 0) break;
+      const int qd = act ? *(const int *)&S.list[blk][i] : 0;
       int kk[4];
       float4 BB[4];
       float lg[4];
@@ -210,9 +238,9 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        if (i + j >= cnt) break;
-        if (STATS) nev += fpx != kFar ? 1 : 0;
-        const bool tk = fpx != kFar && lg[j] >= l2min;  // a pixel that stopped earlier takes nothing more
+        const bool live = act && i + j < cnt && fpx != kFar;  // a pixel that stopped earlier takes nothing more
+        if (STATS) nev += live ? 1 : 0;
+        const bool tk = live && lg[j] >= l2min;
         if (ballot(tk) != 0 && body(kk[j], BB[j], lg[j], tk)) {
           all_done = true;
           break;
@@ -275,7 +303,7 @@ struct BwdShared {
 //   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
 //   (the colour and depth gradients).
 template <bool DEPTH>
-__device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch> &S, BwdShared &B, int w, int nslots,
+__device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch, 4> &S, BwdShared &B, int w, int nslots,
                                            float (*acc)[kBwdBatch], const float (&Gr)[4][8]) {
   const int lane = threadIdx.x & 63, e = lane >> 3, r = lane & 7;
   float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
@@ -339,13 +367,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
+  const Pixel P = pixel_of<false>(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
   const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
   const float fpx = (float)P.px, fpy = (float)P.py;
 
   constexpr int NQ = DEPTH ? 10 : 9;  // accumulated sums per entry
-  __shared__ Stage<kBwdBatch> S;
+  __shared__ Stage<kBwdBatch, 4> S;
   __shared__ float sAcc[4][NQ][kBwdBatch];  // per wave
   __shared__ BwdShared B;
   __shared__ int sMax;
