@@ -1,15 +1,17 @@
 // Per-tile compositing (forward) and its adjoint.
 //
 // One 256-lane workgroup (four wave64) per 16x16 tile, one lane per pixel;
-// wave w owns the 8x8 quadrant (w & 1, w >> 1) of the tile.  The tile's
-// depth-ordered list is walked in batches of 256 entries.  Each lane gathers
-// one 64-byte render record, converts it to tile-relative form and stages it
-// in LDS, and tests the entry's support box against the four quadrants;
-// ballots then build, per quadrant, the in-order list of the batch entries
-// whose box meets it.  Each wave walks only its own list, reading staged
-// entries with broadcast LDS loads, so a small Gaussian costs nothing in the
-// quadrants it cannot reach.  The workgroup leaves once all 256 pixels have
-// stopped; a wave leaves its list once its 64 pixels have.
+// wave w owns the 8x8 quadrant (w & 1, w >> 1) of the tile, and its four
+// 16-lane groups the 4x4 sub-blocks of that quadrant.  The tile's
+// depth-ordered list is walked in batches (256 entries forward, 120 in the
+// adjoint).  Each lane gathers one 64-byte render record, converts it to
+// tile-relative form and stages it in LDS, and tests the entry's support box
+// against the 16 sub-blocks; ballots then build, per sub-block, the in-order
+// list of the batch entries whose box meets it.  The four groups of a wave
+// walk their own lists side by side (one entry per group per turn), so a
+// small Gaussian costs nothing in the sub-blocks it cannot reach.  The
+// workgroup leaves once all 256 pixels have stopped; a wave leaves its lists
+// once its 64 pixels have.
 //
 // The 2D Gaussian is evaluated in the log2 domain: with d = pixel - mean,
 //   s  = -(A dx^2 + 2 B dx dy + C dy^2) / 2,       alpha = o exp(s)
@@ -17,9 +19,9 @@
 // with (ca, cb, cc) = -log2(e) (A/2, B, C/2) and log2 o folded in at
 // staging.  The skip test alpha >= alpha_min is taken on the exponent,
 // s2 + log2 o >= log2 alpha_min, so a pair that no pixel of the wave keeps
-// costs seven vector operations and no v_exp_f32.  The forward and the adjoint stage, cull and evaluate
-// with the same code and explicit operation order, so the adjoint retraces
-// the forward's decisions exactly.
+// costs seven vector operations and no v_exp_f32.  The forward and the
+// adjoint stage, cull and evaluate with the same code and explicit operation
+// order, so the adjoint retraces the forward's decisions exactly.
 #include "common.h"
 
 namespace gsmi {
@@ -27,7 +29,7 @@ namespace {
 
 constexpr int kThreads = 256;  // one workgroup per tile, one lane per pixel
 constexpr int kBatch = 256;    // forward: tile-list entries staged per round
-constexpr int kBwdBatch = 128; // adjoint: small enough for per-wave accumulators (no LDS atomics)
+constexpr int kBwdBatch = 120; // adjoint: small enough for per-wave accumulators (no LDS atomics)
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr float kFar = 1e30f;  // pixel coordinate of a stopped pixel
@@ -39,23 +41,23 @@ struct RenderArgs {
   const uint32_t *values, *ranges;
 };
 
-// NB staged entries; NL cull blocks: 4 (the 8x8 quadrants, block q at
-// (q & 1, q >> 1)) or 16 (4x4 sub-blocks, block 4 q + g: sub-block
-// (g & 1, g >> 1) of quadrant q)
-template <int NB, int NL>
+// NB staged entries and the lists of the 16 cull blocks: block 4 q + g is
+// the 4x4 sub-block (g & 1, g >> 1) of the 8x8 quadrant (q & 1, q >> 1)
+constexpr int kBlocks = 16;
+template <int NB>
 struct Stage {
-  float4 a[NB];          // mean x, y relative to the tile origin, ca, cb
-  float4 b[NB];          // cc, log2 opacity, depth, colour r
-  float2 c[NB];          // colour g, b
-  uint8_t list[NL][NB];  // per cull block: batch entries whose box meets it, in order
-  int cnt[4][NL];        // [entry wave][cull block] entries
+  float4 a[NB];               // mean x, y relative to the tile origin, ca, cb
+  float4 b[NB];               // cc, log2 opacity, depth, colour r
+  float2 c[NB];               // colour g, b
+  uint8_t list[kBlocks][NB];  // per cull block: batch entries whose box meets it, in order
+  int cnt[4][kBlocks];        // [entry wave][cull block] entries
 };
 
 // Stages entries [base, end) of the tile list (at most NB) and builds the
 // per-block lists.  Called by all 256 lanes; contains two barriers.
-template <int NB, int NL>
+template <int NB>
 __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, uint32_t end, float ox, float oy,
-                                            Stage<NB, NL> &S, uint32_t *gid_out) {
+                                            Stage<NB> &S, uint32_t *gid_out) {
   const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
   const uint32_t j = base + t;
   unsigned mask = 0;
@@ -73,38 +75,30 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
     // support box, widened so that FP32 rounding can never cull a pixel the
     // per-pixel test would accept
     const float hx = r3.x * (1.0f + 1e-4f) + 1e-3f, hy = r3.y * (1.0f + 1e-4f) + 1e-3f;
-    if (NL == 4) {
-      const bool x0 = mx - hx <= 7.0f && mx + hx >= 0.0f;
-      const bool x1 = mx - hx <= 15.0f && mx + hx >= 8.0f;
-      const bool y0 = my - hy <= 7.0f && my + hy >= 0.0f;
-      const bool y1 = my - hy <= 15.0f && my + hy >= 8.0f;
-      mask = (unsigned)(x0 && y0) | (unsigned)(x1 && y0) << 1 | (unsigned)(x0 && y1) << 2 | (unsigned)(x1 && y1) << 3;
-    } else {
-      // columns / rows of 4 pixels met by the box, then their products
-      unsigned cx = 0, cy = 0;
+    // columns / rows of 4 pixels met by the box, then their products
+    unsigned cx = 0, cy = 0;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        cx |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
-        cy |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << c;
-      }
+    for (int c = 0; c < 4; ++c) {
+      cx |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
+      cy |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << c;
+    }
 #pragma unroll
-      for (int bl = 0; bl < 16; ++bl) {
-        const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
-        mask |= ((cx >> bx) & (cy >> by) & 1u) << bl;
-      }
+    for (int bl = 0; bl < kBlocks; ++bl) {
+      const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
+      mask |= ((cx >> bx) & (cy >> by) & 1u) << bl;
     }
   }
   const uint64_t lt = lanemask_lt();
-  int rank[NL];
+  int rank[kBlocks];
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
+  for (int q = 0; q < kBlocks; ++q) {
     const uint64_t bal = ballot((mask >> q) & 1u);
     rank[q] = __popcll(bal & lt);
     if (lane == 0) S.cnt[ew][q] = __popcll(bal);
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < NL; ++q) {
+  for (int q = 0; q < kBlocks; ++q) {
     if ((mask >> q) & 1u) {
       const int off = rank[q] + (ew > 0 ? S.cnt[0][q] : 0) + (ew > 1 ? S.cnt[1][q] : 0) + (ew > 2 ? S.cnt[2][q] : 0);
       S.list[q][off] = (uint8_t)t;
@@ -126,33 +120,18 @@ __device__ __forceinline__ float clamp_alpha(float raw, float alpha_max) {
   return __builtin_amdgcn_fmed3f(raw, 0.0f, alpha_max);
 }
 
-// The length of wave w's quadrant list and its entries i .. i + 3 (i a
-// multiple of 4, one 32-bit read): the same for every lane, so they live in
-// scalar registers and the loops stay uniform.  The loops take four entries
-// per turn, so all four exponents are in flight before the first body.
-template <int NB>
-__device__ __forceinline__ int list_count(const Stage<NB, 4> &S, int w) {
-  return __builtin_amdgcn_readfirstlane(S.cnt[0][w] + S.cnt[1][w] + S.cnt[2][w] + S.cnt[3][w]);
-}
-template <int NB>
-__device__ __forceinline__ int list_quad(const Stage<NB, 4> &S, int w, int i) {
-  return __builtin_amdgcn_readfirstlane(*(const int *)&S.list[w][i]);
-}
-
 struct Pixel {
   int px, py, u, v;
   bool inside;
 };
 
-// SUB = false: lane l of wave w is pixel (l & 7, l >> 3) of quadrant w;
-// SUB = true: the lanes 16 g .. 16 g + 15 of wave w are the 4x4 sub-block g
-// of quadrant w, lane l its pixel (l & 3, (l >> 2) & 3).
-template <bool SUB>
+// The lanes 16 g .. 16 g + 15 of wave w are the 4x4 sub-block g of
+// quadrant w, lane l its pixel (l & 3, (l >> 2) & 3).
 __device__ __forceinline__ Pixel pixel_of(int tile, int tiles_x, int W, int H) {
   const int t = threadIdx.x, w = t >> 6, l = t & 63, g = l >> 4;
   Pixel p;
-  p.px = SUB ? (w & 1) * 8 + (g & 1) * 4 + (l & 3) : (w & 1) * 8 + (l & 7);
-  p.py = SUB ? (w >> 1) * 8 + (g >> 1) * 4 + ((l >> 2) & 3) : (w >> 1) * 8 + (l >> 3);
+  p.px = (w & 1) * 8 + (g & 1) * 4 + (l & 3);
+  p.py = (w >> 1) * 8 + (g >> 1) * 4 + ((l >> 2) & 3);
   p.u = (tile % tiles_x) * GS_TILE + p.px;
   p.v = (tile / tiles_x) * GS_TILE + p.py;
   p.inside = p.u < W && p.v < H;
@@ -170,7 +149,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;  // uniform over the workgroup
   const int w = threadIdx.x >> 6;
-  const Pixel P = pixel_of<true>(tile, a.tiles_x, a.W, a.H);
+  const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
   const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
   // a pixel that has stopped (or lies outside the image) is moved far away:
@@ -179,7 +158,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const float fpy = (float)P.py;
   const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
-  __shared__ Stage<kBatch, 16> S;
+  __shared__ Stage<kBatch> S;
 
   float T = 1.0f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f;
   int last = 0, nev = 0, nsup = 0, ncomp = 0;
@@ -280,46 +259,58 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-constexpr int kChunk = 8;    // entries per wave handed from phase 1 to phase 2
+constexpr int kChunk = 8;          // wave iterations handed from phase 1 to phase 2
+constexpr uint8_t kNoEntry = 0xff;  // chunk slot of a sub-block that had no entry
 
-// Per-wave chunk table, slot-major with the pixel index XOR-ed by the slot:
-// phase 1 (all lanes, one slot) writes a permutation of one row, phase 2
-// (lane = slot e, row r) reads [e][(8 r + i) ^ e] with at most two lanes per
-// bank, and without padding the workgroup's LDS (39 KB) lets four tiles
-// share a compute unit.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Per-wave chunk table, slot-major with the lane index XOR-ed by the slot:
+// phase 1 (all lanes, one slot) writes a permutation of one row; phase 2
+// (lane = sub-block g, slot e, half h) reads [e][(16 g + 8 h + i) ^ e], one
+// lane per bank.
 struct BwdShared {
-  float gs[4][kChunk][64];  // per wave, chunk slot, pixel p ^ slot: d L / d s  (natural-log exponent)
-  float wt[4][kChunk][64];  // per wave, chunk slot, pixel p ^ slot: blending weight alpha T
-  uint8_t slot[4][kChunk];  // per wave: batch entry of each chunk slot
+  float gs[4][kChunk][64];     // per wave, chunk slot, lane ^ slot: d L / d s  (natural-log exponent)
+  float wt[4][kChunk][64];     // per wave, chunk slot, lane ^ slot: blending weight alpha T
+  uint8_t slot[4][kChunk][4];  // per wave, chunk slot, sub-block: its batch entry (kNoEntry: none)
 };
 
-// Phase 2 of the adjoint for one wave: the chunk's entries are spread over
-// the lanes as (slot e = lane >> 3, pixel row r = lane & 7); each lane sums
-// its row's 8 pixels, the eight rows of a slot (eight adjacent lanes) are
-// combined with three in-row DPP adds, and the slot's first lane adds the ten
-// sums to the tile's LDS accumulator of that entry:
+// Phase 2 of the adjoint for one wave.  A chunk slot holds one entry per
+// 4x4 sub-block (the four sub-blocks of a wave walk their own lists), so
+// the lanes are (sub-block g = lane / 16, slot e, half h = lane % 2); each
+// lane sums the 8 pixels of rows 2 h, 2 h + 1 of its sub-block, the two
+// halves are combined with one DPP add, and lane h = 0 adds the sums to the
+// wave's own accumulator of that entry:
 //   sum gs, gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2 (the mean, conic and
 //   opacity gradients are linear in these: d s / d mean = (A dx + B dy,
 //   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
 //   (the colour and depth gradients).
+// Two sub-blocks of a wave may hold the same entry, so the four sub-blocks
+// add in turn (a read-modify-write per round, rounds kept in order); an
+// entry occurs at most once per sub-block list, so no two lanes of a round
+// share it, and no other wave writes this accumulator.
 template <bool DEPTH>
-__device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch, 4> &S, BwdShared &B, int w, int nslots,
+__device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch> &S, BwdShared &B, int w, int nslots,
                                            float (*acc)[kBwdBatch], const float (&Gr)[4][8]) {
-  const int lane = threadIdx.x & 63, e = lane >> 3, r = lane & 7;
-  float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, myy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
-  int k = 0;
-  if (e < nslots) {
-    k = B.slot[w][e];
+  constexpr int NQ = DEPTH ? 10 : 9;
+  const int lane = threadIdx.x & 63, g = lane >> 4, e = (lane >> 1) & 7, h = lane & 1;
+  float v[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) v[q] = 0.f;
+  const int k = e < nslots ? B.slot[w][e][g] : kNoEntry;
+  if (k != kNoEntry) {
     const float4 A = S.a[k];
-    // the lane's pixels p = 8 r + i share the row (dy) and have dx = x0 + i:
-    // the dx moments follow from sum gs, sum gs i and sum gs i^2
-    const float dy = (float)((w >> 1) * 8 + r) - A.y;
-    const float x0 = (float)((w & 1) * 8) - A.x;
-    float mi = 0.f, mii = 0.f;
+    // pixel i of the lane sits at (x0 + ix, y0 + iy) from the mean, ix = i % 4, iy = i / 4
+    const float x0 = (float)((w & 1) * 8 + (g & 1) * 4) - A.x;
+    const float y0 = (float)((w >> 1) * 8 + (g >> 1) * 4 + 2 * h) - A.y;
+    float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int p = r * 8 + i;
+      const int p = g * 16 + h * 8 + i;
       const float gs = B.gs[w][e][p ^ e], wt = B.wt[w][e][p ^ e];
+      const int ix = i & 3, iy = i >> 2;
       if (i == 0) {  // the sums start at the first term (no add of zero)
         m0 = gs;
         s0 = wt * Gr[0][0];
@@ -329,35 +320,40 @@ __device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch, 4> &S, BwdShar
         continue;
       }
       m0 += gs;
-      mi = i == 1 ? gs : __fmaf_rn(gs, (float)i, mi);
-      mii = i == 1 ? gs : __fmaf_rn(gs, (float)(i * i), mii);
+      if (ix == 1) mx = i == 1 ? gs : mx + gs;
+      if (ix > 1) mx = __fmaf_rn(gs, (float)ix, mx);
+      if (ix == 1) mxx = i == 1 ? gs : mxx + gs;
+      if (ix > 1) mxx = __fmaf_rn(gs, (float)(ix * ix), mxx);
+      if (iy) my = i == 4 ? gs : my + gs;
+      if (iy && ix == 1) mxy = gs;
+      if (iy && ix > 1) mxy = __fmaf_rn(gs, (float)ix, mxy);
       s0 = __fmaf_rn(wt, Gr[0][i], s0);
       s1 = __fmaf_rn(wt, Gr[1][i], s1);
       s2 = __fmaf_rn(wt, Gr[2][i], s2);
       if (DEPTH) sd = __fmaf_rn(wt, Gr[3][i], sd);
     }
-    mx = __fmaf_rn(x0, m0, mi);                                // sum gs dx
-    mxx = __fmaf_rn(x0, __fmaf_rn(x0, m0, 2.0f * mi), mii);    // sum gs dx^2
-    mxy = mx * dy;
-    my = m0 * dy;
-    myy = my * dy;
+    // about the mean: dx = x0 + ix, dy = y0 + iy (iy^2 = iy)
+    v[0] = m0;
+    v[1] = __fmaf_rn(x0, m0, mx);                                               // sum gs dx
+    v[2] = __fmaf_rn(y0, m0, my);                                               // sum gs dy
+    v[3] = __fmaf_rn(x0, __fmaf_rn(x0, m0, 2.0f * mx), mxx);                    // sum gs dx^2
+    v[4] = __fmaf_rn(x0, __fmaf_rn(y0, m0, my), __fmaf_rn(y0, mx, mxy));        // sum gs dx dy
+    v[5] = __fmaf_rn(y0, __fmaf_rn(y0, m0, 2.0f * my), my);                     // sum gs dy^2
+    v[6] = s0;
+    v[7] = s1;
+    v[8] = s2;
+    v[9] = sd;
   }
-  float v[10] = {m0, mx, my, mxx, mxy, myy, s0, s1, s2, sd};
-  // sum over the 8 lanes of a slot: mirror within the half row (i + (7 - i)),
-  // then swap neighbours and pairs (quad_perm [1,0,3,2], [2,3,0,1])
+  // the two halves of a (sub-block, slot) are neighbouring lanes
 #pragma unroll
-  for (int q = 0; q < (DEPTH ? 10 : 9); ++q) {
-    v[q] += dpp_mov<0x141, 0xf>(v[q]);
-    v[q] += dpp_mov<0xb1, 0xf>(v[q]);
-    v[q] += dpp_mov<0x4e, 0xf>(v[q]);
-  }
-  if (e < nslots && r == 0) {
-    // the slot's lane r = 0 stores the sums in this wave's own accumulator
-    // (an entry occurs at most once in a wave's list, so no other lane or
-    // wave writes there); the sums are linear in the gradients, which are
-    // formed once per (tile, entry) when the batch is written out
+  for (int q = 0; q < NQ; ++q) v[q] += dpp_mov<0xb1, 0xf>(v[q]);  // quad_perm [1,0,3,2]
 #pragma unroll
-    for (int q = 0; q < (DEPTH ? 10 : 9); ++q) acc[q][k] = v[q];
+  for (int r = 0; r < 4; ++r) {
+    if (g == r && h == 0 && k != kNoEntry) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q][k] += v[q];
+    }
+    wave_lds_fence();  // the rounds stay separate and in order
   }
 }
 
@@ -366,14 +362,14 @@ template <bool DEPTH>
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const Pixel P = pixel_of<false>(tile, a.tiles_x, a.W, a.H);
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, g = lane >> 4, blk = w * 4 + g;
+  const Pixel P = pixel_of(tile, a.tiles_x, a.W, a.H);
   const uint32_t s = a.ranges[2 * tile], e = a.ranges[2 * tile + 1];
   const float ox = (float)((tile % a.tiles_x) * GS_TILE), oy = (float)((tile / a.tiles_x) * GS_TILE);
   const float fpx = (float)P.px, fpy = (float)P.py;
 
   constexpr int NQ = DEPTH ? 10 : 9;  // accumulated sums per entry
-  __shared__ Stage<kBwdBatch, 4> S;
+  __shared__ Stage<kBwdBatch> S;
   __shared__ float sAcc[4][NQ][kBwdBatch];  // per wave
   __shared__ BwdShared B;
   __shared__ int sMax;
@@ -389,7 +385,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
     GD = DEPTH ? bi.g_depth[pix] : 0.f;
     GA = bi.g_alpha ? bi.g_alpha[pix] : 0.f;
     // G . (everything the pixel outputs): colour incl. background, and depth
-    GI = G0 * bi.image[pix] + G1 * bi.image[np + pix] + G2 * bi.image[2 * np + pix] + (DEPTH ? GD * bi.depth[pix] : 0.f);
+    GI = G0 * bi.image[pix] + G1 * bi.image[np + pix] + G2 * bi.image[2 * np + pix] +
+         (DEPTH ? GD * bi.depth[pix] : 0.f);
     Tf = bi.final_t[pix];
   }
   B.gs[w][0][lane] = G0;  // staged in the (not yet used) chunk table
@@ -398,14 +395,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   B.gs[w][3][lane] = GD;
   if (t == 0) sMax = 0;
   __syncthreads();
-  // phase 2 lane (slot e, row r) sums over the pixels 8 r .. 8 r + 7 of its
-  // wave: their upstream gradients stay in registers for the whole tile
+  // the phase 2 lane (sub-block g, half h) sums over the lanes 16 g + 8 h ..
+  // 16 g + 8 h + 7 of its wave: their upstream gradients stay in registers
   float Gr[4][8];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Gr[c][i] = B.gs[w][c][(lane & 7) * 8 + i];
-  const int wmax = __builtin_amdgcn_readfirstlane(wave_max(ncon));
+    for (int i = 0; i < 8; ++i) Gr[c][i] = B.gs[w][c][g * 16 + (lane & 1) * 8 + i];
+  // the last contributor of any pixel of the sub-block, and of the tile
+  int gmax = ncon;
+#pragma unroll
+  for (int off = 1; off < 16; off <<= 1) gmax = max(gmax, __shfl_xor(gmax, off, 64));
+  const int wmax = __builtin_amdgcn_readfirstlane(wave_max(gmax));
   if (lane == 0 && wmax > 0) atomicMax(&sMax, wmax);
   __syncthreads();
   const uint32_t stop = min(s + (uint32_t)sMax, e);
@@ -424,10 +425,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       for (int i = t; i < 4 * NQ * kBwdBatch / 4; i += kThreads) z[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     stage_batch(a, base, stop, ox, oy, S, nullptr);
-    const int cnt = list_count(S, w);
+    // the length of this lane's sub-block list (the same over its 16 lanes)
+    const int cnt = S.cnt[0][blk] + S.cnt[1][blk] + S.cnt[2][blk] + S.cnt[3][blk];
     const int idx0 = (int)(base - s);
     int nslots = 0;
-    auto body = [&](int k, const float4 &Bv, float lg, bool take) {
+    auto body = [&](int k, const float4 &Bv, float lg, bool take, bool live) {
       const float raw = exp2_fast(lg);
       const float alpha = clamp_alpha(raw, a.alpha_max);
       const float2 C = S.c[k];
@@ -436,22 +438,25 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       GP = __fmaf_rn(wgt, gc, GP);
       const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
       const float dalpha = T * gc + (GAT - GI + GP) * inv;
-      const bool live = take && raw < a.alpha_max;  // the clamp passes no gradient
+      const bool livegrad = take && raw < a.alpha_max;  // the clamp passes no gradient
       // row nslots, column lane ^ nslots: flat index lane ^ (65 nslots) (lane < 64, nslots < 8)
       const int sw = lane ^ (nslots * 65);
-      (&B.gs[w][0][0])[sw] = live ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
+      (&B.gs[w][0][0])[sw] = livegrad ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
       (&B.wt[w][0][0])[sw] = wgt;
-      if (lane == 0) B.slot[w][nslots] = (uint8_t)k;
+      if ((lane & 15) == 0) B.slot[w][nslots][g] = live ? (uint8_t)k : kNoEntry;
       T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
       if (++nslots == kChunk) {
         bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);
         nslots = 0;
       }
     };
-    // four entries per turn: all exponents are evaluated before the first body
-    for (int i = 0; i < cnt; i += 4) {
-      const int qd = list_quad(S, w, i);
-      if (idx0 + (qd & 255) >= wmax) break;  // lists ascend: no pixel of this wave reaches further
+    // the four sub-blocks of a wave walk their own lists side by side, four
+    // entries per turn (all exponents before the first body); a sub-block
+    // whose list is done, or past the last contributor of its pixels, sits out
+    for (int i = 0;; i += 4) {
+      const int qd = i < cnt ? *(const int *)&S.list[blk][i] : 0;
+      const bool act = i < cnt && idx0 + (qd & 255) < gmax;  // lists ascend
+      if (ballot(act) == 0) break;
       int kk[4];
       float4 BB[4];
       float lg[4];
@@ -464,8 +469,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool tk = i + j < cnt && idx0 + kk[j] < ncon && lg[j] >= l2min;
-        if (ballot(tk) != 0) body(kk[j], BB[j], lg[j], tk);
+        const bool live = act && i + j < cnt;
+        const bool tk = live && idx0 + kk[j] < ncon && lg[j] >= l2min;
+        if (ballot(tk) != 0) body(kk[j], BB[j], lg[j], tk, live);
       }
     }
     if (nslots > 0) bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);
