@@ -59,7 +59,7 @@ __global__ __launch_bounds__(64) void k_loss_final(const double *partials, int n
 }
 
 // The same update, four consecutive elements of one plane per lane (16-byte
-// loads and stores); used when the planes hold a multiple of four elements
+// non-temporal loads and stores); used when the planes hold a multiple of four elements
 // and every array is 16-byte aligned.  A quad with no visible Gaussian is
 // not touched; in a partly visible quad the hidden elements are stored back
 // unchanged.
@@ -70,6 +70,17 @@ __device__ __forceinline__ void adam_one(float gi, float &mi, float &vi, float &
   pi -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
 }
 
+// Streaming 16-byte accesses that bypass cache retention: each element of
+// the optimiser state is touched once per step.
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_stream(const float *q) {
+  const v4f x = __builtin_nontemporal_load((const v4f *)q);
+  return make_float4(x.x, x.y, x.z, x.w);
+}
+__device__ __forceinline__ void store_stream(float *q, const float4 &x) {
+  __builtin_nontemporal_store((v4f){x.x, x.y, x.z, x.w}, (v4f *)q);
+}
+
 __global__ __launch_bounds__(256) void k_adam4(float *p, const float *g, float *m, float *v, float lr, float b1,
                                                float b2, float eps, float c1, float c2, const int32_t *visible,
                                                int64_t n_stride) {
@@ -78,15 +89,15 @@ __global__ __launch_bounds__(256) void k_adam4(float *p, const float *g, float *
   const int64_t i = (int64_t)blockIdx.y * n_stride + j;
   const int4 vis = visible ? *(const int4 *)(visible + j) : make_int4(1, 1, 1, 1);
   if ((vis.x | vis.y | vis.z | vis.w) == 0) return;
-  const float4 G = *(const float4 *)(g + i);
-  float4 M = *(const float4 *)(m + i), V = *(const float4 *)(v + i), P = *(const float4 *)(p + i);
+  const float4 G = load_stream(g + i);
+  float4 M = load_stream(m + i), V = load_stream(v + i), P = load_stream(p + i);
   if (vis.x) adam_one(G.x, M.x, V.x, P.x, lr, b1, b2, eps, c1, c2);
   if (vis.y) adam_one(G.y, M.y, V.y, P.y, lr, b1, b2, eps, c1, c2);
   if (vis.z) adam_one(G.z, M.z, V.z, P.z, lr, b1, b2, eps, c1, c2);
   if (vis.w) adam_one(G.w, M.w, V.w, P.w, lr, b1, b2, eps, c1, c2);
-  *(float4 *)(m + i) = M;
-  *(float4 *)(v + i) = V;
-  *(float4 *)(p + i) = P;
+  store_stream(m + i, M);
+  store_stream(v + i, V);
+  store_stream(p + i, P);
 }
 
 // Grid (plane chunks, planes): element i = plane * n_stride + j belongs to
