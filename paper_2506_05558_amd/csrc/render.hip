@@ -281,8 +281,8 @@ struct BwdShared {
 // 4x4 sub-block (the four sub-blocks of a wave walk their own lists), so
 // the lanes are (sub-block g = lane / 16, slot e, half h = lane % 2); each
 // lane sums the 8 pixels of rows 2 h, 2 h + 1 of its sub-block, the two
-// halves are combined with one DPP add, and lane h = 0 adds the sums to the
-// wave's own accumulator of that entry:
+// halves are combined with one DPP add, and the two lanes add the sums (five
+// each) to the wave's own accumulator of that entry:
 //   sum gs, gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2 (the mean, conic and
 //   opacity gradients are linear in these: d s / d mean = (A dx + B dy,
 //   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
@@ -347,11 +347,18 @@ __device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch> &S, BwdShared 
   // the two halves of a (sub-block, slot) are neighbouring lanes
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] += dpp_mov<0xb1, 0xf>(v[q]);  // quad_perm [1,0,3,2]
+  // both lanes of a (sub-block, slot) hold the sums: lane h adds sums
+  // 5 h .. 5 h + 4
+  float u[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) u[j] = h ? (5 + j < NQ ? v[5 + j] : 0.f) : v[j];
+  float *row = &acc[5 * h][0];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    if (g == r && h == 0 && k != kNoEntry) {
+    if (g == r && k != kNoEntry) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) acc[q][k] += v[q];
+      for (int j = 0; j < 5; ++j)
+        if (5 * h + j < NQ) row[j * kBwdBatch + k] += u[j];
     }
     wave_lds_fence();  // the rounds stay separate and in order
   }
