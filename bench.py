@@ -38,8 +38,8 @@ W_IMG, H_IMG, N_VIEWS, PER_VIEW, SH_DEG, SEED = 1920, 1080, 8, 250_000, 3, 2506
 ITERS, SPAWN_K, MLP_BATCH = 30, 100_000, 4096
 
 # MI355X peaks (published): HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s with
-# packed FP32, which this build does not emit: unpacked VALU issue is
-# 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
+# packed FP32, which the kernels are compiled without: unpacked VALU issue
+# is 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -346,6 +346,9 @@ def main():
         roofline["kernel"] = dominant
         roofline["traffic"] = measured_traffic(dominant)
     others = {k: roof(k) for k in ["render_fwd", "render_bwd", "project", "project_bwd"] if k in kernels}
+    for k, r in others.items():
+        if r is not None:
+            r["traffic"] = measured_traffic(k)
 
     out = {
         "metric": "fwd+bwd Mpix/s @1080p 2M Gaussians; steps-to-PSNR learned-init vs plain",
