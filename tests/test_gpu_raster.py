@@ -208,6 +208,25 @@ def test_window_view_sampled_crop():
         _check_image(f"window {crop[:2]}", frame, ref, crop)
 
 
+def test_large_frame_2560x1440_sampled_crops():
+    """The largest frame shape of the scale-out scenario: 2560x1440 (14,400
+    tiles) with 3M resident Gaussians (8 x 375k ray-seeded, SH 3): exact
+    binning and sampled crops (centre, bottom-right corner) against
+    the oracle."""
+    views = synth.trajectory(13, 8, 2560, 1440)
+    scene = synth.window_scene(13, views, 375_000)
+    view = views[4]
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj, binned, frame = gc.run_forward(cam, g)
+    _check_binning(view, proj, binned)
+    ocam, og = gc.oracle_inputs(view, scene)
+    op = orc.project(ocam, og)
+    for crop in [(1256, 696, 40, 40), (2528, 1416, 32, 24)]:
+        ref = orc.render(ocam, op, crop=crop, flag_rel=FLAG_REL)
+        _check_image(f"2560x1440 {crop[:2]}", frame, ref, crop)
+
+
 def test_binning_above_two_million_gaussians():
     """More than 2^21 Gaussians: the pair counts of the emission blocks (one
     per 256 depth-ordered Gaussians) outnumber one scan workgroup's 8192
