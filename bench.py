@@ -262,7 +262,7 @@ def main():
 
     names = ["project", "bin_flags", "bin_compact", "radix_hist", "radix_scatter", "scan", "bin_counts",
              "bin_duplicate", "bin_ranges", "bin_fill", "render_fwd", "loss_l1", "loss_final", "render_bwd",
-             "project_bwd", "pose_reduce", "adam", "zero", "mark_visible", "pose_6d", "pose_6d_bwd",
+             "project_bwd", "project_bwd_sh", "pose_reduce", "adam", "zero", "mark_visible", "pose_6d", "pose_6d_bwd",
              "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
 
     def read_profile():
@@ -276,7 +276,7 @@ def main():
 
     # timed region: HIP events bracket only the kernels whose rooflines are reported
     gsmi.profile_reset()
-    gsmi.profile_select(["render_fwd", "render_bwd", "project", "project_bwd"])
+    gsmi.profile_select(["render_fwd", "render_bwd", "project", "project_bwd", "project_bwd_sh"])
     gsmi.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -317,6 +317,9 @@ def main():
     def roof(name):
         k = kernels[name]
         t = k["ms_per_launch"] * 1e-3
+        if name == "project_bwd" and "project_bwd_sh" in kernels:
+            # the adjoint is two passes (geometry, then SH) per call
+            t = (k["ms_total"] + kernels["project_bwd_sh"]["ms_total"]) / k["launches"] * 1e-3
         if name == "render_fwd":
             ops = support * FWD_PAIR + comp * FWD_COMP
             a = ops / t / 1e12

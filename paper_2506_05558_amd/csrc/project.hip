@@ -102,6 +102,7 @@ struct MultiArgs {
   const float *means, *log_scales, *quats, *opac, *sh;
   float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
   double *partials;                // [nv][gridDim.x][12] pose partial sums
+  float *gc;                       // [nv][3][n] clamped colour gradient per view (adjoint workspace)
   ViewArgs v[kMaxViews];
 };
 
@@ -113,7 +114,7 @@ struct GParams {
   float sh[NB * 3];  // [k][channel]
 };
 
-template <int DEG>
+template <int DEG, bool SH = true>
 __device__ __forceinline__ void load_params(const MultiArgs &m, int64_t i, GParams<DEG> &P) {
   const int64_t n = m.n;
 #pragma unroll
@@ -123,8 +124,10 @@ __device__ __forceinline__ void load_params(const MultiArgs &m, int64_t i, GPara
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.ls[k] = m.log_scales[k * n + i];
   P.logit = m.opac[i];
+  if (SH) {
 #pragma unroll
-  for (int k = 0; k < GParams<DEG>::NB * 3; ++k) P.sh[k] = m.sh[(int64_t)k * n + i];
+    for (int k = 0; k < GParams<DEG>::NB * 3; ++k) P.sh[k] = m.sh[(int64_t)k * n + i];
+  }
 }
 
 // Geometry of one Gaussian in one view: FP64 for the forward projection
@@ -298,58 +301,32 @@ __global__ __launch_bounds__(kBlock) void k_project_views(MultiArgs m) {
 
 // ---------------------------------------------------------------- backward
 // Gradient accumulators of one Gaussian over the views of a launch.
-template <int DEG>
 struct GAcc {
   float gm[3], gl[3], gq[4], go;
-  float gsh[GParams<DEG>::NB * 3];
 };
 
 // Adjoint of Gaussian i in one view where it is visible, in FP32 (the
 // forward decided visibility; the adjoint only chains gradients), from the
 // summed 2D gradients g0..g2 and the view's colour record rgbz (its clamps).
-// Adds the parameter gradients to acc and writes this Gaussian's pose terms
-// into pose[12]: dL/dR (row-major) and dL/dt.
+// Adds the geometry and opacity gradients to acc, writes this Gaussian's
+// pose terms into pose[12] (dL/dR row-major, dL/dt) and its clamped colour
+// gradient into gc[3], which the SH pass chains to the SH coefficients and
+// the view direction.
 template <int DEG>
 __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs &v, int64_t i, const float4 &g0,
                                               const float4 &g1, const float4 &g2, const float4 &rgbz,
-                                              const GParams<DEG> &P,
-                                              GAcc<DEG> &acc, float pose[12]) {
+                                              const GParams<DEG> &P, GAcc &acc, float pose[12],
+                                              float gc[3]) {
   Geo<float> f;
   geometry<float, DEG>(m, v, P, f);
   const float mu[3] = {P.mu[0], P.mu[1], P.mu[2]};
   // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -):
   // the sums of the Gaussian's per-pair 2D gradients
 
-  // colour -> SH coefficients and view direction (no pose path, section 4.3).
-  // A channel whose colour was clamped at 0 passes no gradient.
-  {
-    const float gc0 = rgbz.x > 0.f ? g1.z : 0.f;
-    const float gc1 = rgbz.y > 0.f ? g1.w : 0.f;
-    const float gc2 = rgbz.z > 0.f ? g2.x : 0.f;
-    float d[3], dinv;
-    view_dir<float>(f.R, f.t, mu, d, dinv);
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-#pragma unroll
-    for (int k = 0; k < GParams<DEG>::NB; ++k) {
-      float Y, ax, ay, az;
-      sh_term<float>(k, d[0], d[1], d[2], Y, ax, ay, az);
-      acc.gsh[k * 3] += gc0 * Y;
-      acc.gsh[k * 3 + 1] += gc1 * Y;
-      acc.gsh[k * 3 + 2] += gc2 * Y;
-      if (DEG > 0) {
-        const float wk = gc0 * P.sh[k * 3] + gc1 * P.sh[k * 3 + 1] + gc2 * P.sh[k * 3 + 2];
-        gx += wk * ax;
-        gy += wk * ay;
-        gz += wk * az;
-      }
-    }
-    if (DEG > 0) {
-      const float radial = gx * d[0] + gy * d[1] + gz * d[2];
-      acc.gm[0] += (gx - radial * d[0]) * dinv;
-      acc.gm[1] += (gy - radial * d[1]) * dinv;
-      acc.gm[2] += (gz - radial * d[2]) * dinv;
-    }
-  }
+  // colour: a channel whose colour was clamped at 0 passes no gradient
+  gc[0] = rgbz.x > 0.f ? g1.z : 0.f;
+  gc[1] = rgbz.y > 0.f ? g1.w : 0.f;
+  gc[2] = rgbz.z > 0.f ? g2.x : 0.f;
 
   {
     const float o = real_rcp(1.0f + __expf(-P.logit));
@@ -500,15 +477,13 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool valid = i < m.n;
   GParams<DEG> P;
-  GAcc<DEG> acc;
-  if (valid) load_params<DEG>(m, i, P);
+  GAcc acc;
+  if (valid) load_params<DEG, false>(m, i, P);
 #pragma unroll
   for (int k = 0; k < 3; ++k) acc.gm[k] = acc.gl[k] = 0.f;
 #pragma unroll
   for (int k = 0; k < 4; ++k) acc.gq[k] = 0.f;
   acc.go = 0.f;
-#pragma unroll
-  for (int k = 0; k < GParams<DEG>::NB * 3; ++k) acc.gsh[k] = 0.f;
   bool any = false;
   __shared__ float4 stage[kBlock / 64][3][64];
   __shared__ float tb[12][kBlock];
@@ -532,9 +507,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
     const float4 rgbz = nt > 0 ? *(const float4 *)(v.rec + i * GS_REC_FLOATS + 8) : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 g0, g1, g2;
     pair_sums(v.pair_grad, fs, nt, stage[wv], g0, g1, g2);
+    float gc[3] = {0.f, 0.f, 0.f};
     if (nt > 0) {
-      backward_view<DEG>(m, v, i, g0, g1, g2, rgbz, P, acc, term);
+      backward_view<DEG>(m, v, i, g0, g1, g2, rgbz, P, acc, term, gc);
       any = true;
+    }
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) m.gc[(int64_t)(vi * 3 + c) * m.n + i] = gc[c];
     }
     // block reduction of this view's 12 pose partials in a fixed order
     // (deterministic): transposed through LDS, 16 lanes per component each
@@ -568,8 +548,72 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) m.gq[k * n + i] += acc.gq[k];
   m.go[i] += acc.go;
+}
+
+// The SH part of the projection adjoint, a pass of its own so that the SH
+// coefficients and their gradients (96 registers at degree 3) do not share
+// a lane with the geometry adjoint: per Gaussian and view, from the clamped
+// colour gradient gc of the geometry pass, dL/d sh_k += gc Y_k(d) and the
+// view-direction part of the mean gradient (the view direction carries no
+// pose gradient, section 4.3).  Runs after k_project_bwd_views on the same
+// views.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
+  constexpr int NB = GParams<DEG>::NB;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= m.n) return;
+  const int64_t n = m.n;
+  float mu[3], sh[NB * 3], gsh[NB * 3], gm[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-  for (int k = 0; k < GParams<DEG>::NB * 3; ++k) m.gsh[(int64_t)k * n + i] += acc.gsh[k];
+  for (int k = 0; k < 3; ++k) mu[k] = m.means[k * n + i];
+#pragma unroll
+  for (int k = 0; k < NB * 3; ++k) {
+    sh[k] = DEG > 0 ? m.sh[(int64_t)k * n + i] : 0.f;
+    gsh[k] = 0.f;
+  }
+  bool any = false;
+  for (int vi = 0; vi < m.nv; ++vi) {
+    const float gc0 = m.gc[(int64_t)(vi * 3) * n + i], gc1 = m.gc[(int64_t)(vi * 3 + 1) * n + i],
+                gc2 = m.gc[(int64_t)(vi * 3 + 2) * n + i];
+    if (gc0 == 0.f && gc1 == 0.f && gc2 == 0.f) continue;  // not visible, or every channel clamped
+    any = true;
+    const ViewArgs &v = m.v[vi];
+    float R[9], t[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = v.pose[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) t[k] = v.pose[9 + k];
+    float d[3], dinv;
+    view_dir<float>(R, t, mu, d, dinv);
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      float Y, ax, ay, az;
+      sh_term<float>(k, d[0], d[1], d[2], Y, ax, ay, az);
+      gsh[k * 3] += gc0 * Y;
+      gsh[k * 3 + 1] += gc1 * Y;
+      gsh[k * 3 + 2] += gc2 * Y;
+      if (DEG > 0) {
+        const float wk = gc0 * sh[k * 3] + gc1 * sh[k * 3 + 1] + gc2 * sh[k * 3 + 2];
+        gx += wk * ax;
+        gy += wk * ay;
+        gz += wk * az;
+      }
+    }
+    if (DEG > 0) {
+      const float radial = gx * d[0] + gy * d[1] + gz * d[2];
+      gm[0] += (gx - radial * d[0]) * dinv;
+      gm[1] += (gy - radial * d[1]) * dinv;
+      gm[2] += (gz - radial * d[2]) * dinv;
+    }
+  }
+  if (!any) return;
+  if (DEG > 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.gm[k * n + i] += gm[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NB * 3; ++k) m.gsh[(int64_t)k * n + i] += gsh[k];
 }
 
 struct PoseOut {
@@ -700,6 +744,12 @@ gs_status launch_project_bwd(const MultiArgs &m, int deg, hipStream_t s) {
     case 2: GS_LAUNCH("project_bwd", k_project_bwd_views<2>, blocks, kBlock, 0, s, m); break;
     default: GS_LAUNCH("project_bwd", k_project_bwd_views<3>, blocks, kBlock, 0, s, m); break;
   }
+  switch (deg) {
+    case 0: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<0>, blocks, kBlock, 0, s, m); break;
+    case 1: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<1>, blocks, kBlock, 0, s, m); break;
+    case 2: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<2>, blocks, kBlock, 0, s, m); break;
+    default: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<3>, blocks, kBlock, 0, s, m); break;
+  }
   bool pose = false;
   PoseOuts outs;
   for (int v = 0; v < kMaxViews; ++v) {
@@ -760,7 +810,9 @@ gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *byt
   GS_REQUIRE(bytes && n >= 0 && n_views >= 0, "gs_project_bwd_views_workspace: bad argument");
   const int64_t blocks = proj_blocks(n);
   const int nv = std::max(1, std::min(kMaxViews, (int)n_views));
-  *bytes = align_up(sizeof(double) * 12 * (size_t)nv * (size_t)(blocks > 0 ? blocks : 1));
+  // pose partials, then the per-view clamped colour gradients
+  *bytes = align_up(sizeof(double) * 12 * (size_t)nv * (size_t)(blocks > 0 ? blocks : 1)) +
+           align_up(sizeof(float) * 3 * (size_t)nv * (size_t)(n > 0 ? n : 1));
   return GS_OK;
 }
 
@@ -790,6 +842,8 @@ gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_r
     m.gm = grads->means; m.gl = grads->log_scales; m.gq = grads->quats; m.go = grads->opacity_logits;
     m.gsh = grads->sh;
     m.partials = (double *)ws;
+    m.gc = (float *)((char *)ws + align_up(sizeof(double) * 12 * (size_t)std::max(1, std::min(kMaxViews, (int)n_views)) *
+                                           (size_t)proj_blocks(g->n)));
     m.nv = std::min(kMaxViews, n_views - v0);
     for (int k = 0; k < m.nv; ++k) {
       const gs_view &gv = views[v0 + k];
