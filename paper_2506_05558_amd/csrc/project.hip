@@ -572,9 +572,15 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
     gsh[k] = 0.f;
   }
   bool any = false;
+  // the colour gradients are loaded one view ahead
+  float n0 = m.gc[i], n1 = m.gc[n + i], n2 = m.gc[2 * n + i];
   for (int vi = 0; vi < m.nv; ++vi) {
-    const float gc0 = m.gc[(int64_t)(vi * 3) * n + i], gc1 = m.gc[(int64_t)(vi * 3 + 1) * n + i],
-                gc2 = m.gc[(int64_t)(vi * 3 + 2) * n + i];
+    const float gc0 = n0, gc1 = n1, gc2 = n2;
+    if (vi + 1 < m.nv) {
+      n0 = m.gc[(int64_t)(vi * 3 + 3) * n + i];
+      n1 = m.gc[(int64_t)(vi * 3 + 4) * n + i];
+      n2 = m.gc[(int64_t)(vi * 3 + 5) * n + i];
+    }
     if (gc0 == 0.f && gc1 == 0.f && gc2 == 0.f) continue;  // not visible, or every channel clamped
     any = true;
     const ViewArgs &v = m.v[vi];
