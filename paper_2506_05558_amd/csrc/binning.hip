@@ -8,7 +8,7 @@
 // order of a stable sort of (tile << 32 | depth bits) over pairs emitted in
 // Gaussian-index order, at about a third of the key traffic.
 //
-// Radix pass layout: every workgroup (16 waves) owns 4096 consecutive keys,
+// Radix pass layout: every workgroup (8 waves) owns 2048 consecutive keys,
 // each wave a contiguous run of 256.  The histogram kernel counts each
 // block's digits into the digit-major table [digit][block]; one workgroup
 // per digit scans its row in place and records the row total.  The scatter
@@ -25,10 +25,12 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanBlock * kScanItems;  // 4096
-constexpr int kRadixBlock = 1024;                   // 16 waves
+// 8 waves of 256 keys: short per-wave ranking chains, and small enough LDS
+// (24-32 KB) that the sorts of one view run beside another view's renders
+constexpr int kRadixBlock = 512;                    // 8 waves
 constexpr int kWaves = kRadixBlock / 64;
 constexpr int kWaveKeys = 256;                      // keys per wave in a radix pass
-constexpr int kBlockKeys = kWaves * kWaveKeys;      // keys per workgroup (4096)
+constexpr int kBlockKeys = kWaves * kWaveKeys;      // keys per workgroup (2048)
 
 // ------------------------------------------------------------------- scan
 template <class T>
