@@ -191,13 +191,13 @@ def main():
         n_spawned.append(gsmi.spawn_init(cam_new, new_image, new_depth, spawned, 0, rendered=rendered_new, sp=sp,
                                          mlp_packed=packed, ws=spawn_ws))
 
-    def keyframe_step(iters, use_async=False):
+    def keyframe_step(iters, use_async=False, overlap=True):
         spawn_new_frame()
         for _ in range(iters):
-            step(use_async=use_async)
+            step(use_async=use_async, overlap=overlap)
         trainer.step(train_x, train_y)
 
-    def step(count_pairs=False, use_async=False):
+    def step(count_pairs=False, use_async=False, overlap=True):
         state["step"] += 1
         k = state["step"]
         gsmi.zero_(gflat)
@@ -207,13 +207,14 @@ def main():
         gsmi.pose_from_6d(x6, poses)
         gsmi.project_views(wviews, g, params)
         if use_async:  # no host synchronisation: the pair counts stay on the device
+            ss = side if overlap else torch.cuda.current_stream()
             ev_proj.record()
-            with torch.cuda.stream(side):
-                side.wait_event(ev_proj)
+            with torch.cuda.stream(ss):
+                ss.wait_event(ev_proj)
                 lists = []
                 for i, (cam, vw) in enumerate(zip(cams, wviews)):
                     lists.append(view_sorters[i].sort_async(cam, vw.proj, n_pairs[i:i + 1], first_slot=vw.first_slot))
-                    ev_sorted[i].record(side)
+                    ev_sorted[i].record(ss)
         for i, (cam, vw) in enumerate(zip(cams, wviews)):
             if use_async:
                 torch.cuda.current_stream().wait_event(ev_sorted[i])
@@ -300,6 +301,15 @@ def main():
     gsmi.profile_enable(False)
     breakdown = read_profile()
 
+    # one more keyframe step (not timed) with the sorts on the main stream, nothing beside the
+    # renders: the roofline kernels' uncontended durations (what a kernel trace shows)
+    gsmi.profile_select(["render_fwd", "render_bwd", "project", "project_bwd", "project_bwd_sh"])
+    gsmi.profile_enable(True)
+    keyframe_step(args.iters, use_async=True, overlap=False)
+    torch.cuda.synchronize()
+    gsmi.profile_enable(False)
+    kernels_solo = read_profile()
+
     # one extra step (not timed) with pair counters for the algorithmic work
     step(count_pairs=True)
     torch.cuda.synchronize()
@@ -314,12 +324,12 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     mpix = args.iters * N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
 
-    def roof(name):
-        k = kernels[name]
+    def roof(name, ks=kernels):
+        k = ks[name]
         t = k["ms_per_launch"] * 1e-3
-        if name == "project_bwd" and "project_bwd_sh" in kernels:
+        if name == "project_bwd" and "project_bwd_sh" in ks:
             # the adjoint is two passes (geometry, then SH) per call
-            t = (k["ms_total"] + kernels["project_bwd_sh"]["ms_total"]) / k["launches"] * 1e-3
+            t = (k["ms_total"] + ks["project_bwd_sh"]["ms_total"]) / k["launches"] * 1e-3
         if name == "render_fwd":
             ops = support * FWD_PAIR + comp * FWD_COMP
             a = ops / t / 1e12
@@ -348,6 +358,13 @@ def main():
     if roofline is not None:
         roofline["kernel"] = dominant
         roofline["traffic"] = measured_traffic(dominant)
+        roofline["ms_per_launch"] = kernels[dominant]["ms_per_launch"]
+    # the same kernel without the side-stream sorts running beside it
+    solo = roof(dominant, kernels_solo) if dominant in kernels_solo else None
+    if solo is not None:
+        solo["kernel"] = dominant
+        solo["traffic"] = measured_traffic(dominant)
+        solo["ms_per_launch"] = kernels_solo[dominant]["ms_per_launch"]
     others = {k: roof(k) for k in ["render_fwd", "render_bwd", "project", "project_bwd"] if k in kernels}
     for k, r in others.items():
         if r is not None:
@@ -374,6 +391,7 @@ def main():
                    "iters_per_keyframe": args.iters, "spawn_k": SPAWN_K, "mlp_batch": MLP_BATCH},
         "spawned_per_keyframe": n_spawned[-1] if n_spawned else None,
         "roofline": roofline,
+        "roofline_uncontended": solo,
         "kernel_rooflines": others,
         "kernels_ms_per_step": {k: round(v["ms_total"], 4) for k, v in breakdown.items()},
         "ms_per_joint_iteration": round(ms_step / args.iters, 3),
