@@ -425,6 +425,31 @@ def test_multi_view_ten_views_equal_single_view_sum():
         assert torch.allclose(a, b, rtol=1e-4, atol=1e-6 * float(b.abs().max()))
 
 
+def test_adjoint_is_deterministic():
+    """Two runs of the compositing adjoint and of the projection adjoint on
+    the same inputs give bit-identical gradients (no atomics anywhere)."""
+    gs = gc.gpu()
+    view, scene = synth.single_view(4, 640, 400, 200_000)
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj, binned, frame = gc.run_forward(cam, g)
+    gimg = torch.randn((3, view.height, view.width), device="cuda", generator=torch.Generator("cuda").manual_seed(4))
+    gimg *= 1e-3
+    outs = []
+    for _ in range(2):
+        pg = torch.zeros((binned.n_instances, 12), device="cuda")
+        gs.render_bwd_pairs(cam, proj, binned, frame, gimg, pg)
+        grads = g.zeros_like()
+        d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
+        gs.project_bwd_views([gs.View(cam, proj, pg, binned.first_slot, d_pose)], g, grads)
+        torch.cuda.synchronize()
+        outs.append((pg, grads, d_pose))
+    assert torch.equal(outs[0][0], outs[1][0])
+    for a, b in zip(outs[0][1].tensors(), outs[1][1].tensors()):
+        assert torch.equal(a, b)
+    assert torch.equal(outs[0][2], outs[1][2])
+
+
 def test_async_sort_equals_sync_and_reports_overflow():
     """gs_bin_sort_async gives the lists of gs_bin_sort when they fit; short
     of capacity (forced from the host) it still reports the pair count, keeps
