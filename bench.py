@@ -200,7 +200,8 @@ def main():
     def step(count_pairs=False, use_async=False, overlap=True):
         state["step"] += 1
         k = state["step"]
-        gsmi.zero_(gflat)
+        if not (use_async and overlap):
+            gsmi.zero_(gflat)
         gsmi.zero_(d_pose)
         gsmi.zero_(dx6)
         gsmi.zero_(visible)
@@ -215,6 +216,8 @@ def main():
                 for i, (cam, vw) in enumerate(zip(cams, wviews)):
                     lists.append(view_sorters[i].sort_async(cam, vw.proj, n_pairs[i:i + 1], first_slot=vw.first_slot))
                     ev_sorted[i].record(ss)
+                    if i == 0 and overlap:
+                        gsmi.zero_(gflat)  # next read by the projection adjoint, after the last view's event
         for i, (cam, vw) in enumerate(zip(cams, wviews)):
             if use_async:
                 torch.cuda.current_stream().wait_event(ev_sorted[i])
