@@ -85,6 +85,18 @@ def test_workspace_queries(lib):
     assert lib.gs_bin_sort_workspace(-1, 0, C.byref(sz)) == 1
     lib.gs_render_bwd_workspace.argtypes = [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]
     assert lib.gs_render_bwd_workspace(1000, 3000, C.byref(sz)) == 0 and sz.value >= 48 * 3000
+    # the projection adjoint keeps each view's clamped colour gradient (3 floats per Gaussian) between
+    # its geometry and SH passes, for up to eight views per pass
+    lib.gs_project_bwd_views_workspace.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+    for nv, per in [(1, 1), (8, 8), (20, 8)]:
+        assert lib.gs_project_bwd_views_workspace(100_000, nv, C.byref(sz)) == 0
+        assert sz.value >= 12 * per * 100_000
+    # larger inputs never need less
+    sizes = []
+    for n, cap in [(10, 10), (10_000, 10), (10_000, 100_000), (1_000_000, 100_000)]:
+        assert lib.gs_bin_sort_workspace(n, cap, C.byref(sz)) == 0
+        sizes.append(sz.value)
+    assert sizes == sorted(sizes)
 
 
 def test_spawn_taps_equal_the_oracle_bitwise(lib):
