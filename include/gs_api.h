@@ -255,7 +255,11 @@ gs_status gs_render_bwd_pairs(const gs_camera *cam, const gs_raster_params *rp, 
 /* The projection adjoint over n_views views: per Gaussian, the 2D gradients
  * of its pairs in each view are chained to its parameters and summed over
  * the views into grads (accumulated), and each view's pose gradient goes to
- * its dL_dpose / dL_dtwist.  ws: gs_project_bwd_views_workspace(n, n_views). */
+ * its dL_dpose / dL_dtwist.  Runs as two passes per eight views (geometry,
+ * then SH).  ws: gs_project_bwd_views_workspace(n, n_views) bytes of DEVICE
+ * scratch (FP64 pose partials per workgroup, and each view's clamped colour
+ * gradient, 12 bytes per Gaussian, handed from the first pass to the
+ * second); its contents are not kept between calls. */
 gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *bytes);
 gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream);
