@@ -311,6 +311,7 @@ def main():
     keyframe_step(args.iters, use_async=True, overlap=False)
     torch.cuda.synchronize()
     gsmi.profile_enable(False)
+    gsmi.profile_select(None)
     kernels_solo = read_profile()
 
     # one extra step (not timed) with pair counters for the algorithmic work

@@ -193,6 +193,7 @@ def time_kernels(cam, img, depth, k, packed, X, batch, reps=20):
         tr.step(Xb, Yb)
     torch.cuda.synchronize()
     gsmi.profile_reset()
+    gsmi.profile_select(["mlp_infer", "mlp_train"])
     gsmi.profile_enable(True)
     for _ in range(reps):
         gsmi.spawn_mlp(cam, img, depth, pix, packed, g, 0)
@@ -200,6 +201,7 @@ def time_kernels(cam, img, depth, k, packed, X, batch, reps=20):
         tr.step(Xb, Yb)
     torch.cuda.synchronize()
     gsmi.profile_enable(False)
+    gsmi.profile_select(None)
     infer_ms, n_inf = gsmi.profile_read("mlp_infer")
     train_ms, n_tr = gsmi.profile_read("mlp_train")
     gsmi.profile_reset()
