@@ -146,6 +146,7 @@ def main():
     frame = gsmi.Frame(f(3, H, W), f(H, W), f(H, W), f(H, W), f(H, W, dt=torch.int32))
     g_img = f(3, H, W)
     loss_ws = torch.empty(1 << 16, dtype=torch.uint8, device=dev)
+    fwd_l1_ws = torch.empty(gsmi.render_fwd_l1_workspace(W, H), dtype=torch.uint8, device=dev)
     cams = [gsmi.Camera(W, H, v.fx, v.fy, v.cx, v.cy, poses[i]) for i, v in enumerate(views)]
     # per-view buffers of the window: projections, first slots and pair gradients live until the
     # projection adjoint, which runs once over all views
@@ -229,8 +230,12 @@ def main():
             if count_pairs:
                 fr = gsmi.Frame(frame.image, frame.depth, frame.alpha, frame.final_t, frame.n_contrib,
                                 torch.empty((4, H, W), dtype=torch.int32, device=dev))
-            gsmi.render_fwd(cam, vw.proj, b, params, out=fr)
-            gsmi.loss_l1(fr.image, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i], loss_ws)
+            if count_pairs:  # the pair counters: forward, then the loss
+                gsmi.render_fwd(cam, vw.proj, b, params, out=fr)
+                gsmi.loss_l1(fr.image, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i], loss_ws)
+            else:  # the L1 loss formed in the forward's epilogue
+                gsmi.render_fwd_l1(cam, vw.proj, b, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i],
+                                   fwd_l1_ws, params, out=fr)
             if vw.pair_grad is None or vw.pair_grad.shape[0] < b.n_instances:
                 vw.pair_grad = torch.empty((int(b.n_instances * 1.25) + 1024, 12), dtype=torch.float32, device=dev)
             gsmi.render_bwd_pairs(cam, vw.proj, b, fr, g_img, vw.pair_grad, params=params)

@@ -186,7 +186,7 @@ gs_status gs_bin_sort_async(const gs_camera *cam, const gs_projected *proj, int6
  *   stats [4][H][W] (NULL = not written), per pixel: plane 0 the tile-list
  *   entries up to and including the one that stopped the pixel (the whole
  *   list if it did not stop), plane 1 the entries evaluated (after culling
- *   entries whose support box misses the pixel's 8x8 quadrant), plane 2 the
+ *   entries whose support box misses the pixel's 4x4 sub-block), plane 2 the
  *   entries with alpha >= alpha_min up to and including the stopping one,
  *   plane 3 the entries composited -- the pair counts the work is measured
  *   in.
@@ -194,6 +194,22 @@ gs_status gs_bin_sort_async(const gs_camera *cam, const gs_projected *proj, int6
 gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                         const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,
                         float *final_t, int32_t *n_contrib, int32_t *stats, void *stream);
+
+/* gs_render_fwd with the L1 photometric loss of the joint optimisation
+ * (section 4.3) formed in the same kernel while each pixel's colour is in
+ * registers: writes everything gs_render_fwd writes (no stats) and what
+ * gs_loss_l1(image, target, grad_scale) writes -- dL_dimage = grad_scale *
+ * sign(image - target) with exact zeros, bit-identical to gs_loss_l1's, and
+ * sums[0] = sum |image - target|, sums[1] = sum (image - target)^2 (DEVICE
+ * double[2], overwritten; summed per tile in FP64, then over the tiles in a
+ * fixed order, so they equal gs_loss_l1's up to FP64 rounding).
+ * target, dL_dimage: DEVICE [3][H][W].  ws: DEVICE scratch of
+ * gs_render_fwd_l1_workspace(width, height) bytes (16 per tile). */
+gs_status gs_render_fwd_l1_workspace(int32_t width, int32_t height, size_t *bytes);
+gs_status gs_render_fwd_l1(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                           const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,
+                           float *final_t, int32_t *n_contrib, const float *target, float grad_scale,
+                           float *dL_dimage, double *sums, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- gs_render_bwd ------------------------------------------------------
  * Adjoint of gs_project + gs_render_fwd for upstream gradients of image

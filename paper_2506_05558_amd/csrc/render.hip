@@ -142,9 +142,17 @@ __device__ __forceinline__ Pixel pixel_of(int tile, int tiles_x, int W, int H) {
 struct FwdOut {
   float *image, *depth, *alpha, *final_t;
   int32_t *n_contrib, *stats;
+  // the fused L1 loss (LOSS): target image, gradient scale, dL/dimage and
+  // per-tile partial sums [tile][2] of |image - target| and its square
+  const float *target;
+  float loss_scale;
+  float *g_image;
+  double *partials;
 };
 
-template <bool STATS>
+// LOSS: the L1 photometric loss is formed in the epilogue (the gradient
+// and the tile's partial sums) while the pixel's colour is in registers.
+template <bool STATS, bool LOSS>
 __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;  // uniform over the workgroup
@@ -227,20 +235,84 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
       }
     }
   }
-  if (!P.inside) return;
   const int64_t pix = (int64_t)P.v * a.W + P.u, np = (int64_t)a.W * a.H;
-  o.image[pix] = __fmaf_rn(T, a.bg0, c0);
-  o.image[np + pix] = __fmaf_rn(T, a.bg1, c1);
-  o.image[2 * np + pix] = __fmaf_rn(T, a.bg2, c2);
-  o.depth[pix] = D;
-  o.alpha[pix] = 1.0f - T;
-  o.final_t[pix] = T;
-  o.n_contrib[pix] = last;
-  if (STATS) {
-    o.stats[pix] = ntile;
-    o.stats[np + pix] = nev;
-    o.stats[2 * np + pix] = nsup;
-    o.stats[3 * np + pix] = ncomp;
+  const float v[3] = {__fmaf_rn(T, a.bg0, c0), __fmaf_rn(T, a.bg1, c1), __fmaf_rn(T, a.bg2, c2)};
+  if (P.inside) {
+    o.image[pix] = v[0];
+    o.image[np + pix] = v[1];
+    o.image[2 * np + pix] = v[2];
+    o.depth[pix] = D;
+    o.alpha[pix] = 1.0f - T;
+    o.final_t[pix] = T;
+    o.n_contrib[pix] = last;
+    if (STATS) {
+      o.stats[pix] = ntile;
+      o.stats[np + pix] = nev;
+      o.stats[2 * np + pix] = nsup;
+      o.stats[3 * np + pix] = ncomp;
+    }
+  }
+  if (LOSS) {
+    // d = image - target as gs_loss_l1 forms it (the same binary32 values),
+    // dL/dimage = scale sign(d) with exact zeros; the tile's sums of |d| and
+    // d^2 in FP64, in a fixed order
+    double s1 = 0.0, s2 = 0.0;
+    if (P.inside) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float d = v[c] - o.target[c * np + pix];
+        s1 += fabs((double)d);
+        s2 += (double)d * (double)d;
+        o.g_image[c * np + pix] = d > 0.f ? o.loss_scale : (d < 0.f ? -o.loss_scale : 0.f);
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s1 += __shfl_down(s1, off, 64);
+      s2 += __shfl_down(s2, off, 64);
+    }
+    __shared__ double red[4][2];
+    if ((threadIdx.x & 63) == 0) {
+      red[w][0] = s1;
+      red[w][1] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      o.partials[2 * tile] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+      o.partials[2 * tile + 1] = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    }
+  }
+}
+
+// Sum of the per-tile loss partials in a fixed order: 1024 lanes each add
+// every 1024-th tile, then a wave tree and the 16 wave sums in order.
+constexpr int kSumBlock = 1024;
+__global__ __launch_bounds__(kSumBlock) void k_tile_loss_sums(const double *partials, int ntiles, double *sums) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < ntiles; k += kSumBlock) {
+    a += partials[2 * k];
+    b += partials[2 * k + 1];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off, 64);
+    b += __shfl_down(b, off, 64);
+  }
+  __shared__ double red[kSumBlock / 64][2];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w][0] = a;
+    red[w][1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0, y = 0.0;
+    for (int k = 0; k < kSumBlock / 64; ++k) {
+      x += red[k][0];
+      y += red[k][1];
+    }
+    sums[0] = x;
+    sums[1] = y;
   }
 }
 
@@ -554,11 +626,41 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
   GS_REQUIRE(rp->alpha_max > 0.f && rp->alpha_max < 1.f && rp->t_min > 0.f && rp->t_min < 1.f,
              "gs_render_fwd: raster params out of range");
   RenderArgs a = render_args(cam, rp, proj, values, ranges);
-  FwdOut o{image, depth, alpha, final_t, n_contrib, stats};
+  FwdOut o{image, depth, alpha, final_t, n_contrib, stats, nullptr, 0.f, nullptr, nullptr};
   if (stats)
-    GS_LAUNCH("render_fwd", k_render_fwd<true>, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
+    GS_LAUNCH("render_fwd", (k_render_fwd<true, false>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
   else
-    GS_LAUNCH("render_fwd", k_render_fwd<false>, padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
+    GS_LAUNCH("render_fwd", (k_render_fwd<false, false>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
+  return GS_OK;
+}
+
+gs_status gs_render_fwd_l1_workspace(int32_t width, int32_t height, size_t *bytes) {
+  GS_REQUIRE(bytes && width > 0 && height > 0, "gs_render_fwd_l1_workspace: bad argument");
+  *bytes = align_up(2 * sizeof(double) * (size_t)tiles_x_of(width) * (size_t)tiles_y_of(height));
+  return GS_OK;
+}
+
+gs_status gs_render_fwd_l1(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                           const uint32_t *values, const uint32_t *ranges, float *image, float *depth, float *alpha,
+                           float *final_t, int32_t *n_contrib, const float *target, float grad_scale,
+                           float *dL_dimage, double *sums, void *ws, size_t ws_bytes, void *stream) {
+  gs_status st = validate_camera(cam, "gs_render_fwd_l1");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(rp && proj && ranges && image && depth && alpha && final_t && n_contrib && target && dL_dimage && sums,
+             "gs_render_fwd_l1: NULL argument");
+  GS_REQUIRE(rp->alpha_max > 0.f && rp->alpha_max < 1.f && rp->t_min > 0.f && rp->t_min < 1.f,
+             "gs_render_fwd_l1: raster params out of range");
+  size_t need = 0;
+  gs_render_fwd_l1_workspace(cam->width, cam->height, &need);
+  if (ws_bytes < need || !ws) {
+    set_error("gs_render_fwd_l1: workspace %zu bytes < %zu", ws_bytes, need);
+    return GS_ERR_WORKSPACE;
+  }
+  RenderArgs a = render_args(cam, rp, proj, values, ranges);
+  FwdOut o{image, depth, alpha, final_t, n_contrib, nullptr, target, grad_scale, dL_dimage, (double *)ws};
+  GS_LAUNCH("render_fwd", (k_render_fwd<false, true>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
+  GS_LAUNCH("loss_final", k_tile_loss_sums, 1, kSumBlock, 0, (hipStream_t)stream, (const double *)ws, a.ntiles,
+            sums);
   return GS_OK;
 }
 

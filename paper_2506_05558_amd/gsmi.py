@@ -79,6 +79,9 @@ _sig = {
                                     _vp]),
     "gs_render_fwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp]),
+    "gs_render_fwd_l1_workspace": (C.c_int, [_i32, _i32, _P(_sz)]),
+    "gs_render_fwd_l1": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f,
+                                   _vp, _vp, _vp, _sz, _vp]),
     "gs_render_bwd_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
     "gs_render_bwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp, _vp, _vp, _vp, _i64, _vp,
                                 _vp, _vp, _vp, _vp, _vp, _vp, _P(_Gauss), _vp, _vp, _vp, _sz, _vp]),
@@ -367,6 +370,40 @@ def render_fwd(cam: Camera, proj: Projected, binned: Binned, params: Params = Pa
                               binned.ranges.data_ptr(), out.image.data_ptr(), out.depth.data_ptr(),
                               out.alpha.data_ptr(), out.final_t.data_ptr(), out.n_contrib.data_ptr(),
                               _ptr(out.stats), _stream()))
+    return out
+
+
+def render_fwd_l1_workspace(width: int, height: int) -> int:
+    need = C.c_size_t()
+    _check(_lib.gs_render_fwd_l1_workspace(width, height, C.byref(need)))
+    return int(need.value)
+
+
+def render_fwd_l1(cam: Camera, proj: Projected, binned: Binned, target: torch.Tensor, grad_scale: float,
+                  dL_dimage: torch.Tensor, sums: torch.Tensor, ws: Optional[torch.Tensor] = None,
+                  params: Params = Params(), out: Optional[Frame] = None) -> Frame:
+    """gs_render_fwd_l1: the forward with the L1 loss fused in; dL_dimage
+    (3, H, W) float32 and sums (2,) float64 are written.  ws: a uint8 device
+    tensor of at least render_fwd_l1_workspace(W, H) bytes (new if None)."""
+    H, W = cam.height, cam.width
+    dev = proj.rec.device
+    _require(target, torch.float32, (3, H, W), "target")
+    _require(dL_dimage, torch.float32, (3, H, W), "dL_dimage")
+    _require(sums, torch.float64, (2,), "sums")
+    if out is None:
+        out = Frame(torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.float32, device=dev),
+                    torch.empty((H, W), dtype=torch.int32, device=dev))
+    need = render_fwd_l1_workspace(W, H)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(_lib.gs_render_fwd_l1(C.byref(cam.c()), C.byref(params.c()), C.byref(proj.c()), binned.values.data_ptr(),
+                                 binned.ranges.data_ptr(), out.image.data_ptr(), out.depth.data_ptr(),
+                                 out.alpha.data_ptr(), out.final_t.data_ptr(), out.n_contrib.data_ptr(),
+                                 target.data_ptr(), grad_scale, dL_dimage.data_ptr(), sums.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), _stream()))
     return out
 
 
