@@ -4,6 +4,11 @@
 * Adam (bias-corrected) and its sparse form, which leaves every parameter of
   a Gaussian the step did not process untouched (section 4.3 uses the
   sparse Adam of the fast 3DGS optimiser).
+* Per-Gaussian learning rates (section 4.3 and the joint-optimisation
+  appendix): each Gaussian's rate starts at a fixed value when it is
+  introduced and is multiplied by a decay ratio every time a sparse Adam
+  step processes it, so the factor of a Gaussian is decay^k after k steps
+  that saw it.
 * The continuous 6D rotation representation of the camera poses
   (section 4.3): R's columns by Gram-Schmidt of the two 3-vectors; its
   adjoint is taken with PyTorch CPU autograd in float64.
@@ -22,13 +27,19 @@ def psnr(mse):
     return 10.0 * np.log10(1.0 / mse)
 
 
-def adam(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=None):
+def adam(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=None, lr_scale=None):
+    """One Adam step; lr_scale [n_stride] multiplies the rate of element e
+    by lr_scale[e % n_stride] (the per-Gaussian rate)."""
     p, g, m, v = (np.array(a, np.float64) for a in (p, g, m, v))
     m_new = beta1 * m + (1 - beta1) * g
     v_new = beta2 * v + (1 - beta2) * g * g
     mh = m_new / (1 - beta1 ** step)
     vh = v_new / (1 - beta2 ** step)
-    p_new = p - lr * mh / (np.sqrt(vh) + eps)
+    rate = lr
+    if lr_scale is not None:
+        flat = np.arange(p.size) % n_stride
+        rate = lr * np.asarray(lr_scale, np.float64).reshape(-1)[flat].reshape(p.shape)
+    p_new = p - rate * mh / (np.sqrt(vh) + eps)
     if visible is not None:
         flat = np.arange(p.size) % n_stride
         keep = np.asarray(visible).reshape(-1)[flat].reshape(p.shape) != 0
@@ -36,6 +47,15 @@ def adam(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, 
         m_new = np.where(keep, m_new, m)
         v_new = np.where(keep, v_new, v)
     return p_new, m_new, v_new
+
+
+def lr_decay(lr_scale, decay, visible=None):
+    """The per-Gaussian rates after one sparse step: the Gaussians it
+    processed (visible != 0, or all without a mask) are multiplied by decay."""
+    s = np.array(lr_scale, np.float64)
+    if visible is None:
+        return s * decay
+    return np.where(np.asarray(visible) != 0, s * decay, s)
 
 
 def pose_from_6d(x):

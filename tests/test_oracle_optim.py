@@ -42,6 +42,40 @@ def test_adam_sparse_leaves_hidden_gaussians():
     assert np.array_equal(p1[:, ~hidden], pd[:, ~hidden]) and np.array_equal(v1[:, ~hidden], vd[:, ~hidden])
 
 
+def test_adam_per_gaussian_rate_first_step_closed_form():
+    # the first bias-corrected step moves every element by its own rate
+    # times sign(g): lr * s_j for the elements of Gaussian j
+    rng = np.random.default_rng(4)
+    n = 12
+    p = rng.standard_normal((4, n))
+    g = rng.standard_normal((4, n))
+    s = rng.random(n) + 0.1
+    p1, m1, v1 = optim.adam(p, g, np.zeros((4, n)), np.zeros((4, n)), lr=0.2, step=1, eps=0.0, n_stride=n,
+                            lr_scale=s)
+    assert np.allclose(p1, p - 0.2 * s[None, :] * np.sign(g), atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+    # a hidden Gaussian keeps p, m, v whatever its rate
+    vis = (np.arange(n) % 2).astype(np.int32)
+    p2, m2, _ = optim.adam(p, g, np.zeros((4, n)), np.zeros((4, n)), 0.2, 1, eps=0.0, visible=vis, n_stride=n,
+                           lr_scale=s)
+    assert np.array_equal(p2[:, vis == 0], p[:, vis == 0]) and not m2[:, vis == 0].any()
+    assert np.allclose(p2[:, vis == 1], (p - 0.2 * s[None, :] * np.sign(g))[:, vis == 1], atol=1e-15)
+
+
+def test_lr_decay_counts_processed_steps():
+    # after a schedule of sparse steps each factor is decay^(steps that saw it)
+    rng = np.random.default_rng(5)
+    n, steps, decay = 20, 9, 0.97
+    s = np.ones(n)
+    seen = np.zeros(n, int)
+    for _ in range(steps):
+        vis = (rng.random(n) < 0.6).astype(np.int32)
+        s = optim.lr_decay(s, decay, vis)
+        seen += vis
+    assert np.allclose(s, decay ** seen, rtol=1e-14)
+    assert np.allclose(optim.lr_decay(np.full(3, 2.0), 0.5), [1.0, 1.0, 1.0])
+
+
 def test_pose_6d_orthonormal_and_identity():
     rng = np.random.default_rng(2)
     x = rng.standard_normal((5, 9))
