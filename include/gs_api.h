@@ -291,13 +291,23 @@ gs_status gs_loss_l1(const float *image, const float *target, int64_t count, flo
 
 /* One Adam step (bias-corrected, step >= 1) on count floats:
  *   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
- *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ *   p -= lr_e (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
  * Sparse form (section 4.3, sparse Adam): if visible is not NULL, element e
  * belongs to Gaussian e % n_stride and is left untouched (p, m, v) unless
- * visible[e % n_stride] != 0. */
+ * visible[e % n_stride] != 0.  Per-Gaussian rates (section 4.3 and the
+ * joint-optimisation appendix): if lr_scale [n_stride] is not NULL,
+ * lr_e = lr * lr_scale[e % n_stride] (FP32 product), else lr_e = lr.
+ * n_stride > 0 is required with either array.  In place; no workspace. */
 gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,
-                       float beta2, float eps, int32_t step, const int32_t *visible, int64_t n_stride,
-                       void *stream);
+                       float beta2, float eps, int32_t step, const int32_t *visible, const float *lr_scale,
+                       int64_t n_stride, void *stream);
+
+/* The per-Gaussian rate decay that follows a sparse step (the
+ * joint-optimisation appendix): lr_scale[i] *= decay for every i with
+ * visible[i] != 0 (every i if visible is NULL).  A Gaussian's factor starts
+ * at 1 when it is introduced (the caller writes it), so after k steps that
+ * processed it the factor is decay^k.  decay in (0, 1]. */
+gs_status gs_lr_decay(float *lr_scale, const int32_t *visible, int64_t n, float decay, void *stream);
 
 /* Pose from the continuous 6D rotation representation used for the camera
  * poses (section 4.3): x [V][9] = (a1, a2, t); R's columns are
@@ -314,6 +324,48 @@ gs_status gs_zero(void *ptr, size_t bytes, void *stream);
 /* mask[i] |= (tiles_touched[i] > 0) over n Gaussians: the set a step
  * processed, which the sparse Adam step of section 4.3 updates. */
 gs_status gs_mark_visible(const int32_t *tiles_touched, int64_t n, int32_t *mask, void *stream);
+
+/* ---- multi-scale training (section 4.3) ------------------------------
+ * Coarse-to-fine: a newly added image first trains at 2^l downsampling
+ * (l = 3), one level less every five iterations until full size; the
+ * target is the box-filtered image and the camera the matching coarse one.
+ *
+ * gs_downsample: out [C][H >> level][W >> level] with coarse pixel (x, y)
+ * of plane c = mean (FP32 sum in row order, times 2^-2level) of in[c] over
+ * rows 2^level y .. 2^level y + 2^level - 1 and the same columns of x; the
+ * right and bottom remainders that do not fill a block are dropped.  in
+ * [C][H][W], device memory; out must not overlap in.  level 0..4 (0 is a
+ * copy).  Errors: GS_ERR_INVALID_ARG for bad sizes, NULL pointers, or an
+ * image smaller than one block. */
+gs_status gs_downsample(const float *in, int32_t channels, int32_t width, int32_t height, int32_t level, float *out,
+                        void *stream);
+
+/* The camera that renders the 2^level-downsampled image (host only, no GPU
+ * work): width >> level, height >> level, f / 2^level, and
+ * c' = (c + 1/2) / 2^level - 1/2 (pixel centres at integer coordinates: a
+ * coarse pixel's centre is the centroid of its fine pixels' centres); the
+ * pose pointer, near plane and background are copied.  out may equal cam. */
+gs_status gs_camera_level(const gs_camera *cam, int32_t level, gs_camera *out);
+
+/* Opacity culling (section 4.3, as in 3DGS): Gaussian i is kept iff
+ * opacity_logits[i] >= thr, thr = binary32 rounding of ln(t / (1 - t))
+ * computed in binary64 on the host, t = min_opacity in (0, 1) -- the test
+ * sigmoid(logit) >= t taken on the logit in FP32.  keep_index [n] (device)
+ * receives the kept indices in ascending order, *n_keep (host) their
+ * number; entries past *n_keep are unspecified.  Reads the count back and
+ * synchronises the stream once.  ws: gs_prune_workspace(n) bytes.
+ * n <= 2^31 - 1. */
+gs_status gs_prune_workspace(int64_t n, size_t *bytes);
+gs_status gs_prune_opacity(const float *opacity_logits, int64_t n, float min_opacity, int32_t *keep_index,
+                           int64_t *n_keep, void *ws, size_t ws_bytes, void *stream);
+
+/* dst[p][j] = src[p][index[j]] for p < planes, j < m: src planes of stride
+ * n_src, dst planes of stride m, device memory, not overlapping.  With
+ * gs_prune_opacity's keep_index this compacts every parameter plane, Adam
+ * moment and per-Gaussian rate to the kept Gaussians (planes <= 65535; an
+ * index outside [0, n_src) gives 0). */
+gs_status gs_gather_planes(const float *src, int64_t n_src, int32_t planes, const int32_t *index, int64_t m,
+                           float *dst, void *stream);
 
 /* ---- spawning (section 4.2) ---------------------------------------------
  * A new frame spawns primitives where its image has structure that the

@@ -81,39 +81,54 @@ __device__ __forceinline__ void store_stream(float *q, const float4 &x) {
   __builtin_nontemporal_store((v4f){x.x, x.y, x.z, x.w}, (v4f *)q);
 }
 
+// RATE: lr_scale[j] multiplies the rate of every element of Gaussian j.
+template <bool RATE>
 __global__ __launch_bounds__(256) void k_adam4(float *p, const float *g, float *m, float *v, float lr, float b1,
                                                float b2, float eps, float c1, float c2, const int32_t *visible,
-                                               int64_t n_stride) {
+                                               const float *lr_scale, int64_t n_stride) {
   const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   if (j >= n_stride) return;
   const int64_t i = (int64_t)blockIdx.y * n_stride + j;
   const int4 vis = visible ? *(const int4 *)(visible + j) : make_int4(1, 1, 1, 1);
   if ((vis.x | vis.y | vis.z | vis.w) == 0) return;
+  float4 R = make_float4(lr, lr, lr, lr);
+  if (RATE) {
+    const float4 S = *(const float4 *)(lr_scale + j);
+    R = make_float4(lr * S.x, lr * S.y, lr * S.z, lr * S.w);
+  }
   const float4 G = load_stream(g + i);
   float4 M = load_stream(m + i), V = load_stream(v + i), P = load_stream(p + i);
-  if (vis.x) adam_one(G.x, M.x, V.x, P.x, lr, b1, b2, eps, c1, c2);
-  if (vis.y) adam_one(G.y, M.y, V.y, P.y, lr, b1, b2, eps, c1, c2);
-  if (vis.z) adam_one(G.z, M.z, V.z, P.z, lr, b1, b2, eps, c1, c2);
-  if (vis.w) adam_one(G.w, M.w, V.w, P.w, lr, b1, b2, eps, c1, c2);
+  if (vis.x) adam_one(G.x, M.x, V.x, P.x, R.x, b1, b2, eps, c1, c2);
+  if (vis.y) adam_one(G.y, M.y, V.y, P.y, R.y, b1, b2, eps, c1, c2);
+  if (vis.z) adam_one(G.z, M.z, V.z, P.z, R.z, b1, b2, eps, c1, c2);
+  if (vis.w) adam_one(G.w, M.w, V.w, P.w, R.w, b1, b2, eps, c1, c2);
   store_stream(m + i, M);
   store_stream(v + i, V);
   store_stream(p + i, P);
 }
 
 // Grid (plane chunks, planes): element i = plane * n_stride + j belongs to
-// Gaussian j, so the visibility test needs no division.
+// Gaussian j, so the visibility test and the rate need no division.
 __global__ __launch_bounds__(256) void k_adam(float *p, const float *g, float *m, float *v, int64_t count, float lr,
                                               float b1, float b2, float eps, float c1, float c2,
-                                              const int32_t *visible, int64_t n_stride) {
+                                              const int32_t *visible, const float *lr_scale, int64_t n_stride) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t i = (int64_t)blockIdx.y * n_stride + j;
   if (j >= n_stride || i >= count) return;
   if (visible && !visible[j]) return;
   float mi = m[i], vi = v[i], pi = p[i];
-  adam_one(g[i], mi, vi, pi, lr, b1, b2, eps, c1, c2);
+  adam_one(g[i], mi, vi, pi, lr_scale ? lr * lr_scale[j] : lr, b1, b2, eps, c1, c2);
   m[i] = mi;
   v[i] = vi;
   p[i] = pi;
+}
+
+// The per-Gaussian rates after a sparse step: each Gaussian it processed
+// is multiplied by the decay ratio.
+__global__ __launch_bounds__(256) void k_lr_decay(float *lr_scale, const int32_t *visible, int64_t n, float decay) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n || (visible && !visible[i])) return;
+  lr_scale[i] *= decay;
 }
 
 // R's columns from the two 3-vectors of the 6D representation.
@@ -234,30 +249,45 @@ gs_status gs_loss_l1(const float *image, const float *target, int64_t count, flo
 }
 
 gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int64_t count, float lr, float beta1,
-                       float beta2, float eps, int32_t step, const int32_t *visible, int64_t n_stride,
-                       void *stream) {
+                       float beta2, float eps, int32_t step, const int32_t *visible, const float *lr_scale,
+                       int64_t n_stride, void *stream) {
   GS_REQUIRE(count >= 0 && step >= 1, "gs_adam_step: bad count or step");
   GS_REQUIRE(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f, "gs_adam_step: bad betas");
   if (count == 0) return GS_OK;
   GS_REQUIRE(param && grad && m && v, "gs_adam_step: NULL argument");
-  if (visible) GS_REQUIRE(n_stride > 0, "gs_adam_step: n_stride must be positive with a visibility mask");
+  if (visible || lr_scale)
+    GS_REQUIRE(n_stride > 0, "gs_adam_step: n_stride must be positive with a visibility mask or per-Gaussian rates");
   const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
   const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
-  // without a mask the whole array is one "plane"
-  const int64_t stride = visible ? n_stride : count;
+  // without a mask or rates the whole array is one "plane"
+  const int64_t stride = visible || lr_scale ? n_stride : count;
   const int64_t planes = (count + stride - 1) / stride;
   GS_REQUIRE(planes <= 65535, "gs_adam_step: count / n_stride exceeds 65535 planes");
   const auto a16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
   if (stride % 4 == 0 && count % stride == 0 && a16(param) && a16(grad) && a16(m) && a16(v) &&
-      (!visible || a16(visible))) {
+      (!visible || a16(visible)) && (!lr_scale || a16(lr_scale))) {
     const dim3 grid((unsigned)((stride / 4 + 255) / 256), (unsigned)planes);
-    GS_LAUNCH("adam", k_adam4, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, lr, beta1, beta2, eps, c1, c2,
-              visible, stride);
+    if (lr_scale)
+      GS_LAUNCH("adam", k_adam4<true>, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, lr, beta1, beta2, eps,
+                c1, c2, visible, lr_scale, stride);
+    else
+      GS_LAUNCH("adam", k_adam4<false>, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, lr, beta1, beta2, eps,
+                c1, c2, visible, lr_scale, stride);
     return GS_OK;
   }
   const dim3 grid((unsigned)((stride + 255) / 256), (unsigned)planes);
   GS_LAUNCH("adam", k_adam, grid, 256, 0, (hipStream_t)stream, param, grad, m, v, count, lr, beta1, beta2, eps, c1,
-            c2, visible, stride);
+            c2, visible, lr_scale, stride);
+  return GS_OK;
+}
+
+gs_status gs_lr_decay(float *lr_scale, const int32_t *visible, int64_t n, float decay, void *stream) {
+  GS_REQUIRE(n >= 0, "gs_lr_decay: n < 0");
+  GS_REQUIRE(decay > 0.f && decay <= 1.f, "gs_lr_decay: decay must be in (0, 1]");
+  if (n == 0) return GS_OK;
+  GS_REQUIRE(lr_scale, "gs_lr_decay: NULL rates");
+  GS_LAUNCH("lr_decay", k_lr_decay, (unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream, lr_scale, visible, n,
+            decay);
   return GS_OK;
 }
 

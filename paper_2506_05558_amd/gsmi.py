@@ -92,7 +92,13 @@ _sig = {
     "gs_project_bwd_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
-    "gs_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _i64, _vp]),
+    "gs_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _vp, _i64, _vp]),
+    "gs_lr_decay": (C.c_int, [_vp, _vp, _i64, _f, _vp]),
+    "gs_downsample": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "gs_camera_level": (C.c_int, [_P(_Camera), _i32, _P(_Camera)]),
+    "gs_prune_workspace": (C.c_int, [_i64, _P(_sz)]),
+    "gs_prune_opacity": (C.c_int, [_vp, _i64, _f, _vp, _P(_i64), _vp, _sz, _vp]),
+    "gs_gather_planes": (C.c_int, [_vp, _i64, _i32, _vp, _i64, _vp, _vp]),
     "gs_pose_from_6d": (C.c_int, [_vp, _vp, _i32, _vp]),
     "gs_pose_6d_bwd": (C.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gs_zero": (C.c_int, [_vp, _sz, _vp]),
@@ -525,9 +531,76 @@ def loss_l1(image: torch.Tensor, target: torch.Tensor, grad_scale: Optional[floa
     return sums
 
 
-def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=0):
+def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=0,
+              lr_scale=None):
     _check(_lib.gs_adam_step(param.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), param.numel(), lr,
-                             beta1, beta2, eps, step, _ptr(visible), n_stride, _stream()))
+                             beta1, beta2, eps, step, _ptr(visible), _ptr(lr_scale), n_stride, _stream()))
+
+
+def lr_decay(lr_scale: torch.Tensor, decay: float, visible: Optional[torch.Tensor] = None):
+    """lr_scale[i] *= decay for the Gaussians a sparse step processed."""
+    _check(_lib.gs_lr_decay(lr_scale.data_ptr(), _ptr(visible), lr_scale.numel(), decay, _stream()))
+
+
+# ------------------------------------------------------ multi-scale training
+def coarse_level(iteration: int, start_level: int = 3, every: int = 5) -> int:
+    """Downsampling level of a newly added image at a joint iteration: 2^3
+    first, one level less every five iterations (section 4.3)."""
+    return max(0, start_level - iteration // every)
+
+
+def downsample(image: torch.Tensor, level: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """[C][H][W] -> [C][H >> level][W >> level] box filter."""
+    if image.dim() != 3:
+        raise ValueError(f"image: expected [C][H][W], got {tuple(image.shape)}")
+    _require(image, torch.float32, image.shape, "image")
+    c, h, w = image.shape
+    if out is None:
+        out = torch.empty((c, h >> level, w >> level), dtype=torch.float32, device=image.device)
+    _check(_lib.gs_downsample(image.data_ptr(), c, w, h, level, out.data_ptr(), _stream()))
+    return out
+
+
+def camera_level(cam: Camera, level: int) -> Camera:
+    """The camera of the 2^level-downsampled image (same pose tensor)."""
+    out = _Camera()
+    _check(_lib.gs_camera_level(C.byref(cam.c()), level, C.byref(out)))
+    return Camera(out.width, out.height, out.fx, out.fy, out.cx, out.cy, cam.pose, cam.near_plane, cam.bg)
+
+
+def prune_opacity(opacity_logits: torch.Tensor, min_opacity: float = 0.005,
+                  keep_index: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Ascending int32 indices of the Gaussians opacity culling keeps."""
+    _require(opacity_logits, torch.float32, (opacity_logits.numel(),), "opacity_logits")
+    n = opacity_logits.numel()
+    need = C.c_size_t()
+    _check(_lib.gs_prune_workspace(n, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=opacity_logits.device)
+    if keep_index is None:
+        keep_index = torch.empty(max(n, 1), dtype=torch.int32, device=opacity_logits.device)
+    kept = C.c_int64()
+    _check(_lib.gs_prune_opacity(opacity_logits.data_ptr(), n, min_opacity, keep_index.data_ptr(), C.byref(kept),
+                                 ws.data_ptr(), ws.numel(), _stream()))
+    return keep_index[:kept.value]
+
+
+def gather_planes(src: torch.Tensor, index: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """src [..., n] -> [..., m]: column j is column index[j] (all leading
+    dimensions are planes)."""
+    _require(src, torch.float32, src.shape, "src")
+    _require(index, torch.int32, (index.numel(),), "index")
+    n, m = src.shape[-1], index.numel()
+    planes = src.numel() // max(n, 1)
+    if out is None:
+        out = torch.empty((*src.shape[:-1], m), dtype=torch.float32, device=src.device)
+    _check(_lib.gs_gather_planes(src.data_ptr(), n, planes, index.data_ptr(), m, out.data_ptr(), _stream()))
+    return out
+
+
+def prune_gaussians(g: Gaussians, keep_index: torch.Tensor) -> Gaussians:
+    """The kept Gaussians' parameter planes (new tensors, same order)."""
+    return Gaussians(*(gather_planes(t, keep_index) for t in g.tensors()))
 
 
 def pose_from_6d(x: torch.Tensor, pose: torch.Tensor):

@@ -72,8 +72,11 @@ def test_host_validation_rejects_bad_calls(lib):
                              None) == g.GS_ERR_INVALID_ARG
     # Adam: step must be >= 1
     lib.gs_adam_step.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
-                                                    C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]
-    assert lib.gs_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None, 0,
+                                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    assert lib.gs_adam_step(None, None, None, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None, None, 0,
+                            None) == g.GS_ERR_INVALID_ARG
+    # per-Gaussian rates need a plane stride
+    assert lib.gs_adam_step(1, 1, 1, 1, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None, 1, 0,
                             None) == g.GS_ERR_INVALID_ARG
 
 
@@ -138,3 +141,47 @@ def test_spawn_validation(lib):
                                 None) == g.GS_ERR_CAPACITY
     sz = C.c_size_t()
     assert g._lib.gs_spawn_select_workspace(1920, 1080, C.byref(sz)) == 0 and sz.value >= 24 * 1920 * 1080
+
+
+def test_camera_level_equals_the_oracle(lib):
+    # host-only: the coarse camera is computed on the host (the pose pointer
+    # is only copied, never dereferenced)
+    import numpy as np
+
+    from oracle import multiscale as ms
+    from paper_2506_05558_amd import gsmi
+    cam = gsmi._Camera(1920, 1080, 1111.5, 1050.25, 959.5, 539.5, 0.2, (C.c_float * 3)(0.1, 0.2, 0.3), 0x1000)
+    for level in range(5):
+        out = gsmi._Camera()
+        assert gsmi._lib.gs_camera_level(C.byref(cam), level, C.byref(out)) == 0
+        ref = ms.camera_level(cam.width, cam.height, float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                              level)
+        assert (out.width, out.height) == ref[:2]
+        assert [out.fx, out.fy, out.cx, out.cy] == [float(np.float32(x)) for x in ref[2:]]
+        assert out.pose == cam.pose and out.near_plane == cam.near_plane and list(out.bg) == list(cam.bg)
+    bad = gsmi._Camera()
+    assert gsmi._lib.gs_camera_level(C.byref(cam), 5, C.byref(bad)) == 1
+    tiny = gsmi._Camera(7, 9, 1.0, 1.0, 3.0, 4.0, 0.2, (C.c_float * 3)(), 0x1000)
+    assert gsmi._lib.gs_camera_level(C.byref(tiny), 3, C.byref(bad)) == 1  # 7 >> 3 = 0 columns
+
+
+def test_multiscale_validation(lib):
+    from paper_2506_05558_amd import gsmi
+    L = gsmi._lib
+    assert L.gs_downsample(1, 3, 64, 64, 5, 2, None) == 1        # level out of range
+    assert L.gs_downsample(1, 3, 4, 64, 3, 2, None) == 1         # narrower than one block
+    assert L.gs_downsample(None, 3, 64, 64, 2, 2, None) == 1     # NULL input
+    kept = C.c_int64(-1)
+    assert L.gs_prune_opacity(1, 10, 0.0, 1, C.byref(kept), 1, 1 << 20, None) == 1
+    assert L.gs_prune_opacity(1, 10, 0.005, 1, C.byref(kept), None, 0, None) == gsmi.GS_ERR_WORKSPACE
+    assert L.gs_prune_opacity(None, 0, 0.005, None, C.byref(kept), None, 0, None) == 0 and kept.value == 0
+    assert L.gs_gather_planes(1, 10, 70000, 1, 5, 2, None) == 1  # too many planes
+    assert L.gs_gather_planes(1, 10, 2, 1, 5, 1, None) == 1      # in place
+    assert L.gs_lr_decay(1, None, 10, 0.0, None) == 1
+    assert L.gs_lr_decay(1, None, 10, 1.5, None) == 1
+    sz = C.c_size_t()
+    sizes = []
+    for n in (1, 1000, 2_000_000):
+        assert L.gs_prune_workspace(n, C.byref(sz)) == 0
+        sizes.append(sz.value)
+    assert sizes == sorted(sizes) and sizes[-1] >= 8 * 2_000_000
