@@ -36,6 +36,9 @@ sys.path.insert(0, ROOT)
 
 W_IMG, H_IMG, N_VIEWS, PER_VIEW, SH_DEG, SEED = 1920, 1080, 8, 250_000, 3, 2506
 ITERS, SPAWN_K, MLP_BATCH = 30, 100_000, 4096
+# per-Gaussian learning rates: each sparse step that processes a Gaussian multiplies its rate by
+# LR_DECAY (the ratio is not given; the factor halves after ~140 processed steps)
+LR_DECAY = 0.995
 
 # MI355X peaks (published): HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s with
 # packed FP32, which the kernels are compiled without: unpacked VALU issue
@@ -140,6 +143,7 @@ def main():
     poses = torch.zeros((N_VIEWS, 12), dtype=torch.float32, device=dev)
     d_pose = torch.zeros((N_VIEWS, 12), dtype=torch.float64, device=dev)
     visible = torch.zeros(n, dtype=torch.int32, device=dev)
+    rates = torch.ones(n, dtype=torch.float32, device=dev)  # per-Gaussian rate factors, 1 when introduced
     sums = torch.zeros((N_VIEWS, 2), dtype=torch.float64, device=dev)
     proj = gsmi.alloc_projected(n, dev)
     f = lambda *s, dt=torch.float32: torch.empty(s, dtype=dt, device=dev)
@@ -153,6 +157,17 @@ def main():
     wviews = [gsmi.View(cams[i], gsmi.alloc_projected(n, dev), None,
                         torch.empty(n, dtype=torch.int32, device=dev), d_pose[i]) for i in range(N_VIEWS)]
     pbwd_ws = torch.empty(gsmi.project_bwd_views_workspace(n, N_VIEWS), dtype=torch.uint8, device=dev)
+    # coarse-to-fine for the newest keyframe of the window (the last view): its image pyramid,
+    # coarse cameras (sharing the pose) and per-level frame buffers
+    newest = N_VIEWS - 1
+    c2f = {}
+    for lv in (1, 2, 3):
+        cl = gsmi.camera_level(cams[newest], lv)
+        c2f[lv] = dict(cam=cl, target=gsmi.downsample(targets[newest], lv),
+                       frame=gsmi.Frame(f(3, cl.height, cl.width), f(cl.height, cl.width), f(cl.height, cl.width),
+                                        f(cl.height, cl.width), f(cl.height, cl.width, dt=torch.int32)),
+                       g_img=f(3, cl.height, cl.width))
+    level = [0]
     lr = dict(means=1.6e-4 * 10, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4,
               pose=1e-4)
     state = dict(step=0)
@@ -192,10 +207,14 @@ def main():
         n_spawned.append(gsmi.spawn_init(cam_new, new_image, new_depth, spawned, 0, rendered=rendered_new, sp=sp,
                                          mlp_packed=packed, ws=spawn_ws))
 
-    def keyframe_step(iters, use_async=False, overlap=True):
+    def keyframe_step(iters, use_async=False, overlap=True, coarse_to_fine=False):
         spawn_new_frame()
-        for _ in range(iters):
+        for it in range(iters):
+            level[0] = gsmi.coarse_level(it) if coarse_to_fine else 0
+            wviews[newest].cam = c2f[level[0]]["cam"] if level[0] else cams[newest]
             step(use_async=use_async, overlap=overlap)
+        level[0] = 0
+        wviews[newest].cam = cams[newest]
         trainer.step(train_x, train_y)
 
     def step(count_pairs=False, use_async=False, overlap=True):
@@ -214,31 +233,35 @@ def main():
             with torch.cuda.stream(ss):
                 ss.wait_event(ev_proj)
                 lists = []
-                for i, (cam, vw) in enumerate(zip(cams, wviews)):
-                    lists.append(view_sorters[i].sort_async(cam, vw.proj, n_pairs[i:i + 1], first_slot=vw.first_slot))
+                for i, vw in enumerate(wviews):
+                    lists.append(view_sorters[i].sort_async(vw.cam, vw.proj, n_pairs[i:i + 1],
+                                                            first_slot=vw.first_slot))
                     ev_sorted[i].record(ss)
                     if i == 0 and overlap:
                         gsmi.zero_(gflat)  # next read by the projection adjoint, after the last view's event
-        for i, (cam, vw) in enumerate(zip(cams, wviews)):
+        for i, vw in enumerate(wviews):
+            cam, fr, tgt, gi = vw.cam, frame, targets[i], g_img
+            if i == newest and level[0]:
+                lv = c2f[level[0]]
+                fr, tgt, gi = lv["frame"], lv["target"], lv["g_img"]
             if use_async:
                 torch.cuda.current_stream().wait_event(ev_sorted[i])
                 b = lists[i]
             else:
                 b = sorter(cam, vw.proj, first_slot=vw.first_slot)
                 m_seen[i] = max(m_seen[i], b.n_instances)
-            fr = frame
             if count_pairs:
                 fr = gsmi.Frame(frame.image, frame.depth, frame.alpha, frame.final_t, frame.n_contrib,
                                 torch.empty((4, H, W), dtype=torch.int32, device=dev))
             if count_pairs:  # the pair counters: forward, then the loss
                 gsmi.render_fwd(cam, vw.proj, b, params, out=fr)
                 gsmi.loss_l1(fr.image, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i], loss_ws)
-            else:  # the L1 loss formed in the forward's epilogue
-                gsmi.render_fwd_l1(cam, vw.proj, b, targets[i], 1.0 / (3 * H * W * N_VIEWS), g_img, sums[i],
+            else:  # the L1 loss formed in the forward's epilogue (mean over each view's pixels)
+                gsmi.render_fwd_l1(cam, vw.proj, b, tgt, 1.0 / (3 * cam.height * cam.width * N_VIEWS), gi, sums[i],
                                    fwd_l1_ws, params, out=fr)
             if vw.pair_grad is None or vw.pair_grad.shape[0] < b.n_instances:
                 vw.pair_grad = torch.empty((int(b.n_instances * 1.25) + 1024, 12), dtype=torch.float32, device=dev)
-            gsmi.render_bwd_pairs(cam, vw.proj, b, fr, g_img, vw.pair_grad, params=params)
+            gsmi.render_bwd_pairs(cam, vw.proj, b, fr, gi, vw.pair_grad, params=params)
             gsmi.mark_visible(vw.proj, visible)
             if count_pairs:
                 st = fr.stats.view(4, -1).to(torch.int64).sum(1).cpu().numpy()
@@ -251,9 +274,12 @@ def main():
         gsmi.pose_6d_bwd(x6, d_pose, dx6)
         for name in ["means", "log_scales", "quats", "opacity_logits"]:
             gsmi.adam_step(getattr(g, name), getattr(grads, name), getattr(m1, name), getattr(m2, name), lr[name],
-                           k, visible=visible, n_stride=n)
-        gsmi.adam_step(g.sh[0], grads.sh[0], m1.sh[0], m2.sh[0], lr["sh_dc"], k, visible=visible, n_stride=n)
-        gsmi.adam_step(g.sh[1:], grads.sh[1:], m1.sh[1:], m2.sh[1:], lr["sh_rest"], k, visible=visible, n_stride=n)
+                           k, visible=visible, n_stride=n, lr_scale=rates)
+        gsmi.adam_step(g.sh[0], grads.sh[0], m1.sh[0], m2.sh[0], lr["sh_dc"], k, visible=visible, n_stride=n,
+                       lr_scale=rates)
+        gsmi.adam_step(g.sh[1:], grads.sh[1:], m1.sh[1:], m2.sh[1:], lr["sh_rest"], k, visible=visible, n_stride=n,
+                       lr_scale=rates)
+        gsmi.lr_decay(rates, LR_DECAY, visible)
         gsmi.adam_step(x6[1:], dx6[1:], px_m[1:], px_v[1:], lr["pose"], k, eps=1e-12)
 
     for _ in range(args.warmup):
@@ -271,8 +297,8 @@ def main():
 
     names = ["project", "bin_flags", "bin_compact", "radix_hist", "radix_scatter", "scan", "bin_counts",
              "bin_duplicate", "bin_ranges", "bin_fill", "render_fwd", "loss_l1", "loss_final", "render_bwd",
-             "project_bwd", "project_bwd_sh", "pose_reduce", "adam", "zero", "mark_visible", "pose_6d", "pose_6d_bwd",
-             "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
+             "project_bwd", "project_bwd_sh", "pose_reduce", "adam", "lr_decay", "zero", "mark_visible", "pose_6d",
+             "pose_6d_bwd", "downsample", "prune_flags", "prune_index", "gather_planes", "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
 
     def read_profile():
         out = {}
@@ -331,6 +357,7 @@ def main():
     visible_per_view = sum(p[6] for p in pairs) / N_VIEWS
 
     ms_step = elapsed * 1e3 / args.steps
+    multiscale = measure_multiscale(gsmi, keyframe_step, args.iters, targets, g, m1, m2, rates, ms_step)
     mpix = args.iters * N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
 
     def roof(name, ks=kernels):
@@ -408,6 +435,7 @@ def main():
                            "composited": comp, "tile_list_walked_bwd": walked, "instances": M,
                            "visible_gaussians": visible_per_view},
         "psnr_start_end": [round(sum(psnr0) / N_VIEWS, 3), round(sum(psnr1) / N_VIEWS, 3)],
+        "multiscale": multiscale,
     }
     if not args.no_study:
         # second half of the metric: learned vs rule initialisation of spawned primitives
@@ -435,6 +463,68 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     print(json.dumps(out))
+
+
+def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms_full):
+    """Multi-scale training (section 4.3), outside the headline: a keyframe whose newest view
+    trains coarse-to-fine (2^3, 2^2, 2^1 for five iterations each, then full size), the box filter
+    of a 1920x1080 target at each level, and opacity culling of the whole optimiser state (keep
+    list, then a gather of every parameter plane, both Adam moments and the rates)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keyframe_step(iters, use_async=True, coarse_to_fine=True)
+    torch.cuda.synchronize()
+    ms_c2f = (time.perf_counter() - t0) * 1e3
+
+    def hbm(nbytes, ms):
+        a = nbytes / (ms * 1e-3) / 1e9
+        return dict(bound="hbm", achieved=a, peak=PEAK_HBM_GBS, unit="GB/s", frac=a / PEAK_HBM_GBS,
+                    ms_per_launch=ms, traffic=None)
+
+    img = targets[0]
+    c, h, w = img.shape
+    down = {}
+    for lv in (1, 2, 3):
+        out = torch.empty((c, h >> lv, w >> lv), dtype=torch.float32, device=img.device)
+        gsmi.profile_reset()
+        gsmi.profile_select(["downsample"])
+        gsmi.profile_enable(True)
+        for _ in range(20):
+            gsmi.downsample(img, lv, out=out)
+        torch.cuda.synchronize()
+        gsmi.profile_enable(False)
+        ms, cnt = gsmi.profile_read("downsample")
+        nbytes = 4 * c * ((h >> lv) << lv) * ((w >> lv) << lv) + 4 * out.numel()
+        down[f"level{lv}"] = hbm(nbytes, ms / cnt)
+
+    n = g.n
+    state = [t for gg in (g, m1, m2) for t in gg.tensors()] + [rates]
+    planes = sum(t.numel() // n for t in state)
+    gsmi.profile_reset()
+    gsmi.profile_select(["prune_flags", "scan", "prune_index", "gather_planes"])
+    gsmi.profile_enable(True)
+    keep = gsmi.prune_opacity(g.opacity_logits, 0.005)
+    kept = keep.numel()
+    outs = [gsmi.gather_planes(t, keep) for t in state]
+    torch.cuda.synchronize()
+    gsmi.profile_enable(False)
+    prof = {k: gsmi.profile_read(k) for k in ["prune_flags", "scan", "prune_index", "gather_planes"]}
+    gsmi.profile_select(None)
+    gsmi.profile_reset()
+    del outs
+    torch.cuda.empty_cache()
+    ms_keep = prof["prune_flags"][0] + prof["scan"][0] + prof["prune_index"][0]
+    ms_gather = prof["gather_planes"][0]
+    return {
+        "coarse_to_fine_keyframe_ms": round(ms_c2f, 3), "full_size_keyframe_ms": round(ms_full, 3),
+        "newest_view_levels": [gsmi.coarse_level(i) for i in range(iters)],
+        "downsample_1920x1080x3": down,
+        "opacity_culling": {"gaussians": n, "kept": kept, "min_opacity": 0.005, "planes_gathered": planes,
+                            "keep_list_ms": round(ms_keep, 4), "gather_ms": round(ms_gather, 4),
+                            # per kept Gaussian and plane: 4 B read + 4 B written, plus the 4 B index
+                            "gather_roofline": hbm(kept * (8 * planes + 4), ms_gather)},
+    }
 
 
 def measured_traffic(kernel):
