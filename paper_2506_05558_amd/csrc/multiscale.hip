@@ -9,37 +9,49 @@ namespace gsmi {
 namespace {
 
 // Coarse pixel (x, y) of plane c = mean of the S x S fine block at
-// (S x, S y).  One lane per coarse pixel: a wave reads S rows of 64 S
-// consecutive floats, 16-byte loads where the rows allow them (VEC).
+// (S x, S y), summed in row order.  VEC (rows a multiple of 4 floats,
+// 16-byte aligned): a lane reads one 16-byte segment per row and makes
+// PX = max(1, 4 / S) neighbouring coarse pixels, so a wave reads 64
+// consecutive segments of each row it touches; otherwise one lane per
+// coarse pixel with 4-byte loads.
 template <int S, bool VEC>
 __global__ __launch_bounds__(256) void k_downsample(const float *in, int W, int H, int Wc, int Hc, int64_t total,
                                                     float *out) {
-  const int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int PX = VEC && S < 4 ? 4 / S : 1;
+  const int64_t o = ((int64_t)blockIdx.x * 256 + threadIdx.x) * PX;
   if (o >= total) return;
   const int x = (int)(o % Wc);
   const int64_t r = o / Wc;
   const int y = (int)(r % Hc);
   const int64_t c = r / Hc;
   const float *src = in + (c * H + (int64_t)S * y) * W + (int64_t)S * x;
-  float acc = 0.f;
+  float acc[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) acc[k] = 0.f;
 #pragma unroll
   for (int i = 0; i < S; ++i) {
     const float *row = src + (int64_t)i * W;
     if (VEC) {
 #pragma unroll
-      for (int j = 0; j < S; j += 4) {
+      for (int j = 0; j < (S < 4 ? 4 : S); j += 4) {
         const float4 q = *(const float4 *)(row + j);
-        acc += q.x;
-        acc += q.y;
-        acc += q.z;
-        acc += q.w;
+        const float e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[(j + k) / S % PX] += e[k];
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < S; ++j) acc += row[j];
+      for (int j = 0; j < S; ++j) acc[0] += row[j];
     }
   }
-  out[o] = acc * (1.0f / (float)(S * S));  // exact: a power of two
+  constexpr float kInv = 1.0f / (float)(S * S);  // exact: a power of two
+  if constexpr (PX == 4) {
+    *(float4 *)(out + o) = make_float4(acc[0] * kInv, acc[1] * kInv, acc[2] * kInv, acc[3] * kInv);
+  } else if constexpr (PX == 2) {
+    *(float2 *)(out + o) = make_float2(acc[0] * kInv, acc[1] * kInv);
+  } else {
+    out[o] = acc[0] * kInv;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_keep_flags(const float *logits, int64_t n, float thr, uint32_t *flags) {
@@ -53,27 +65,54 @@ __global__ __launch_bounds__(256) void k_keep_index(const uint32_t *flags, const
   if (i < n && flags[i]) index[pos[i]] = (int32_t)i;
 }
 
-// Grid (column chunks, planes).  An index outside [0, n_src) gives 0.
-__global__ __launch_bounds__(256) void k_gather_planes(const float *src, int64_t n_src, const int32_t *index,
-                                                       int64_t m, float *dst) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+// Grid (column chunks, plane groups of kGatherPlanes).  An index outside
+// [0, n_src) gives 0.  VEC (m a multiple of 4, index and dst 16-byte
+// aligned): four columns per lane, one 16-byte index load for the whole
+// plane group and one 16-byte store per plane.
+constexpr int kGatherPlanes = 8;
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_gather_planes(const float *src, int64_t n_src, int planes,
+                                                       const int32_t *index, int64_t m, float *dst) {
+  constexpr int PX = VEC ? 4 : 1;
+  const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * PX;
   if (j >= m) return;
-  const int64_t p = blockIdx.y;
-  const int32_t k = index[j];
-  dst[p * m + j] = (k >= 0 && k < n_src) ? src[p * n_src + k] : 0.0f;
+  int32_t k[PX];
+  if constexpr (VEC) {
+    const int4 q = *(const int4 *)(index + j);
+    k[0] = q.x, k[1] = q.y, k[2] = q.z, k[3] = q.w;
+  } else {
+    k[0] = index[j];
+  }
+  bool ok[PX];
+#pragma unroll
+  for (int c = 0; c < PX; ++c) ok[c] = k[c] >= 0 && k[c] < n_src;
+  const int p0 = blockIdx.y * kGatherPlanes;
+#pragma unroll
+  for (int u = 0; u < kGatherPlanes; ++u) {
+    const int p = p0 + u;
+    if (p >= planes) break;
+    const float *plane = src + (int64_t)p * n_src;
+    float x[PX];
+#pragma unroll
+    for (int c = 0; c < PX; ++c) x[c] = ok[c] ? plane[k[c]] : 0.0f;
+    if constexpr (VEC)
+      *(float4 *)(dst + (int64_t)p * m + j) = make_float4(x[0], x[1], x[2], x[3]);
+    else
+      dst[(int64_t)p * m + j] = x[0];
+  }
 }
 
 template <int S>
 gs_status launch_downsample(const float *in, int W, int H, int Wc, int Hc, int64_t total, float *out,
                             hipStream_t s) {
-  const unsigned grid = (unsigned)((total + 255) / 256);
-  const bool vec = S % 4 == 0 && W % 4 == 0 && ((uintptr_t)in & 15u) == 0;
-  if constexpr (S % 4 == 0) {
-    if (vec) {
-      GS_LAUNCH("downsample", (k_downsample<S, true>), grid, 256, 0, s, in, W, H, Wc, Hc, total, out);
-      return GS_OK;
-    }
+  const bool vec = W % 4 == 0 && ((uintptr_t)in & 15u) == 0 && ((uintptr_t)out & 15u) == 0;
+  if (vec) {
+    constexpr int PX = S < 4 ? 4 / S : 1;
+    const unsigned grid = (unsigned)((total / PX + 255) / 256);
+    GS_LAUNCH("downsample", (k_downsample<S, true>), grid, 256, 0, s, in, W, H, Wc, Hc, total, out);
+    return GS_OK;
   }
+  const unsigned grid = (unsigned)((total + 255) / 256);
   GS_LAUNCH("downsample", (k_downsample<S, false>), grid, 256, 0, s, in, W, H, Wc, Hc, total, out);
   return GS_OK;
 }
@@ -181,8 +220,17 @@ gs_status gs_gather_planes(const float *src, int64_t n_src, int32_t planes, cons
   if (m == 0 || planes == 0) return GS_OK;
   GS_REQUIRE(src && index && dst, "gs_gather_planes: NULL argument");
   GS_REQUIRE(src != dst, "gs_gather_planes: src and dst must not be the same buffer");
-  const dim3 grid((unsigned)((m + 255) / 256), (unsigned)planes);
-  GS_LAUNCH("gather_planes", k_gather_planes, grid, 256, 0, (hipStream_t)stream, src, n_src, index, m, dst);
+  const auto a16 = [](const void *q) { return ((uintptr_t)q & 15u) == 0; };
+  const unsigned groups = (unsigned)((planes + kGatherPlanes - 1) / kGatherPlanes);
+  if (m % 4 == 0 && a16(index) && a16(dst)) {
+    const dim3 grid((unsigned)((m / 4 + 255) / 256), groups);
+    GS_LAUNCH("gather_planes", k_gather_planes<true>, grid, 256, 0, (hipStream_t)stream, src, n_src, (int)planes,
+              index, m, dst);
+    return GS_OK;
+  }
+  const dim3 grid((unsigned)((m + 255) / 256), groups);
+  GS_LAUNCH("gather_planes", k_gather_planes<false>, grid, 256, 0, (hipStream_t)stream, src, n_src, (int)planes,
+            index, m, dst);
   return GS_OK;
 }
 
