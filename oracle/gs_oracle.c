@@ -13,7 +13,11 @@
  * What this computes is the plain definition, with no acceleration beyond a
  * conservative bounding-box pre-test:
  *   * every Gaussian is projected on its own (EWA: Sigma2 = J W Sigma W^T J^T
- *     + eps I);
+ *     + eps I).  With the screen-space filter of multi-scale training
+ *     (section 4.3 cites Mip-Splatting for it), eps I is the covariance of a
+ *     Gaussian low-pass filter convolved with the splat, and the opacity is
+ *     scaled by rho = sqrt(det(Sigma2 - eps I) / det Sigma2) so that the
+ *     splat's integral o rho 2 pi sqrt(det Sigma2) does not depend on eps;
  *   * the visible Gaussians are put in (depth, index) order once;
  *   * every pixel walks ALL of them front to back: alpha = min(alpha_max,
  *     o * exp(-d^T Sigma2^-1 d / 2)); an alpha below alpha_min is skipped;
@@ -51,6 +55,7 @@ typedef struct {
   double alpha_min; /* smallest alpha that is composited */
   double t_min;     /* transmittance cutoff */
   double guard;     /* guard band factor of the Jacobian clamp */
+  int32_t mip_filter; /* 1: eps2d is a screen-space filter with opacity compensation */
 } orc_cam;
 
 typedef struct {
@@ -194,6 +199,7 @@ typedef struct {
   int clx, cly; /* Jacobian clamp active on x / y */
   double qn[4], qnorm, Rq[9], s[3], M[9], Sig[9], V[9], J[6];
   double a, b, c, det, A, B, C;
+  double a0, c0, det0, rho, osig; /* unfiltered covariance, its determinant, compensation, sigmoid */
   double mx, my, o, lmax, rarg, hx, hy;
   double dir[3], dnorm, dhat[3], val[3], rgb[3];
   int clamped;
@@ -267,10 +273,13 @@ static void project_one(const orc_cam *cam, const orc_gauss *g, int64_t i, gfwd 
   for (int r = 0; r < 2; ++r)
     for (int cc = 0; cc < 2; ++cc)
       S2[2 * r + cc] = JV[3 * r] * f->J[3 * cc] + JV[3 * r + 1] * f->J[3 * cc + 1] + JV[3 * r + 2] * f->J[3 * cc + 2];
+  f->a0 = S2[0];
+  f->c0 = S2[3];
   f->a = S2[0] + cam->eps2d;
   f->b = 0.5 * (S2[1] + S2[2]);
   f->c = S2[3] + cam->eps2d;
   f->det = f->a * f->c - f->b * f->b;
+  f->det0 = f->a0 * f->c0 - f->b * f->b;
   if (!(f->det > 0.0)) return;
   f->A = f->c / f->det;
   f->B = -f->b / f->det;
@@ -280,7 +289,9 @@ static void project_one(const orc_cam *cam, const orc_gauss *g, int64_t i, gfwd 
   f->my = cam->fy * f->p[1] / z + cam->cy;
 
   const double al = g->opacity_logits[i];
-  f->o = 1.0 / (1.0 + exp(-al));
+  f->osig = 1.0 / (1.0 + exp(-al));
+  f->rho = cam->mip_filter ? sqrt(fmax(f->det0, 0.0) / f->det) : 1.0;
+  f->o = f->osig * f->rho;
   if (!(f->o >= cam->alpha_min)) return;
   const double h = 0.5 * (f->a - f->c);
   f->lmax = 0.5 * (f->a + f->c) + sqrt(h * h + f->b * f->b);
@@ -650,8 +661,8 @@ void orc_project_bwd(const orc_cam *cam, const orc_gauss *g, const double *g2d, 
       for (int a = 0; a < 3; ++a) gmu[a] += (gdh[a] - f.dhat[a] * dd) / f.dnorm;
     }
 
-    /* opacity logit */
-    d_opacity_logits[i] += gi[5] * f.o * (1.0 - f.o);
+    /* opacity logit: o = sigmoid(logit) rho */
+    d_opacity_logits[i] += gi[5] * f.rho * f.osig * (1.0 - f.osig);
 
     /* conic -> Sigma2 (full-matrix gradient, symmetric) */
     const double Q[4] = {f.A, f.B, f.B, f.C};
@@ -661,6 +672,16 @@ void orc_project_bwd(const orc_cam *cam, const orc_gauss *g, const double *g2d, 
       for (int c = 0; c < 2; ++c) QG[2 * r + c] = Q[2 * r] * Gq[c] + Q[2 * r + 1] * Gq[2 + c];
     for (int r = 0; r < 2; ++r)
       for (int c = 0; c < 2; ++c) gS2[2 * r + c] = -(QG[2 * r] * Q[c] + QG[2 * r + 1] * Q[2 + c]);
+    if (cam->mip_filter) {
+      /* rho^2 = det0 / det with det0 = a0 c0 - b^2, det = (a0 + eps)(c0 + eps) - b^2:
+         d rho = d(rho^2) / (2 rho), quotient rule; the off-diagonal b sits in two entries */
+      const double g_rho = gi[5] * f.osig, D0 = f.det0, D = f.det, k = g_rho / (2.0 * f.rho * D * D);
+      gS2[0] += k * (f.c0 * D - D0 * f.c);
+      gS2[3] += k * (f.a0 * D - D0 * f.a);
+      const double gb = k * (-2.0 * f.b * D + 2.0 * f.b * D0);
+      gS2[1] += 0.5 * gb;
+      gS2[2] += 0.5 * gb;
+    }
 
     /* Sigma2 = J V J^T + eps I:  gV = J^T gS2 J,  gJ = 2 gS2 J V */
     double gV[9], gJ[6], JV[6];

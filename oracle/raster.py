@@ -38,7 +38,7 @@ class _Cam(C.Structure):
                 ("cx", C.c_double), ("cy", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
                 ("near_plane", C.c_double), ("bg", C.c_double * 3), ("eps2d", C.c_double),
                 ("alpha_max", C.c_double), ("alpha_min", C.c_double), ("t_min", C.c_double),
-                ("guard", C.c_double)]
+                ("guard", C.c_double), ("mip_filter", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -93,6 +93,7 @@ class Camera:
     alpha_min: float = 1.0 / 255.0
     t_min: float = 1e-4
     guard: float = 1.3
+    mip_filter: int = 0  # 1: eps2d is a screen-space filter, opacity scaled by sqrt(det Sigma2_raw / det Sigma2)
 
     @staticmethod
     def from_view(view, **kw):
@@ -111,6 +112,7 @@ class Camera:
         c.bg[:] = list(self.bg)
         c.eps2d, c.alpha_max, c.alpha_min, c.t_min, c.guard = (self.eps2d, self.alpha_max, self.alpha_min,
                                                                  self.t_min, self.guard)
+        c.mip_filter = int(self.mip_filter)
         return c
 
 

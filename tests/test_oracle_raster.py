@@ -139,6 +139,65 @@ def test_single_gaussian_closed_form(oracle_lib):
     assert abs(gr["t"][2] - gr["means"][2, 0]) < 1e-10 * max(1, abs(ref))
 
 
+def test_mip_filter_single_gaussian_closed_form(oracle_lib):
+    # screen-space filter of variance eps: v_k = raw_k + eps and the opacity
+    # scaled by rho = sqrt(raw_1 raw_2 / (v_1 v_2)) for an axis-aligned splat
+    orc = oracle_lib
+    view, sc = _one_gaussian(s=(0.01, 0.015, 0.05), logit=1.5)
+    eps = 0.1
+    cam = _cam(orc, view, eps2d=eps, mip_filter=1)
+    g = _g(orc, sc)
+    proj, out = orc.forward(cam, g)
+    z, f = float(sc.means[2, 0]), cam.fx
+    s = np.exp(g.log_scales[:, 0])
+    r1, r2 = f * f * s[0] ** 2 / z ** 2, f * f * s[1] ** 2 / z ** 2
+    v1, v2 = r1 + eps, r2 + eps
+    rho = math.sqrt(r1 * r2 / (v1 * v2))
+    o = 1 / (1 + math.exp(-g.opacity_logits[0]))
+    assert abs(proj["opacity"][0] - o * rho) < 1e-15
+    yy, xx = np.mgrid[0:view.height, 0:view.width]
+    dx, dy = xx - view.cx, yy - view.cy
+    e = np.exp(-0.5 * (dx * dx / v1 + dy * dy / v2))
+    raw = o * rho * e
+    a = np.where(raw >= 1 / 255, np.minimum(raw, 0.99), 0.0)
+    assert np.abs(out["alpha"] - a).max() < 1e-14
+    rng = np.random.default_rng(1)
+    GA = rng.standard_normal((view.height, view.width))
+    gr = orc.backward(cam, g, proj, g_alpha=GA)
+    live = (raw >= 1 / 255) & (raw < 0.99)
+    # d alpha / d logit = e rho o (1 - o)
+    ref = np.sum(GA * live * e) * rho * o * (1 - o)
+    assert abs(gr["opacity_logits"][0] - ref) < 1e-10 * max(1, abs(ref))
+    # log-scale k: raw_k = f^2 s_k^2 / z^2 moves v_k and rho; d raw_k / d log s_k = 2 raw_k,
+    # d rho / d raw_k = rho (1 / raw_k - 1 / v_k) / 2, d alpha / d v_k = alpha d^2 / (2 v_k^2)
+    for k, (rk, vk, d2) in enumerate([(r1, v1, dx * dx), (r2, v2, dy * dy)]):
+        dv = np.sum(GA * live * raw * d2 / (2 * vk * vk))
+        drho = np.sum(GA * live * o * e) * rho * (1 / rk - 1 / vk) / 2
+        ref = (dv + drho) * 2 * rk
+        assert abs(gr["log_scales"][k, 0] - ref) < 1e-9 * max(1, abs(ref)), k
+
+
+def test_mip_filter_preserves_the_splat_integral(oracle_lib):
+    # the filter keeps o 2 pi sqrt(det Sigma2): the compensated opacity times
+    # sqrt(det) equals the unfiltered one's, whatever the filter variance
+    orc = oracle_lib
+    view, sc, _ = synth.tiny_scene(2, n=300, size=64)
+    g = _g(orc, sc)
+    p0 = orc.project(_cam(orc, view, eps2d=0.0), g)
+    for eps in (0.1, 0.3, 2.0):
+        p1 = orc.project(_cam(orc, view, eps2d=eps, mip_filter=1), g)
+        both = (p0["visible"] > 0) & (p1["visible"] > 0)
+        assert both.sum() > 100
+        det = lambda c: c[0] * c[2] - c[1] * c[1]
+        lhs = p1["opacity"][both] * np.sqrt(det(p1["cov2d"])[both])
+        rhs = p0["opacity"][both] * np.sqrt(det(p0["cov2d"])[both])
+        assert np.allclose(lhs, rhs, rtol=1e-9, atol=0)
+        assert (p1["opacity"][both] < p0["opacity"][both]).all()
+    # with eps = 0 the filter changes nothing
+    p2 = orc.project(_cam(orc, view, eps2d=0.0, mip_filter=1), g)
+    assert np.array_equal(p2["opacity"], p0["opacity"])
+
+
 def test_single_gaussian_alpha_clamp(oracle_lib):
     orc = oracle_lib
     view, sc = _one_gaussian(logit=8.0, s=(0.1, 0.1, 0.1))
@@ -233,12 +292,12 @@ def _fd_scene_ok(orc, cam, g):
     return (out["flags"] == 0).all()
 
 
-@pytest.mark.parametrize("deg,seed", [(0, 11), (3, 12)])
-def test_finite_differences_params(oracle_lib, deg, seed):
+@pytest.mark.parametrize("deg,seed,mip", [(0, 11, 0), (3, 12, 0), (3, 14, 1)])
+def test_finite_differences_params(oracle_lib, deg, seed, mip):
     orc = oracle_lib
     for s in range(seed, seed + 50):
         view, sc = synth.small_scene(s, sh_degree=deg)
-        cam = _cam(orc, view, bg=(0.2, 0.1, 0.05))
+        cam = _cam(orc, view, bg=(0.2, 0.1, 0.05), mip_filter=mip, eps2d=0.1 if mip else 0.3)
         g = _g(orc, sc)
         if _fd_scene_ok(orc, cam, g):
             break
