@@ -86,6 +86,10 @@ typedef struct {
   float alpha_min; /* smaller alphas are skipped (1/255) */
   float t_min;     /* a pixel stops before transmittance would drop below this (1e-4) */
   float guard;     /* guard band of the perspective Jacobian, in half-FOVs (1.3) */
+  int32_t mip_filter; /* 0: eps2d is the 3DGS dilation; else the screen-space filter
+                         of multi-scale training (section 4.3, Mip-Splatting): eps2d
+                         is the filter's variance (0.1 there) and each splat's opacity
+                         is scaled by sqrt(det Sigma2_raw / det Sigma2) (default 0) */
 } gs_raster_params;  /* HOST memory */
 
 typedef struct {
@@ -104,7 +108,7 @@ typedef struct {
   int32_t *tiles_touched; /* [n] number of 16x16 tiles the support square meets */
 } gs_projected;           /* HOST struct of DEVICE pointers */
 
-/* Fills *p with the constants above (0.3, 0.99, 1/255, 1e-4, 1.3). */
+/* Fills *p with the constants above (0.3, 0.99, 1/255, 1e-4, 1.3, 0). */
 void gs_default_params(gs_raster_params *p);
 
 const char *gs_last_error(void);
@@ -118,7 +122,9 @@ const char *gs_last_error(void);
  *   Sigma2 = J R Sigma R^T J^T + eps2d I; conic = Sigma2^-1;
  *   colour = max(0, sum_k sh_k Y_k(dir) + 0.5), dir = unit(mean - camera
  *   centre), real SH up to degree 3;
- *   o = sigmoid(logit); culled if o < alpha_min;
+ *   o = sigmoid(logit), times rho = sqrt(det Sigma2_raw / det Sigma2) with
+ *   Sigma2_raw = Sigma2 - eps2d I if mip_filter (the splat keeps its
+ *   integral o 2 pi sqrt(det Sigma2)); culled if o < alpha_min;
  *   support: the ellipse where o exp(-d^T conic d / 2) >= alpha_min, i.e.
  *   d^T conic d <= qmax = 2 ln(o / alpha_min); its bounding box has
  *   half-extents hx = sqrt(qmax Sigma2_xx), hy = sqrt(qmax Sigma2_yy) and

@@ -80,6 +80,7 @@ void gs_default_params(gs_raster_params *p) {
   p->alpha_min = 1.0f / 255.0f;
   p->t_min = 1e-4f;
   p->guard = 1.3f;
+  p->mip_filter = 0;
 }
 
 void gs_profile_enable(int on) { g_prof_on = on != 0; }

@@ -99,6 +99,7 @@ struct MultiArgs {
   int64_t n;
   int nv;
   float eps2d, alpha_min, guard;
+  int mip;  // eps2d is a screen-space filter whose opacity compensation applies
   const float *means, *log_scales, *quats, *opac, *sh;
   float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
   double *partials;                // [nv][gridDim.x][12] pose partial sums
@@ -221,6 +222,24 @@ __device__ __forceinline__ bool geometry(const MultiArgs &m, const ViewArgs &v, 
   return true;
 }
 
+__device__ __forceinline__ double real_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float real_sqrt(float x) { return __builtin_sqrtf(x); }
+
+// Opacity compensation of the screen-space filter: rho = sqrt(det0 / det)
+// with det0 the determinant of the unfiltered 2D covariance TM TM^T and
+// det that of the filtered one.  det0 is the sum of the squared 2x2 minors
+// of TM (Cauchy-Binet: never negative, no cancellation between a0 c0 and
+// b^2 for thin splats); det = det0 + eps (a0 + c0) + eps^2.
+template <class Real>
+__device__ __forceinline__ Real mip_rho(const Geo<Real> &f, Real eps, Real &det0, Real &det) {
+  const Real m01 = f.TM[0] * f.TM[4] - f.TM[1] * f.TM[3];
+  const Real m02 = f.TM[0] * f.TM[5] - f.TM[2] * f.TM[3];
+  const Real m12 = f.TM[1] * f.TM[5] - f.TM[2] * f.TM[4];
+  det0 = m01 * m01 + m02 * m02 + m12 * m12;
+  det = det0 + eps * (f.a + f.c - eps);  // a0 + c0 + eps = a + c - eps
+  return real_sqrt(det0 / det);
+}
+
 // Unit view direction from the camera centre C = -R^T t and 1/|mu - C|.
 template <class Real>
 __device__ __forceinline__ void view_dir(const Real R[9], const Real t[3], const Real mu[3], Real d[3], Real &dinv) {
@@ -251,6 +270,10 @@ __device__ __forceinline__ void project_one(const MultiArgs &m, const ViewArgs &
   }
   if (ok) {
     o = 1.0 / (1.0 + exp(-(double)P.logit));
+    if (m.mip) {
+      double det0, det;
+      o *= mip_rho<double>(f, (double)m.eps2d, det0, det);
+    }
     ok = o >= (double)m.alpha_min;
   }
   if (ok) {
@@ -328,18 +351,29 @@ __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs
   gc[1] = rgbz.y > 0.f ? g1.w : 0.f;
   gc[2] = rgbz.z > 0.f ? g2.x : 0.f;
 
-  {
-    const float o = real_rcp(1.0f + __expf(-P.logit));
-    acc.go += g1.y * o * (1.0f - o);
-  }
+  // opacity o = sigmoid(logit) rho (rho = 1 without the screen-space filter)
+  const float osig = real_rcp(1.0f + __expf(-P.logit));
+  float rho = 1.0f, det0 = 0.f, detf = 1.f;
+  if (m.mip) rho = mip_rho<float>(f, m.eps2d, det0, detf);
+  acc.go += g1.y * rho * osig * (1.0f - osig);
 
   // conic -> Sigma2: dL/dSigma2 = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
   const float gA = g0.z, hB = 0.5f * g0.w, gC = g1.x;
   const float QG00 = f.A * gA + f.B * hB, QG01 = f.A * hB + f.B * gC;
   const float QG10 = f.B * gA + f.C * hB, QG11 = f.B * hB + f.C * gC;
-  const float S00 = -(QG00 * f.A + QG01 * f.B);
-  const float S01 = -(QG00 * f.B + QG01 * f.C);
-  const float S11 = -(QG10 * f.B + QG11 * f.C);
+  float S00 = -(QG00 * f.A + QG01 * f.B);
+  float S01 = -(QG00 * f.B + QG01 * f.C);
+  float S11 = -(QG10 * f.B + QG11 * f.C);
+  if (m.mip && det0 > 0.f) {
+    // rho through the unfiltered covariance (a0, b, c0): d rho = rho / 2 d(ln det0 - ln det),
+    // with d ln det0 = (c0, -2 b, a0) / det0 and d ln det = (c, -2 b, a) / det; the
+    // off-diagonal b sits in two entries of the full-matrix gradient
+    const float k = 0.5f * g1.y * osig * rho, i0 = real_rcp(det0), i1 = real_rcp(detf);
+    const float a0 = f.a - m.eps2d, c0 = f.c - m.eps2d;
+    S00 += k * (c0 * i0 - f.c * i1);
+    S11 += k * (a0 * i0 - f.a * i1);
+    S01 += k * f.b * (i1 - i0);
+  }
 
   // Sigma2 = TM TM^T: gTM = 2 S TM
   float gTM[6];
@@ -707,6 +741,7 @@ MultiArgs multi_args(const gs_raster_params *rp, const gs_gaussians *g) {
   m.eps2d = rp->eps2d;
   m.alpha_min = rp->alpha_min;
   m.guard = rp->guard;
+  m.mip = rp->mip_filter != 0;
   m.means = g->means; m.log_scales = g->log_scales; m.quats = g->quats; m.opac = g->opacity_logits; m.sh = g->sh;
   m.gm = m.gl = m.gq = m.go = m.gsh = nullptr;
   m.partials = nullptr;

@@ -44,7 +44,7 @@ class _Camera(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("eps2d", C.c_float), ("alpha_max", C.c_float), ("alpha_min", C.c_float), ("t_min", C.c_float),
-                ("guard", C.c_float)]
+                ("guard", C.c_float), ("mip_filter", C.c_int32)]
 
 
 class _Gauss(C.Structure):
@@ -162,9 +162,10 @@ class Params:
     alpha_min: float = 1.0 / 255.0
     t_min: float = 1e-4
     guard: float = 1.3
+    mip_filter: int = 0  # 1: eps2d is a screen-space filter with opacity compensation
 
     def c(self):
-        return _Params(self.eps2d, self.alpha_max, self.alpha_min, self.t_min, self.guard)
+        return _Params(self.eps2d, self.alpha_max, self.alpha_min, self.t_min, self.guard, int(self.mip_filter))
 
 
 @dataclass
@@ -245,7 +246,7 @@ class Projected:
 def default_params() -> Params:
     p = _Params()
     _lib.gs_default_params(C.byref(p))
-    return Params(p.eps2d, p.alpha_max, p.alpha_min, p.t_min, p.guard)
+    return Params(p.eps2d, p.alpha_max, p.alpha_min, p.t_min, p.guard, p.mip_filter)
 
 
 def alloc_projected(n: int, device="cuda") -> Projected:

@@ -42,6 +42,9 @@ def test_default_params(lib):
     p = gsmi.default_params()
     assert abs(p.eps2d - 0.3) < 1e-7 and abs(p.alpha_max - 0.99) < 1e-7
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.t_min - 1e-4) < 1e-10 and abs(p.guard - 1.3) < 1e-7
+    assert p.mip_filter == 0
+    # the C struct matches the header's layout: five floats, then the filter flag
+    assert C.sizeof(gsmi._Params) == 24 and gsmi._Params.mip_filter.offset == 20
 
 
 def test_host_validation_rejects_bad_calls(lib):

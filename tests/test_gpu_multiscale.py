@@ -2,18 +2,21 @@
 oracle in oracle/multiscale.py and oracle/optim.py: per-Gaussian Adam rates
 and their decay, the coarse-to-fine box filter (every level, ragged sizes,
 both load paths, the full 1920x1080 frame), a full forward + adjoint at the
-coarse camera, and opacity culling (bit-exact keep lists, gathers, and an
-image that culling below alpha_min leaves bit-identical)."""
+coarse camera, the screen-space (Mip-Splatting) filter with opacity
+compensation through projection, compositing and both adjoints, and opacity
+culling (bit-exact keep lists, gathers, and an image that culling below
+alpha_min leaves bit-identical)."""
 import numpy as np
 import pytest
 import torch
 
 from oracle import multiscale as ms
 from oracle import optim
+from oracle import raster as orc
 from paper_2506_05558_amd import synth
 
 from . import gpu_common as gc
-from .test_gpu_raster import _full_case
+from .test_gpu_raster import FLAG_REL, _check_binning, _check_grads, _check_image, _full_case
 
 pytestmark = pytest.mark.gpu
 
@@ -135,3 +138,63 @@ def test_culling_below_alpha_min_leaves_the_image_bit_identical():
     _, _, cut = gc.run_forward(cam, g2)
     assert torch.equal(full.image, cut.image) and torch.equal(full.depth, cut.depth)
     assert torch.equal(full.final_t, cut.final_t)
+
+
+def _mip_case(name, view, scene, seed, eps=0.1):
+    gs = gc.gpu()
+    params = gs.Params(eps2d=eps, mip_filter=1)
+    cam = gc.gpu_camera(view)
+    g = gc.gpu_gauss(scene)
+    proj = gs.project(cam, g, params)
+    binned = gs.BinSorter(0)(cam, proj)
+    frame = gs.render_fwd(cam, proj, binned, params)
+    torch.cuda.synchronize()
+    ocam = orc.Camera.from_view(view, eps2d=eps, mip_filter=1)
+    og = orc.Gaussians.from_scene(scene)
+    op = orc.project(ocam, og)
+    rec = proj.rec.cpu().numpy()
+    vis = op["visible"] > 0
+    assert np.array_equal(vis, proj.radius.cpu().numpy()[0] > 0)
+    # the compensated opacity, and the support box it sets
+    assert np.abs(rec[vis, 7] - op["opacity"][vis]).max() <= 1e-6
+    assert np.abs(rec[vis, 12:14] - op["half"].T[vis]).max() <= 1e-6 * (1 + np.abs(op["half"]).max())
+    _check_binning(view, proj, binned)
+    ref = orc.render(ocam, op, flag_rel=FLAG_REL)
+    _check_image(name, frame, ref)
+    gi, gd, ga = gc.flagged_upstream((view.height, view.width), ref["flags"], seed)
+    d_pose = torch.zeros(12, dtype=torch.float64, device="cuda")
+    d_twist = torch.zeros(6, dtype=torch.float64, device="cuda")
+    grads = gs.render_bwd(cam, g, proj, binned, frame, torch.tensor(gi, device="cuda"),
+                          torch.tensor(gd, device="cuda"), torch.tensor(ga, device="cuda"), dL_dpose=d_pose,
+                          dL_dtwist=d_twist, params=params)
+    torch.cuda.synchronize()
+    _check_grads(name, grads, d_pose, d_twist, orc.backward(ocam, og, op, gi, gd, ga))
+
+
+def test_mip_filter_full_parity():
+    view, scene, _ = synth.tiny_scene(13)
+    _mip_case("mip", view, scene, seed=3)
+
+
+def test_mip_filter_at_the_coarse_camera():
+    # the filter's purpose: the coarse levels of coarse-to-fine training
+    view, scene, _ = synth.tiny_scene(14, n=3000, size=160)
+    w, h, fx, fy, cx, cy = ms.camera_level(view.width, view.height, view.fx, view.fy, view.cx, view.cy, 2)
+    cv = synth.View(w, h, np.float32(fx), np.float32(fy), np.float32(cx), np.float32(cy), view.R, view.t)
+    _mip_case("mip-coarse2", cv, scene, seed=4)
+
+
+def test_mip_filter_window_views_match_single_view():
+    # the multi-view projection and adjoint take the same filter per view
+    gs = gc.gpu()
+    params = gs.Params(eps2d=0.1, mip_filter=1)
+    views = synth.trajectory(5, 3, 96, 64)
+    scene = synth.window_scene(5, views, 800, 1)
+    g = gc.gpu_gauss(scene)
+    cams = [gc.gpu_camera(v) for v in views]
+    wv = [gs.View(c, gs.alloc_projected(g.n), None, torch.empty(g.n, dtype=torch.int32, device="cuda"))
+          for c in cams]
+    gs.project_views(wv, g, params)
+    for c, v in zip(cams, wv):
+        one = gs.project(c, g, params)
+        assert torch.equal(one.rec, v.proj.rec) and torch.equal(one.radius, v.proj.radius)
