@@ -96,7 +96,8 @@ def main():
     n = gt_scene.n
     print(f"# scene generated in {time.time() - t0:.1f}s: {n} Gaussians", file=sys.stderr, flush=True)
 
-    params = gsmi.Params()
+    # the screen-space filter of multi-scale training (variance 0.1 px^2, opacity compensated)
+    params = gsmi.Params(eps2d=0.1, mip_filter=1)
     sorter = gsmi.BinSorter(capacity=12 * PER_VIEW * N_VIEWS)
     H, W = H_IMG, W_IMG
 
@@ -298,7 +299,8 @@ def main():
     names = ["project", "bin_flags", "bin_compact", "radix_hist", "radix_scatter", "scan", "bin_counts",
              "bin_duplicate", "bin_ranges", "bin_fill", "render_fwd", "loss_l1", "loss_final", "render_bwd",
              "project_bwd", "project_bwd_sh", "pose_reduce", "adam", "lr_decay", "zero", "mark_visible", "pose_6d",
-             "pose_6d_bwd", "downsample", "prune_flags", "prune_index", "gather_planes", "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
+             "pose_6d_bwd", "downsample", "prune_flags", "prune_index", "gather_planes", "spawn_prob", "spawn_select",
+             "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
 
     def read_profile():
         out = {}
@@ -421,8 +423,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "one keyframe: spawn on the new 1920x1080 frame (LoG probability vs the render, "
                                "fixed-K 100k, rule + BF16 MLP), 30 joint pose+Gaussian iterations over 8 keyframes "
-                               "x 1920x1080 with 2M Gaussians (8 x 250k ray-seeded, SH degree 3, L1, sparse Adam), "
-                               "one FP32 MLP training step (batch 4096)",
+                               "x 1920x1080 with 2M Gaussians (8 x 250k ray-seeded, SH degree 3, screen-space "
+                               "filter, L1, sparse Adam with per-Gaussian rates), one FP32 MLP training step "
+                               "(batch 4096)",
                    "views": N_VIEWS, "width": W, "height": H, "gaussians": n, "sh_degree": SH_DEG,
                    "iters_per_keyframe": args.iters, "spawn_k": SPAWN_K, "mlp_batch": MLP_BATCH},
         "spawned_per_keyframe": n_spawned[-1] if n_spawned else None,
