@@ -558,7 +558,7 @@ def cpu_baseline(view, scene, n_crops):
     from oracle import raster as orc
 
     threads = min(os.cpu_count() or 1, 64)
-    cam = orc.Camera.from_view(view)
+    cam = orc.Camera.from_view(view, eps2d=0.1, mip_filter=1)
     og = orc.Gaussians.from_scene(scene)
     t0 = time.perf_counter()
     op = orc.project(cam, og)
