@@ -500,6 +500,7 @@ def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms
         ms, cnt = gsmi.profile_read("downsample")
         nbytes = 4 * c * ((h >> lv) << lv) * ((w >> lv) << lv) + 4 * out.numel()
         down[f"level{lv}"] = hbm(nbytes, ms / cnt)
+        down[f"level{lv}"]["traffic"] = measured_traffic(f"downsample_level{lv}")
 
     n = g.n
     state = [t for gg in (g, m1, m2) for t in gg.tensors()] + [rates]
@@ -519,6 +520,13 @@ def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms
     torch.cuda.empty_cache()
     ms_keep = prof["prune_flags"][0] + prof["scan"][0] + prof["prune_index"][0]
     ms_gather = prof["gather_planes"][0]
+    # the gather runs once per state tensor: the roofline covers all of them together
+    gather_roof = hbm(kept * (8 * planes + 4), ms_gather)
+    per_launch = measured_traffic("gather_planes")
+    gather_roof["traffic"] = None if per_launch is None else per_launch * len(state)
+    gather_roof["launches"] = len(state)
+    gather_roof["ms_per_launch"] = ms_gather / len(state)
+    gather_roof["ms_total"] = ms_gather
     return {
         "coarse_to_fine_keyframe_ms": round(ms_c2f, 3), "full_size_keyframe_ms": round(ms_full, 3),
         "newest_view_levels": [gsmi.coarse_level(i) for i in range(iters)],
@@ -526,7 +534,7 @@ def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms
         "opacity_culling": {"gaussians": n, "kept": kept, "min_opacity": 0.005, "planes_gathered": planes,
                             "keep_list_ms": round(ms_keep, 4), "gather_ms": round(ms_gather, 4),
                             # per kept Gaussian and plane: 4 B read + 4 B written, plus the 4 B index
-                            "gather_roofline": hbm(kept * (8 * planes + 4), ms_gather)},
+                            "gather_roofline": gather_roof},
     }
 
 
