@@ -40,11 +40,13 @@ ITERS, SPAWN_K, MLP_BATCH = 30, 100_000, 4096
 # LR_DECAY (the ratio is not given; the factor halves after ~140 processed steps)
 LR_DECAY = 0.995
 
-# MI355X peaks (published): HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s with
-# packed FP32, which the kernels are compiled without: unpacked VALU issue
-# is 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s.
+# MI355X peaks (published): HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s counts an
+# FMA as two flops, so one lane-op per FMA gives 78.6 T lane-ops/s
+# (256 CU x 4 SIMD x 32 lanes x 2.4 GHz).  Non-packed v_fma_f32 reaches it:
+# the FMA probe measures 58.6 T lane-ops/s, above a 16-lane-per-clock
+# reading (39.3), and v_exp_f32 a quarter of 78.6.
 PEAK_HBM_GBS = 8000.0
-PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_VALU_TOPS = 157.3 / 2
 
 # Algorithmic work (lane-operations) per (pixel, Gaussian) pair, from the
 # definition.  Only pairs inside the Gaussian's support (alpha >= alpha_min)
@@ -360,6 +362,7 @@ def main():
 
     ms_step = elapsed * 1e3 / args.steps
     multiscale = measure_multiscale(gsmi, keyframe_step, args.iters, targets, g, m1, m2, rates, ms_step)
+    peaks = measure_peaks(gsmi)
     mpix = args.iters * N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
 
     def roof(name, ks=kernels):
@@ -407,6 +410,11 @@ def main():
     for k, r in others.items():
         if r is not None:
             r["traffic"] = measured_traffic(k)
+    # the same fractions against the rates measured on this device
+    measured_peak = {"GB/s": peaks["hbm_copy_GBs"], "Tlane-op/s": peaks["valu_fma_Tlaneop_s"]}
+    for r in [roofline, solo, *others.values()]:
+        if r is not None:
+            r["frac_of_measured_peak"] = r["achieved"] / measured_peak[r["unit"]]
 
     out = {
         "metric": "fwd+bwd Mpix/s @1080p 2M Gaussians; steps-to-PSNR learned-init vs plain",
@@ -439,6 +447,7 @@ def main():
                            "visible_gaussians": visible_per_view},
         "psnr_start_end": [round(sum(psnr0) / N_VIEWS, 3), round(sum(psnr1) / N_VIEWS, 3)],
         "multiscale": multiscale,
+        "measured_peaks": peaks,
     }
     if not args.no_study:
         # second half of the metric: learned vs rule initialisation of spawned primitives
@@ -466,6 +475,42 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     print(json.dumps(out))
+
+
+def measure_peaks(gsmi):
+    """The achievable rates on this device beside the datasheet peaks: a 1 GiB 16-byte copy
+    (read + written bytes per second), 8 chains of v_fma_f32 and of v_exp_f32 per lane over
+    2048 workgroups of 256 lanes (8 waves per SIMD), lane-ops per second."""
+    import torch
+    dev = "cuda"
+    src = torch.ones(256 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    out = torch.empty(2048 * 256, dtype=torch.float32, device=dev)
+    res = {}
+    for name, run, work in [
+        ("probe_copy", lambda: gsmi.probe_copy(src, dst), 2 * src.numel() * 4),
+        ("probe_fma", lambda: gsmi.probe_valu(0, 2048, 16384, out), 2048 * 256 * 16384 * 8),
+        ("probe_exp", lambda: gsmi.probe_valu(1, 2048, 4096, out), 2048 * 256 * 4096 * 8),
+    ]:
+        run()
+        torch.cuda.synchronize()
+        gsmi.profile_reset()
+        gsmi.profile_select([name])
+        gsmi.profile_enable(True)
+        for _ in range(5):
+            run()
+        torch.cuda.synchronize()
+        gsmi.profile_enable(False)
+        ms, cnt = gsmi.profile_read(name)
+        res[name] = work / (ms / cnt * 1e-3)
+    gsmi.profile_select(None)
+    gsmi.profile_reset()
+    del src, dst, out
+    torch.cuda.empty_cache()
+    return {"hbm_copy_GBs": round(res["probe_copy"] / 1e9, 1),
+            "valu_fma_Tlaneop_s": round(res["probe_fma"] / 1e12, 2),
+            "valu_exp_Tlaneop_s": round(res["probe_exp"] / 1e12, 2),
+            "datasheet": {"hbm_GBs": PEAK_HBM_GBS, "valu_Tlaneop_s": round(PEAK_VALU_TOPS, 2)}}
 
 
 def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms_full):

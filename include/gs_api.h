@@ -500,6 +500,18 @@ gs_status gs_spawn_init(const gs_camera *cam, const float *image, const float *d
                         const gs_spawn_params *sp, const void *mlp_packed, gs_gaussians *out, int64_t offset,
                         int64_t *n_spawned, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- measurement probes --------------------------------------------------
+ * The achievable rates on the device, reported beside the datasheet peaks
+ * that the roofline fractions use.
+ * gs_probe_copy: dst = src over `bytes` bytes with 16-byte loads and
+ * stores (2 x bytes of HBM traffic); bytes and both pointers 16-byte
+ * multiples, device memory, not overlapping.
+ * gs_probe_valu: blocks x 256 lanes each run iters x 8 independent chains of
+ * one VALU operation -- kind 0: v_fma_f32 (one lane-op per FMA), kind 1:
+ * v_exp_f32 -- and write one float per lane to out [blocks * 256]. */
+gs_status gs_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
+gs_status gs_probe_valu(int32_t kind, int32_t blocks, int32_t iters, float *out, void *stream);
+
 /* ---- profiling ----------------------------------------------------------
  * When enabled, every kernel launch is bracketed with HIP events on its
  * stream; gs_profile_read sums the elapsed milliseconds of all launches of

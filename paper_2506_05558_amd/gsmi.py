@@ -121,6 +121,8 @@ _sig = {
     "gs_spawn_init_workspace": (C.c_int, [_i32, _i32, _i64, _P(_sz)]),
     "gs_spawn_init": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _P(_SpawnParams), _vp, _P(_Gauss), _i64, _P(_i64), _vp,
                                 _sz, _vp]),
+    "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
+    "gs_probe_valu": (C.c_int, [_i32, _i32, _i32, _vp, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
     "gs_profile_reset": (None, []),
     "gs_profile_select": (None, [C.c_char_p]),
@@ -809,6 +811,16 @@ class MlpTrainer:
                                       self.eps, max(self.step_count, 1), self.loss.data_ptr(), _ptr(grad),
                                       self.ws.data_ptr(), self.ws.numel(), _stream()))
         return self.loss
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor):
+    """dst = src with the library's 16-byte copy kernel (HBM rate probe)."""
+    _check(_lib.gs_probe_copy(src.data_ptr(), dst.data_ptr(), src.numel() * src.element_size(), _stream()))
+
+
+def probe_valu(kind: int, blocks: int, iters: int, out: torch.Tensor):
+    """blocks x 256 lanes x iters x 8 chained v_fma_f32 (kind 0) or v_exp_f32 (kind 1)."""
+    _check(_lib.gs_probe_valu(kind, blocks, iters, out.data_ptr(), _stream()))
 
 
 def profile_enable(on: bool = True):

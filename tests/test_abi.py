@@ -188,3 +188,14 @@ def test_multiscale_validation(lib):
         assert L.gs_prune_workspace(n, C.byref(sz)) == 0
         sizes.append(sz.value)
     assert sizes == sorted(sizes) and sizes[-1] >= 8 * 2_000_000
+
+
+def test_probe_validation(lib):
+    from paper_2506_05558_amd import gsmi
+    L = gsmi._lib
+    assert L.gs_probe_copy(16, 32, 24, None) == 1          # not a 16-byte multiple
+    assert L.gs_probe_copy(16, 16, 32, None) == 1          # in place
+    assert L.gs_probe_copy(None, None, 0, None) == 0
+    assert L.gs_probe_valu(2, 8, 8, 16, None) == 1         # unknown kind
+    assert L.gs_probe_valu(0, 0, 8, 16, None) == 1         # no blocks
+    assert L.gs_probe_valu(1, 8, 8, None, None) == 1       # no output
