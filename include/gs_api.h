@@ -500,6 +500,35 @@ gs_status gs_spawn_init(const gs_camera *cam, const float *image, const float *d
                         const gs_spawn_params *sp, const void *mlp_packed, gs_gaussians *out, int64_t offset,
                         int64_t *n_spawned, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- guided-matching depth (the appendix on depth for new primitives) ----
+ * Depth for the primitives a frame spawns (section 4.2), found around the
+ * monocular depth Z*.  Per pixel (x, y) of frame i:
+ *   candidates d_k = lo + k (hi - lo) / (n_cand - 1), lo = max(1/Z* - r_inv,
+ *   1e-3), hi = 1/Z* + r_inv (inverse depths; the paper's r_inv = 0.1);
+ *   the neighbour j (of n_nb) whose reprojections of d_0 and d_{n-1} lie
+ *   farthest apart in pixels with both inside [0, W-1] x [0, H-1] and in
+ *   front of camera j (ties: the lower j; none: no estimate);
+ *   reprojection p = R_j (K^-1 (x, y, 1) / d_k) + t_j, (u, v) = (fx p_x /
+ *   p_z + cx, fy p_y / p_z + cy), shared intrinsics;
+ *   C_k = <F_i(x, y), F_j(u, v)>, F_j bilinear with pixel centres at
+ *   integers and taps outside the image counted as 0; a candidate behind
+ *   camera j has none;
+ *   k* = argmax C_k (lowest k on ties), delta = (C_{k*-1} - C_{k*+1}) /
+ *   (2 (C_{k*-1} - 2 C_{k*} + C_{k*+1})) when both neighbours exist and the
+ *   denominator is negative, else 0; depth = 1 / (lo + (k* + delta)(hi -
+ *   lo) / (n_cand - 1)).
+ * feat_i: FP16 [H][W][channels] (channel-last, 16-byte aligned), channels
+ * in {8, 16, 32, 64}; feat_nb: HOST array of n_nb (1..4) DEVICE pointers of
+ * the same layout; rel_poses: HOST [n_nb][12] = R (row-major) then t of
+ * each neighbour's camera relative to frame i's; zmono [H][W] FP32.
+ * Outputs [H][W]: depth (NaN: no estimate, also where Z* is not positive
+ * and finite), best = k* (optional, -1: none), choice = j (optional, -1).
+ * Inner products in FP32 from exact FP16 products.  n_cand 3..1024. */
+gs_status gs_guided_depth(int32_t width, int32_t height, int32_t channels, float fx, float fy, float cx, float cy,
+                          const void *feat_i, int32_t n_nb, const void *const *feat_nb, const float *rel_poses,
+                          const float *zmono, int32_t n_cand, float r_inv, float *depth, int32_t *best,
+                          int32_t *choice, void *stream);
+
 /* ---- measurement probes --------------------------------------------------
  * The achievable rates on the device, reported beside the datasheet peaks
  * that the roofline fractions use.

@@ -87,9 +87,10 @@ def choose_neighbour(K, poses, zmono, n: int, W: int, H: int):
     return choice
 
 
-def correlations(Fi, Fjs, K, poses, zmono, n: int):
+def correlations(Fi, Fjs, K, poses, zmono, n: int, mask=None):
     """[n][H][W] correlation volume against each pixel's chosen neighbour
-    (-inf where a candidate has none), the candidates and the choice."""
+    (-inf where a candidate has none, and outside mask if given), the
+    candidates and the choice."""
     H, W, _ = Fi.shape
     d = candidates(zmono, n)
     choice = choose_neighbour(K, poses, zmono, n, W, H)
@@ -97,7 +98,7 @@ def correlations(Fi, Fjs, K, poses, zmono, n: int):
     fi = Fi.astype(np.float64)
     C = np.full((n, H, W), -np.inf)
     for j, (R, t) in enumerate(poses):
-        sel = choice == j
+        sel = (choice == j) if mask is None else (choice == j) & mask
         if not sel.any():
             continue
         for k in range(n):
@@ -129,7 +130,15 @@ def refine(C, d):
     return depth, kb, delta
 
 
-def guided_depth(Fi, Fjs, K, poses, zmono, n: int = 32):
-    C, d, choice = correlations(Fi, Fjs, K, poses, zmono, n)
+def guided_depth(Fi, Fjs, K, poses, zmono, n: int = 32, mask=None):
+    """Depth per pixel (nan: no estimate, also where Z* is not a positive
+    finite number, and outside mask if given)."""
+    zmono = np.asarray(zmono, np.float64)
+    has = np.isfinite(zmono) & (zmono > 0)
+    zsafe = np.where(has, zmono, 1.0)
+    C, d, choice = correlations(Fi, Fjs, K, poses, zsafe, n, mask)
+    C[:, ~has] = -np.inf
+    choice = np.where(has, choice, -1)
     depth, kb, delta = refine(C, d)
-    return dict(depth=depth, best=kb, delta=delta, choice=choice, corr=C, cand=d)
+    return dict(depth=depth, best=np.where(np.isfinite(depth), kb, -1), delta=delta, choice=choice, corr=C,
+                cand=d)

@@ -16,6 +16,7 @@ import os
 from dataclasses import dataclass, field
 from typing import Optional
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -121,6 +122,8 @@ _sig = {
     "gs_spawn_init_workspace": (C.c_int, [_i32, _i32, _i64, _P(_sz)]),
     "gs_spawn_init": (C.c_int, [_P(_Camera), _vp, _vp, _vp, _P(_SpawnParams), _vp, _P(_Gauss), _i64, _P(_i64), _vp,
                                 _sz, _vp]),
+    "gs_guided_depth": (C.c_int, [_i32, _i32, _i32, _f, _f, _f, _f, _vp, _i32, _P(_vp), _P(C.c_float), _vp, _i32, _f,
+                                  _vp, _vp, _vp, _vp]),
     "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
     "gs_probe_valu": (C.c_int, [_i32, _i32, _i32, _vp, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
@@ -811,6 +814,29 @@ class MlpTrainer:
                                       self.eps, max(self.step_count, 1), self.loss.data_ptr(), _ptr(grad),
                                       self.ws.data_ptr(), self.ws.numel(), _stream()))
         return self.loss
+
+
+def guided_depth(feat_i: torch.Tensor, feat_nb, rel_poses, zmono: torch.Tensor, fx: float, fy: float, cx: float,
+                 cy: float, n_cand: int = 32, r_inv: float = 0.1, out=None):
+    """Depth around the monocular depth by feature correlation with the
+    neighbouring frames.  feat_i, feat_nb[j]: float16 [H][W][C]; rel_poses:
+    [n_nb][12] (host values: R row-major, t); returns (depth, best, choice)."""
+    H, W, Cc = feat_i.shape
+    for f in [feat_i, *feat_nb]:
+        _require(f, torch.float16, (H, W, Cc), "features")
+    _require(zmono, torch.float32, (H, W), "zmono")
+    if out is None:
+        dev = feat_i.device
+        out = (torch.empty((H, W), dtype=torch.float32, device=dev),
+               torch.empty((H, W), dtype=torch.int32, device=dev),
+               torch.empty((H, W), dtype=torch.int32, device=dev))
+    depth, best, choice = out
+    ptrs = (_vp * len(feat_nb))(*[f.data_ptr() for f in feat_nb])
+    poses = np.ascontiguousarray(np.asarray(rel_poses, np.float32).reshape(len(feat_nb), 12))
+    _check(_lib.gs_guided_depth(W, H, Cc, fx, fy, cx, cy, feat_i.data_ptr(), len(feat_nb), ptrs,
+                                poses.ctypes.data_as(_P(C.c_float)), zmono.data_ptr(), n_cand, r_inv,
+                                depth.data_ptr(), _ptr(best), _ptr(choice), _stream()))
+    return depth, best, choice
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor):

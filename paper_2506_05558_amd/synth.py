@@ -266,3 +266,42 @@ def mlp_init(seed: int, dims=(196, 64, 64, 7), last_scale: float = 0.1) -> np.nd
             w *= last_scale
         parts += [w.ravel(), np.zeros(dims[i + 1])]
     return np.concatenate(parts).astype(np.float32)
+
+
+def depth_frames(seed: int, width: int = 1920, height: int = 1080, channels: int = 32, n_nb: int = 2,
+                 mono_err: float = 0.15):
+    """Inputs of the guided-matching depth: frame i and n_nb neighbours
+    looking at a tilted textured plane Z = z0 + a X + b Y (frame i's
+    coordinates).  Features are random Fourier features of the plane point
+    (X, Y) where each pixel's ray meets the plane, stored float16 [H][W][C];
+    the monocular depth is the true depth times (1 + N(0, mono_err)).
+    Returns (feat_i, [feat_j], rel_poses [n_nb][12], zmono, true depth, K)."""
+    rng = np.random.default_rng(seed)
+    f = 0.7 * width
+    K = (f, f, (width - 1) / 2.0, (height - 1) / 2.0)
+    z0, a, b = rng.uniform(3.0, 6.0), rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3)
+    om = rng.normal(0.0, 2.0 * np.pi * f / (8.0 * z0), (channels, 2))  # texture periods of ~8 px at z0
+    ph = rng.uniform(0.0, 2.0 * np.pi, channels)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64)
+    rays = np.stack([(xx - K[2]) / K[0], (yy - K[3]) / K[1], np.ones_like(xx)], -1)
+    nrm = np.array([-a, -b, 1.0])
+
+    def view(R, t):
+        # camera j: p_j = R p_i + t, so its centre is -R^T t and its rays R^T r in frame i
+        o = -R.T @ t
+        d = rays @ R  # (R^T r) for every pixel
+        s = (z0 - nrm @ o) / (d @ nrm)
+        P = o + s[..., None] * d
+        phase = P[..., 0:1] * om[:, 0] + P[..., 1:2] * om[:, 1] + ph
+        return (np.sqrt(2.0 / channels) * np.cos(phase)).astype(np.float16), P[..., 2]
+
+    feat_i, z_true = view(np.eye(3), np.zeros(3))
+    feats, poses = [], []
+    for _ in range(n_nb):
+        R = _rotation(rng.standard_normal(3), math.radians(rng.uniform(0.5, 3.0)))
+        t = np.array([rng.uniform(-0.4, 0.4), rng.uniform(-0.1, 0.1), rng.uniform(-0.2, 0.2)])
+        fj, _ = view(R, t)
+        feats.append(fj)
+        poses.append(np.concatenate([R.reshape(9), t]))
+    zmono = (z_true * (1.0 + rng.normal(0.0, mono_err, z_true.shape))).astype(np.float32)
+    return feat_i, feats, np.array(poses, np.float32), zmono, z_true, K

@@ -199,3 +199,21 @@ def test_probe_validation(lib):
     assert L.gs_probe_valu(2, 8, 8, 16, None) == 1         # unknown kind
     assert L.gs_probe_valu(0, 0, 8, 16, None) == 1         # no blocks
     assert L.gs_probe_valu(1, 8, 8, None, None) == 1       # no output
+
+
+def test_guided_depth_validation(lib):
+    from paper_2506_05558_amd import gsmi
+    L = gsmi._lib
+    ptrs = (C.c_void_p * 1)(16)
+    pose = (C.c_float * 12)()
+    args = lambda **kw: dict(dict(w=64, h=32, c=32, nb=1, n=32, r=0.1, fi=16), **kw)
+
+    def call(a):
+        return L.gs_guided_depth(a["w"], a["h"], a["c"], 50.0, 50.0, 31.5, 15.5, a["fi"], a["nb"], ptrs, pose, 16,
+                                 a["n"], a["r"], 16, None, None, None)
+    assert call(args(c=24)) == 1      # channels not 8/16/32/64
+    assert call(args(nb=5)) == 1      # at most four neighbours
+    assert call(args(n=2)) == 1       # at least three candidates
+    assert call(args(r=0.0)) == 1     # empty range
+    assert call(args(fi=8)) == 1      # features not 16-byte aligned
+    assert call(args(w=0)) == 1
