@@ -363,6 +363,7 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     multiscale = measure_multiscale(gsmi, keyframe_step, args.iters, targets, g, m1, m2, rates, ms_step)
     peaks = measure_peaks(gsmi)
+    guided = measure_depth(gsmi, synth)
     mpix = args.iters * N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
 
     def roof(name, ks=kernels):
@@ -448,6 +449,7 @@ def main():
         "psnr_start_end": [round(sum(psnr0) / N_VIEWS, 3), round(sum(psnr1) / N_VIEWS, 3)],
         "multiscale": multiscale,
         "measured_peaks": peaks,
+        "guided_depth": guided,
     }
     if not args.no_study:
         # second half of the metric: learned vs rule initialisation of spawned primitives
@@ -475,6 +477,52 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     print(json.dumps(out))
+
+
+def measure_depth(gsmi, synth):
+    """Guided-matching depth of a new 1920x1080 frame (the appendix on depth for new primitives):
+    32 FP16 feature channels, 32 inverse-depth candidates, two neighbouring frames; the frame
+    and its neighbours view a tilted textured plane, the monocular depth is 15 % off."""
+    import numpy as np
+    import torch
+    W, H, C, N, NB = 1920, 1080, 32, 32, 2
+    fi, fjs, poses, zm, zt, K = synth.depth_frames(SEED, W, H, C, NB)
+    dev = "cuda"
+    t_fi = torch.tensor(fi, device=dev)
+    t_fj = [torch.tensor(f, device=dev) for f in fjs]
+    t_zm = torch.tensor(zm, device=dev)
+    out = gsmi.guided_depth(t_fi, t_fj, poses, t_zm, *K, n_cand=N)
+    torch.cuda.synchronize()
+    gsmi.profile_reset()
+    gsmi.profile_select(["guided_depth"])
+    gsmi.profile_enable(True)
+    for _ in range(10):
+        gsmi.guided_depth(t_fi, t_fj, poses, t_zm, *K, n_cand=N, out=out)
+    torch.cuda.synchronize()
+    gsmi.profile_enable(False)
+    ms, cnt = gsmi.profile_read("guided_depth")
+    gsmi.profile_select(None)
+    gsmi.profile_reset()
+    ms /= cnt
+    depth = out[0].cpu().numpy()
+    est = np.isfinite(depth)
+    n_est = int(est.sum())
+    # algorithmic work per pixel with an estimate: per candidate a bilinear sample (4 C
+    # multiply-adds) and an inner product (C); bytes: the frame's and the neighbours'
+    # features read once, Z* read, depth / best / choice written
+    ops = n_est * N * 5 * C
+    nbytes = W * H * (2 * C * (1 + NB) + 16)
+    a_ops = ops / (ms * 1e-3) / 1e12
+    a_hbm = nbytes / (ms * 1e-3) / 1e9
+    err = np.abs(depth[est] / zt[est] - 1)
+    return {"workload": f"{W}x{H}, {C} FP16 channels, {N} candidates, {NB} neighbouring frames",
+            "ms_per_frame": round(ms, 4), "Mpix_s": round(W * H / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "alu", "achieved": a_ops, "peak": PEAK_VALU_TOPS, "unit": "Tlane-op/s",
+                         "frac": a_ops / PEAK_VALU_TOPS, "traffic": measured_traffic("guided_depth")},
+            "hbm": {"achieved": a_hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a_hbm / PEAK_HBM_GBS},
+            "estimates": round(n_est / (W * H), 4),
+            "median_rel_error": round(float(np.median(err)), 5),
+            "monocular_median_rel_error": round(float(np.median(np.abs(zm[est] / zt[est] - 1))), 5)}
 
 
 def measure_peaks(gsmi):
