@@ -5,12 +5,16 @@
 // neighbour's bilinearly sampled features at each candidate's reprojection,
 // the best candidate and a parabola through its neighbours.
 //
-// Layout: features FP16 channel-last [H][W][C] (a pixel's vector is C / 8
-// 16-byte segments), one lane per pixel over 64 x 4 pixel tiles, so the
-// lanes of a wave read neighbouring segments of the same rows.  A tap's
-// inner product is v_dot2_f32_f16 over half2 pairs (FP16 products are exact
-// in FP32), weighted by the tap's bilinear weight: sum_tap w <f_i, F_tap>
-// equals <f_i, sum_tap w F_tap>.
+// Layout: features FP16 channel-last [H][W][C] (a pixel's vector is S = C / 8
+// 16-byte segments).  S lanes share a pixel, lane s holding segment s, and
+// a workgroup covers 256 / S consecutive pixels of a row, so one load
+// instruction of a wave reads the whole vectors of 64 / S neighbouring
+// taps (contiguous lines) rather than one segment of 64 scattered vectors.
+// A tap's partial inner product is v_dot2_f32_f16 over half2 pairs (FP16
+// products are exact in FP32), weighted by the tap's bilinear weight
+// (sum_tap w <f_i, F_tap> equals <f_i, sum_tap w F_tap>); the S partials
+// are summed across the lanes with xor shuffles, so every lane of a pixel
+// holds the same correlation and takes the same decisions.
 #include "common.h"
 
 namespace gsmi {
@@ -51,22 +55,29 @@ __device__ __forceinline__ void project_nb(const DepthArgs &A, const float a[3],
 
 template <int C>
 __global__ __launch_bounds__(256) void k_guided_depth(DepthArgs A) {
-  constexpr int S = C / 8;  // 16-byte segments per pixel
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (x >= A.W || y >= A.H) return;
-  const int64_t pix = (int64_t)y * A.W + x;
+  constexpr int S = C / 8;    // 16-byte segments per pixel = lanes per pixel
+  constexpr int PX = 256 / S; // pixels per workgroup (one row segment)
+  const int seg = threadIdx.x % S;
+  const int x = blockIdx.x * PX + threadIdx.x / S;
+  const int y = blockIdx.y;
+  // lanes past the row end still take part in the shuffles, on a clamped pixel
+  const bool live = x < A.W;
+  const int xc = live ? x : A.W - 1;
+  const int64_t pix = (int64_t)y * A.W + xc;
+  const bool lead = live && seg == 0;
   const float zm = A.zmono[pix];
   if (!(zm > 0.f && zm < __builtin_inff())) {  // no monocular depth: no estimate
-    if (A.choice) A.choice[pix] = -1;
-    A.depth[pix] = __builtin_nanf("");
-    if (A.best) A.best[pix] = -1;
+    if (lead) {
+      if (A.choice) A.choice[pix] = -1;
+      A.depth[pix] = __builtin_nanf("");
+      if (A.best) A.best[pix] = -1;
+    }
     return;
   }
   const float inv = 1.0f / zm;
   const float lo = fmaxf(inv - A.r_inv, A.d_min), hi = inv + A.r_inv;
   const float step = (hi - lo) / (float)(A.n_cand - 1);
-  const float ray[3] = {((float)x - A.cx) / A.fx, ((float)y - A.cy) / A.fy, 1.0f};
+  const float ray[3] = {((float)xc - A.cx) / A.fx, ((float)y - A.cy) / A.fy, 1.0f};
 
   // the neighbour whose reprojections of the nearest and farthest candidates
   // lie farthest apart, both inside its image (ties: the lower index)
@@ -88,10 +99,12 @@ __global__ __launch_bounds__(256) void k_guided_depth(DepthArgs A) {
       jb = j;
     }
   }
-  if (A.choice) A.choice[pix] = jb;
+  if (lead && A.choice) A.choice[pix] = jb;
   if (jb < 0) {
-    A.depth[pix] = __builtin_nanf("");
-    if (A.best) A.best[pix] = -1;
+    if (lead) {
+      A.depth[pix] = __builtin_nanf("");
+      if (A.best) A.best[pix] = -1;
+    }
     return;
   }
   float a[3], t[3];
@@ -100,15 +113,14 @@ __global__ __launch_bounds__(256) void k_guided_depth(DepthArgs A) {
     a[r] = A.R[jb][3 * r] * ray[0] + A.R[jb][3 * r + 1] * ray[1] + A.R[jb][3 * r + 2];
     t[r] = A.t[jb][r];
   }
-  const uint4 *fj = A.fj[jb];
-  uint4 f[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) f[s] = A.fi[pix * S + s];
+  const uint4 *fj = A.fj[jb] + seg;
+  const uint4 f = A.fi[pix * S + seg];
 
   // streaming argmax (lowest k on ties) with the values beside the best
   const float kNone = -__builtin_inff();
   float cbest = kNone, cleft = kNone, cright = kNone, cprev = kNone;
   int kbest = -1;
+#pragma unroll 2
   for (int k = 0; k < A.n_cand; ++k) {
     const float d = lo + step * (float)k;
     float u, v, z;
@@ -122,19 +134,20 @@ __global__ __launch_bounds__(256) void k_guided_depth(DepthArgs A) {
       const float fx0 = floorf(u), fy0 = floorf(v);
       const float ax = u - fx0, ay = v - fy0;
       const int x0 = (int)fx0, y0 = (int)fy0;
-      c = 0.f;
+      // a tap outside the image reads a clamped pixel with weight 0 (features
+      // are finite), so the four loads issue without branches
+      float part = 0.f;
 #pragma unroll
       for (int tap = 0; tap < 4; ++tap) {
         const int xx = x0 + (tap & 1), yy = y0 + (tap >> 1);
-        const float w = ((tap & 1) ? ax : 1.0f - ax) * ((tap >> 1) ? ay : 1.0f - ay);
-        if (xx >= 0 && xx < A.W && yy >= 0 && yy < A.H) {
-          const uint4 *q = fj + ((int64_t)yy * A.W + xx) * S;
-          float dp = 0.f;
-#pragma unroll
-          for (int s = 0; s < S; ++s) dp = dot8(f[s], q[s], dp);
-          c = __builtin_fmaf(w, dp, c);
-        }
+        const bool in = xx >= 0 && xx < A.W && yy >= 0 && yy < A.H;
+        const float w = in ? ((tap & 1) ? ax : 1.0f - ax) * ((tap >> 1) ? ay : 1.0f - ay) : 0.0f;
+        const int xs = min(max(xx, 0), A.W - 1), ys = min(max(yy, 0), A.H - 1);
+        part = __builtin_fmaf(w, dot8(f, fj[((int64_t)ys * A.W + xs) * S], 0.f), part);
       }
+      c = part;
+#pragma unroll
+      for (int o = 1; o < S; o <<= 1) c += __shfl_xor(c, o, 64);
     }
     if (k == kbest + 1 && kbest >= 0) cright = c;
     if (c > cbest) {
@@ -145,6 +158,7 @@ __global__ __launch_bounds__(256) void k_guided_depth(DepthArgs A) {
     }
     cprev = c;
   }
+  if (!lead) return;
   if (kbest < 0) {  // no candidate in front of the neighbour
     A.depth[pix] = __builtin_nanf("");
     if (A.best) A.best[pix] = -1;
@@ -190,13 +204,16 @@ gs_status gs_guided_depth(int32_t width, int32_t height, int32_t channels, float
     for (int k = 0; k < 3; ++k) A.t[j][k] = j < n_nb ? rel_poses[12 * j + 9 + k] : 0.f;
   }
   A.zmono = zmono; A.depth = depth; A.best = best; A.choice = choice;
-  const dim3 grid((unsigned)((width + 63) / 64), (unsigned)((height + 3) / 4));
   hipStream_t s = (hipStream_t)stream;
+  const auto grid = [&](int c) {  // 256 / (c / 8) pixels of one row per workgroup
+    const int px = 256 / (c / 8);
+    return dim3((unsigned)((width + px - 1) / px), (unsigned)height);
+  };
   switch (channels) {
-    case 8: GS_LAUNCH("guided_depth", k_guided_depth<8>, grid, 256, 0, s, A); break;
-    case 16: GS_LAUNCH("guided_depth", k_guided_depth<16>, grid, 256, 0, s, A); break;
-    case 32: GS_LAUNCH("guided_depth", k_guided_depth<32>, grid, 256, 0, s, A); break;
-    default: GS_LAUNCH("guided_depth", k_guided_depth<64>, grid, 256, 0, s, A); break;
+    case 8: GS_LAUNCH("guided_depth", k_guided_depth<8>, grid(8), 256, 0, s, A); break;
+    case 16: GS_LAUNCH("guided_depth", k_guided_depth<16>, grid(16), 256, 0, s, A); break;
+    case 32: GS_LAUNCH("guided_depth", k_guided_depth<32>, grid(32), 256, 0, s, A); break;
+    default: GS_LAUNCH("guided_depth", k_guided_depth<64>, grid(64), 256, 0, s, A); break;
   }
   return GS_OK;
 }
