@@ -593,7 +593,7 @@ def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms
         gsmi.profile_reset()
         gsmi.profile_select(["downsample"])
         gsmi.profile_enable(True)
-        busy2.copy_(busy)
+        gsmi.probe_copy(busy, busy2)
         for _ in range(20):
             gsmi.downsample(img, lv, out=out)
         torch.cuda.synchronize()
@@ -612,10 +612,10 @@ def measure_multiscale(gsmi, keyframe_step, iters, targets, g, m1, m2, rates, ms
     gsmi.profile_reset()
     gsmi.profile_select(["prune_flags", "scan", "prune_index", "gather_planes"])
     gsmi.profile_enable(True)
-    busy2.copy_(busy)
+    gsmi.probe_copy(busy, busy2)
     keep = gsmi.prune_opacity(g.opacity_logits, 0.005)
     kept = keep.numel()
-    busy2.copy_(busy)
+    gsmi.probe_copy(busy, busy2)
     outs = [gsmi.gather_planes(t, keep, out=o) for t, o in zip(state, outs)]
     torch.cuda.synchronize()
     gsmi.profile_enable(False)

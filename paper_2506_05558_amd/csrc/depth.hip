@@ -58,8 +58,13 @@ __global__ __launch_bounds__(256) void k_guided_depth(DepthArgs A) {
   constexpr int S = C / 8;    // 16-byte segments per pixel = lanes per pixel
   constexpr int PX = 256 / S; // pixels per workgroup (one row segment)
   const int seg = threadIdx.x % S;
-  const int x = blockIdx.x * PX + threadIdx.x / S;
-  const int y = blockIdx.y;
+  // workgroups go round-robin to the 8 XCDs: give each XCD a contiguous band of row
+  // segments, so the neighbour rows that adjacent rows gather stay in one L2
+  const int nx = (A.W + PX - 1) / PX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile >= nx * A.H) return;
+  const int x = (tile % nx) * PX + threadIdx.x / S;
+  const int y = tile / nx;
   // lanes past the row end still take part in the shuffles, on a clamped pixel
   const bool live = x < A.W;
   const int xc = live ? x : A.W - 1;
@@ -205,9 +210,10 @@ gs_status gs_guided_depth(int32_t width, int32_t height, int32_t channels, float
   }
   A.zmono = zmono; A.depth = depth; A.best = best; A.choice = choice;
   hipStream_t s = (hipStream_t)stream;
-  const auto grid = [&](int c) {  // 256 / (c / 8) pixels of one row per workgroup
+  const auto grid = [&](int c) {  // 256 / (c / 8) pixels of one row per workgroup, padded to 8 XCDs
     const int px = 256 / (c / 8);
-    return dim3((unsigned)((width + px - 1) / px), (unsigned)height);
+    const int64_t tiles = (int64_t)((width + px - 1) / px) * height;
+    return dim3((unsigned)((tiles + 7) / 8 * 8));
   };
   switch (channels) {
     case 8: GS_LAUNCH("guided_depth", k_guided_depth<8>, grid(8), 256, 0, s, A); break;
