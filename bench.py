@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--cpu-crops", type=int, default=12)
     ap.add_argument("--no-study", action="store_true", help="skip the steps-to-PSNR study of the spawn MLP")
     ap.add_argument("--study-train-seeds", default="100:140")
+    ap.add_argument("--profile-view", type=int, default=None,
+                    help="only project, bin, render and back-propagate an L1 loss for this window view, three "
+                         "times (a short run for counter passes), then exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with one plain 256 MiB device copy, the reference for HBM byte counters")
     return ap.parse_args()
@@ -90,6 +93,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
+    if args.profile_view is not None:
+        profile_view(gsmi, synth, args.profile_view)
+        return
     t0 = time.time()
     views_all = synth.trajectory(SEED, N_VIEWS + 1, W_IMG, H_IMG)
     views, new_view = views_all[:N_VIEWS], views_all[N_VIEWS]
@@ -477,6 +483,30 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
     print(json.dumps(out))
+
+
+def profile_view(gsmi, synth, index):
+    """Three forward + adjoint passes of one window view with the benchmark's parameters."""
+    import numpy as np
+    import torch
+    views = synth.trajectory(SEED, N_VIEWS + 1, W_IMG, H_IMG)[:N_VIEWS]
+    g = gsmi.Gaussians.from_arrays(synth.window_scene(SEED, views, PER_VIEW, SH_DEG).arrays())
+    v = views[index]
+    pose = torch.tensor(np.concatenate([v.R.reshape(9), v.t]).astype(np.float32), device="cuda")
+    cam = gsmi.Camera(W_IMG, H_IMG, v.fx, v.fy, v.cx, v.cy, pose)
+    params = gsmi.Params(eps2d=0.1, mip_filter=1)
+    sorter = gsmi.BinSorter(12 * PER_VIEW * N_VIEWS)
+    grads = g.zeros_like()
+    target = torch.rand(3, H_IMG, W_IMG, device="cuda", generator=torch.Generator(device="cuda").manual_seed(SEED))
+    g_img = torch.empty_like(target)
+    for it in range(3):
+        proj = gsmi.project(cam, g, params)
+        b = sorter(cam, proj)
+        fr = gsmi.render_fwd(cam, proj, b, params)
+        gsmi.loss_l1(fr.image, target, dL_dimage=g_img)
+        gsmi.render_bwd(cam, g, proj, b, fr, g_img, grads=grads, params=params)
+        torch.cuda.synchronize()
+        print(f"# view {index} pass {it}: {b.n_instances} pairs", file=sys.stderr, flush=True)
 
 
 def measure_depth(gsmi, synth):
