@@ -4,7 +4,10 @@
  * forward and backward (paper section 4.3: 30 such iterations per keyframe,
  * sparse Adam on the Gaussians, poses optimised jointly and receiving
  * gradient through Gaussian position and rotation but not through the
- * spherical harmonics), plus the primitive-spawning step of section 4.2.
+ * spherical harmonics), plus the primitive-spawning step of section 4.2,
+ * the multi-scale training helpers of section 4.3 (screen-space filter,
+ * coarse-to-fine pyramid, per-Gaussian learning rates, opacity culling),
+ * the guided-matching depth of new primitives, and measurement probes.
  *
  * The rasterizer is the EWA splatting model of the 3DGS codebase the paper
  * builds on (section 5): Gaussians with mean, log-scales, rotation
