@@ -7,7 +7,9 @@
  * spherical harmonics), plus the primitive-spawning step of section 4.2,
  * the multi-scale training helpers of section 4.3 (screen-space filter,
  * coarse-to-fine pyramid, per-Gaussian learning rates, opacity culling),
- * the guided-matching depth of new primitives, and measurement probes.
+ * the guided-matching depth of new primitives, the anchor decisions of
+ * section 4.4 (creation trigger, two-anchor blending), and measurement
+ * probes.
  *
  * The rasterizer is the EWA splatting model of the 3DGS codebase the paper
  * builds on (section 5): Gaussians with mean, log-scales, rotation
@@ -531,6 +533,27 @@ gs_status gs_guided_depth(int32_t width, int32_t height, int32_t channels, float
                           const void *feat_i, int32_t n_nb, const void *const *feat_nb, const float *rel_poses,
                           const float *zmono, int32_t n_cand, float r_inv, float *depth, int32_t *best,
                           int32_t *choice, void *stream);
+
+/* ---- anchors (section 4.4) ------------------------------------------------
+ * gs_anchor_sizes: the creation trigger's per-Gaussian test.  A primitive's
+ * size from a camera is S / D, S its scale and D the distance of its mean to
+ * the camera centre C = -R^T t (pose: HOST [12], R row-major then t, the
+ * world -> camera pose of the previous camera); S is read as the largest of
+ * the three axis scales, and the test is f S < tau D in FP64 with f the
+ * focal length in pixels and tau the threshold in pixels (the paper's
+ * tau_min = 1).  flags [n] (optional) receives 1 / 0; count (DEVICE, one
+ * uint64) receives the number of small Gaussians (overwritten, not
+ * accumulated).  An anchor is created when count > 0.4 n.
+ * gs_anchor_blend_weight (host only): the nearer anchor's weight for two
+ * anchors at distances d1 <= d2 with overlap o in (0, 0.5): 1 for
+ * r = d1 / d2 < 1 - o, else 1 - (r - (1 - o)) 0.5 / o (the other anchor
+ * takes 1 - w).
+ * gs_scale_opacity: out[i] = logit(w sigmoid(logits[i])) in FP64, w in
+ * [0, 1] (w = 0 gives -inf: the Gaussian is culled); out may equal logits. */
+gs_status gs_anchor_sizes(const float *means, const float *log_scales, int64_t n, const float *pose, float f,
+                          float tau, int32_t *flags, unsigned long long *count, void *stream);
+gs_status gs_anchor_blend_weight(float d1, float d2, float overlap, float *w);
+gs_status gs_scale_opacity(const float *logits, int64_t n, float w, float *out, void *stream);
 
 /* ---- measurement probes --------------------------------------------------
  * The achievable rates on the device, reported beside the datasheet peaks

@@ -6,10 +6,8 @@
   here as S = the largest of its three axis scales and the size in pixels
   f S / D with f = sqrt(fx fy).  An anchor is created when more than 40 %
   of the active Gaussians are smaller than tau_min = 1 pixel from the
-  previous camera.  The per-Gaussian test is taken in binary32 as
-  f S < tau D, with S = exp(max log-scale) and D = |mu - C| formed in
-  binary64 and rounded once (a pin checks it against the binary64 test
-  away from ties).
+  previous camera.  The per-Gaussian test f S < tau D is taken in binary64
+  with S = exp(max log-scale) and D = |mu - C|.
 * Blending: with the two nearest anchors at distances d1 <= d2 and overlap
   o in (0, 0.5), r = d1 / d2 and the nearer anchor's weight is 1 for
   r < 1 - o and 1 - (r - (1 - o)) 0.5 / o otherwise; the other anchor gets

@@ -124,6 +124,9 @@ _sig = {
                                 _sz, _vp]),
     "gs_guided_depth": (C.c_int, [_i32, _i32, _i32, _f, _f, _f, _f, _vp, _i32, _P(_vp), _P(C.c_float), _vp, _i32, _f,
                                   _vp, _vp, _vp, _vp]),
+    "gs_anchor_sizes": (C.c_int, [_vp, _vp, _i64, _P(C.c_float), _f, _f, _vp, _vp, _vp]),
+    "gs_anchor_blend_weight": (C.c_int, [_f, _f, _f, _P(C.c_float)]),
+    "gs_scale_opacity": (C.c_int, [_vp, _i64, _f, _vp, _vp]),
     "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
     "gs_probe_valu": (C.c_int, [_i32, _i32, _i32, _vp, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
@@ -837,6 +840,34 @@ def guided_depth(feat_i: torch.Tensor, feat_nb, rel_poses, zmono: torch.Tensor, 
                                 poses.ctypes.data_as(_P(C.c_float)), zmono.data_ptr(), n_cand, r_inv,
                                 depth.data_ptr(), _ptr(best), _ptr(choice), _stream()))
     return depth, best, choice
+
+
+# ------------------------------------------------------------------ anchors
+def anchor_sizes(g: Gaussians, pose, f: float, tau: float = 1.0, flags: Optional[torch.Tensor] = None,
+                 count: Optional[torch.Tensor] = None):
+    """Count (device int64 [1]) of the Gaussians smaller than tau pixels
+    from the camera with world->camera pose [12] (host values); flags [n]
+    optional.  An anchor is created when count > 0.4 n."""
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=g.means.device)
+    p = (C.c_float * 12)(*[float(x) for x in np.asarray(pose, np.float32).reshape(12)])
+    _check(_lib.gs_anchor_sizes(g.means.data_ptr(), g.log_scales.data_ptr(), g.n, p, f, tau, _ptr(flags),
+                                count.data_ptr(), _stream()))
+    return count
+
+
+def anchor_blend_weight(d1: float, d2: float, overlap: float = 0.1) -> float:
+    w = C.c_float()
+    _check(_lib.gs_anchor_blend_weight(d1, d2, overlap, C.byref(w)))
+    return w.value
+
+
+def scale_opacity(logits: torch.Tensor, w: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """logit(w sigmoid(logits)): the opacities of an anchor's Gaussians at blend weight w."""
+    if out is None:
+        out = torch.empty_like(logits)
+    _check(_lib.gs_scale_opacity(logits.data_ptr(), logits.numel(), w, out.data_ptr(), _stream()))
+    return out
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor):

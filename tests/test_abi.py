@@ -217,3 +217,17 @@ def test_guided_depth_validation(lib):
     assert call(args(r=0.0)) == 1     # empty range
     assert call(args(fi=8)) == 1      # features not 16-byte aligned
     assert call(args(w=0)) == 1
+
+
+def test_anchor_blend_weight_equals_the_oracle(lib):
+    # host-only: the blending weight of two anchors
+    from oracle import anchors as an
+    from paper_2506_05558_amd import gsmi
+    for d1, d2, o in [(1.0, 3.0, 0.1), (0.95, 1.0, 0.1), (1.0, 1.0, 0.2), (0.7, 1.0, 0.4), (0.0, 2.0, 0.25)]:
+        assert abs(gsmi.anchor_blend_weight(d1, d2, o) - an.blend_weight(d1, d2, o)) < 1e-6
+    w = C.c_float()
+    L = gsmi._lib
+    assert L.gs_anchor_blend_weight(2.0, 1.0, 0.1, C.byref(w)) == 1    # d1 > d2
+    assert L.gs_anchor_blend_weight(1.0, 2.0, 0.5, C.byref(w)) == 1    # overlap not below 0.5
+    assert L.gs_scale_opacity(1, 10, 1.5, 1, None) == 1                # w > 1
+    assert L.gs_anchor_sizes(1, 1, 10, None, 1.0, 1.0, None, 1, None) == 1  # no pose
