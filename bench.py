@@ -370,6 +370,7 @@ def main():
     multiscale = measure_multiscale(gsmi, keyframe_step, args.iters, targets, g, m1, m2, rates, ms_step)
     peaks = measure_peaks(gsmi)
     guided = measure_depth(gsmi, synth)
+    anchor = measure_anchor_trigger(gsmi, g, np.concatenate([views[-1].R.reshape(9), views[-1].t]), views[-1].fx)
     mpix = args.iters * N_VIEWS * W * H / (ms_step * 1e-3) / 1e6
 
     def roof(name, ks=kernels):
@@ -456,6 +457,7 @@ def main():
         "multiscale": multiscale,
         "measured_peaks": peaks,
         "guided_depth": guided,
+        "anchor_trigger": anchor,
     }
     if not args.no_study:
         # second half of the metric: learned vs rule initialisation of spawned primitives
@@ -553,6 +555,36 @@ def measure_depth(gsmi, synth):
             "estimates": round(n_est / (W * H), 4),
             "median_rel_error": round(float(np.median(err)), 5),
             "monocular_median_rel_error": round(float(np.median(np.abs(zm[est] / zt[est] - 1))), 5)}
+
+
+def measure_anchor_trigger(gsmi, g, pose, f):
+    """The anchor-creation test (section 4.4) over the 2M active Gaussians from one camera:
+    24 B read (mean, log-scales) and a 4 B flag written per Gaussian."""
+    import torch
+    flags = torch.empty(g.n, dtype=torch.int32, device=g.means.device)
+    count = gsmi.anchor_sizes(g, pose, f, flags=flags)
+    torch.cuda.synchronize()
+    busy = torch.empty(256 << 20, dtype=torch.float32, device=g.means.device)
+    busy2 = torch.empty_like(busy)
+    gsmi.profile_reset()
+    gsmi.profile_select(["anchor_sizes"])
+    gsmi.profile_enable(True)
+    gsmi.probe_copy(busy, busy2)
+    for _ in range(10):
+        gsmi.anchor_sizes(g, pose, f, flags=flags, count=count)
+    torch.cuda.synchronize()
+    gsmi.profile_enable(False)
+    ms, cnt = gsmi.profile_read("anchor_sizes")  # two launches per call: the count's clear and the test
+    gsmi.profile_select(None)
+    gsmi.profile_reset()
+    ms = ms / 10
+    a = g.n * 28 / (ms * 1e-3) / 1e9
+    small = int(count.item())
+    del busy, busy2
+    torch.cuda.empty_cache()
+    return {"gaussians": g.n, "small": small, "creates_anchor": small > 0.4 * g.n, "ms_per_call": round(ms, 4),
+            "roofline": {"bound": "hbm", "achieved": a, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": a / PEAK_HBM_GBS,
+                         "traffic": None}}
 
 
 def measure_peaks(gsmi):

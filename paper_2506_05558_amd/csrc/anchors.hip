@@ -8,24 +8,29 @@
 namespace gsmi {
 namespace {
 
-// flag[i] = f S_i < tau D_i with S_i = exp(max log-scale), D_i = |mu_i - C|;
-// the block's count goes to *count with one 64-bit integer atomic
-// (integer sums are exact, so the total does not depend on the order)
+// flag[i] = f S_i < tau D_i with S_i = exp(max log-scale), D_i = |mu_i - C|.
+// A grid-stride loop over at most kSizeBlocks workgroups, each adding its
+// count to *count with one 64-bit integer atomic: atomics on one address from
+// the 8 XCDs serialise through the fabric, so their number is kept small
+// (integer sums are exact, so the total does not depend on the order).
+constexpr int kSizeBlocks = 512;
 __global__ __launch_bounds__(256) void k_anchor_sizes(const float *means, const float *log_scales, int64_t n,
                                                       double cx, double cy, double cz, double f, double tau,
                                                       int32_t *flags, unsigned long long *count) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  bool small = false;
-  if (i < n) {
+  unsigned int mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const double dx = (double)means[i] - cx, dy = (double)means[n + i] - cy, dz = (double)means[2 * n + i] - cz;
     const double D = sqrt(dx * dx + dy * dy + dz * dz);
     const float lmax = fmaxf(fmaxf(log_scales[i], log_scales[n + i]), log_scales[2 * n + i]);
-    small = f * exp((double)lmax) < tau * D;
+    const bool small = f * exp((double)lmax) < tau * D;
     if (flags) flags[i] = small ? 1 : 0;
+    mine += small ? 1u : 0u;
   }
-  const uint64_t b = ballot(small);
+  // block sum: wave sums by xor shuffles, then four waves through LDS
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
   __shared__ unsigned int wc[4];
-  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (unsigned int)__popcll(b);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = mine;
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned int c = wc[0] + wc[1] + wc[2] + wc[3];
@@ -64,8 +69,9 @@ gs_status gs_anchor_sizes(const float *means, const float *log_scales, int64_t n
   hipStream_t s = (hipStream_t)stream;
   GS_LAUNCH("anchor_sizes", k_zero_u64, 1, 1, 0, s, count);
   if (n == 0) return GS_OK;
-  GS_LAUNCH("anchor_sizes", k_anchor_sizes, (unsigned)((n + 255) / 256), 256, 0, s, means, log_scales, n, C[0], C[1],
-            C[2], (double)f, (double)tau, flags, count);
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, kSizeBlocks);
+  GS_LAUNCH("anchor_sizes", k_anchor_sizes, blocks, 256, 0, s, means, log_scales, n, C[0], C[1], C[2], (double)f,
+            (double)tau, flags, count);
   return GS_OK;
 }
 
