@@ -473,6 +473,10 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   B.gs[w][2][lane] = G2;
   B.gs[w][3][lane] = GD;
   if (t == 0) sMax = 0;
+  {  // the accumulators start at zero; afterwards each batch's writer clears what it read
+    float4 *z = (float4 *)&sAcc[0][0][0];
+    for (int i = t; i < 4 * NQ * kBwdBatch / 4; i += kThreads) z[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   __syncthreads();
   // the phase 2 lane (sub-block g, half h) sums over the lanes 16 g + 8 h ..
   // 16 g + 8 h + 7 of its wave: their upstream gradients stay in registers
@@ -497,12 +501,11 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const float GAT = GA * Tf;
   const float l2min = __builtin_amdgcn_logf(a.alpha_min);
 
+  // No barrier opens a batch: lane t stages entry t and is also the lane that wrote out
+  // entry t of the previous batch and cleared its accumulator column, so its own program
+  // order covers those; the other lanes' accumulator writes come after the staging
+  // barriers, and the walk of the previous batch ended at the barrier before its write-out.
   for (uint32_t base = s; base < stop; base += kBwdBatch) {
-    __syncthreads();  // every wave is done with the previous batch's stage and accumulators
-    {
-      float4 *z = (float4 *)&sAcc[0][0][0];
-      for (int i = t; i < 4 * NQ * kBwdBatch / 4; i += kThreads) z[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
     stage_batch(a, base, stop, ox, oy, S, nullptr);
     // the length of this lane's sub-block list (the same over its 16 lanes)
     const int cnt = S.cnt[0][blk] + S.cnt[1][blk] + S.cnt[2][blk] + S.cnt[3][blk];
@@ -572,6 +575,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
                            -0.5f * v[3], -v[4]);
       dst[1] = make_float4(-0.5f * v[5], v[0] * exp2_fast(-Bb.y), v[6], v[7]);
       dst[2] = make_float4(v[8], v[9], 0.f, 0.f);
+    }
+    if (t < kBwdBatch) {  // clear column t of the four accumulators for the next batch
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        sAcc[0][q][t] = 0.f;
+        sAcc[1][q][t] = 0.f;
+        sAcc[2][q][t] = 0.f;
+        sAcc[3][q][t] = 0.f;
+      }
     }
   }
   // entries past the last contributor of every pixel receive nothing from this tile
