@@ -238,6 +238,8 @@ gs_status gs_render_fwd_l1(const gs_camera *cam, const gs_raster_params *rp, con
  * clamp, colour clamp, guard band) are held fixed: the clamp's derivative
  * is zero.  Per-tile contributions go to a per-pair buffer in the workspace
  * (no global atomics) and are summed per Gaussian in slot order.
+ * With n_instances == 0 no pixel depends on any Gaussian: the call adds
+ * nothing, and values / slots / first_slot may then be NULL.
  * ws: gs_render_bwd_workspace(n, n_instances) bytes. */
 gs_status gs_render_bwd_workspace(int64_t n, int64_t n_instances, size_t *bytes);
 gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const gs_gaussians *g,

@@ -733,7 +733,11 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
   if ((st = gs_render_bwd_pairs(cam, rp, proj, values, slots, ranges, n_instances, image, depth, final_t,
                                 n_contrib, dL_dimage, dL_ddepth, dL_dalpha, pair_grad, stream)) != GS_OK)
     return st;
-  if (g->n == 0) return GS_OK;
+  // Without a (Gaussian, tile) pair no pixel depends on any Gaussian or on the
+  // pose: every gradient this call would add is zero, and the accumulating
+  // outputs stay as they are.  (The projection adjoint reads a first slot per
+  // Gaussian, which the caller need not provide in that case.)
+  if (g->n == 0 || n_instances == 0) return GS_OK;
   gs_view view;
   view.cam = *cam;
   view.proj = *proj;
@@ -741,9 +745,6 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
   view.first_slot = first_slot;
   view.dL_dpose = dL_dpose;
   view.dL_dtwist = dL_dtwist;
-  static const uint32_t kNoSlot = 0;
-  if (n_instances == 0) view.first_slot = &kNoSlot;  // never read: no Gaussian touches a tile
-  if (n_instances == 0) view.pair_grad = (const float *)&kNoSlot;
   return gs_project_bwd_views(1, &view, rp, g, grads, pose_ws, pose_bytes, stream);
 }
 

@@ -902,7 +902,7 @@ def profile_read(kernel: str):
 # ------------------------------------------------------------------ autograd
 class _Rasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose, cam_static, params, sorter):
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, pose, cam_static, params, sorter, shared):
         g = Gaussians(means.contiguous(), log_scales.contiguous(), quats.contiguous(), opacity_logits.contiguous(),
                       sh.contiguous())
         cam = Camera(cam_static.width, cam_static.height, cam_static.fx, cam_static.fy, cam_static.cx,
@@ -910,6 +910,13 @@ class _Rasterize(torch.autograd.Function):
         proj = project(cam, g, params)
         binned = sorter(cam, proj)
         frame = render_fwd(cam, proj, binned, params)
+        if shared:
+            # the sorter's buffers are reused by its next call (another view of
+            # the same loss may run before this backward): keep this view's own
+            # lists (the first n_instances pairs, the ranges and first slots)
+            M = binned.n_instances
+            binned = Binned(binned.tile_ids[:M].clone(), binned.values[:M].clone(), binned.slots[:M].clone(),
+                            binned.ranges.clone(), binned.first_slot.clone(), M)
         ctx.state = (g, cam, proj, binned, frame, params)
         ctx.mark_non_differentiable(frame.n_contrib)
         return frame.image, frame.depth, frame.alpha
@@ -923,11 +930,13 @@ class _Rasterize(torch.autograd.Function):
         grads = render_bwd(cam, g, proj, binned, frame, g_image, f(g_depth), f(g_alpha), dL_dpose=d_pose,
                            params=params)
         return (grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh,
-                d_pose.to(torch.float32), None, None, None)
+                d_pose.to(torch.float32), None, None, None, None)
 
 
 def rasterize(g: Gaussians, cam: Camera, params: Params = Params(), sorter: Optional[BinSorter] = None):
     """Differentiable render: returns (image (3,H,W), depth (H,W), alpha (H,W)).
-    Gradients flow to every Gaussian plane and to cam.pose (float32 [12])."""
+    Gradients flow to every Gaussian plane and to cam.pose (float32 [12]).
+    A caller's sorter may be shared by several calls before their backward:
+    each call then keeps a copy of its own lists."""
     return _Rasterize.apply(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, cam.pose, cam, params,
-                            sorter or BinSorter())
+                            sorter or BinSorter(), sorter is not None)

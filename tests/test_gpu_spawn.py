@@ -131,6 +131,11 @@ def test_rule_attributes():
     pix = gs.spawn_select(cam, ps, sp)
     n = len(pix)
     assert n > 1000
+    # the expected attributes take P_L and the selected pixels from the oracle
+    # (both are bit-exact there, which the selection tests check on their own)
+    PL_ref, PS_ref = spawn.probability_f32(img, ren)
+    pix_ref = np.flatnonzero(spawn.mask_bernoulli(spawn.quantize(PS_ref), 7))
+    assert np.array_equal(pix.cpu().numpy(), pix_ref)
     for deg in (0, 3):
         off = 17
         nb = (deg + 1) ** 2
@@ -141,7 +146,7 @@ def test_rule_attributes():
         torch.cuda.synchronize()
         R, t = pose[:9].reshape(3, 3).astype(np.float64), pose[9:].astype(np.float64)
         f32 = lambda x: float(np.float32(x))
-        ref = spawn.rule_attributes(pix.cpu().numpy(), pl.cpu().numpy(), img, depth, R, t, f32(cam.fx), f32(cam.fy),
+        ref = spawn.rule_attributes(pix_ref, PL_ref, img, depth, R, t, f32(cam.fx), f32(cam.fy),
                                     f32(cam.cx), f32(cam.cy), opacity=f32(0.1), min_prob=f32(1e-4))
         m = out.means.cpu().numpy().astype(np.float64)
         assert (m[:, :off] == 7.0).all()  # entries before the offset untouched

@@ -104,3 +104,46 @@ def test_pose_6d_vjp_finite_differences():
         fd[idx] = ((optim.pose_from_6d(xp) - optim.pose_from_6d(xm)) * G).sum() / (2 * h)
     assert np.abs(fd - an).max() < 1e-8 * max(1.0, np.abs(an).max())
     assert math.isfinite(an.sum())
+
+
+def test_adam_constant_gradient_every_step_closed_form():
+    # with a constant gradient from zero moments, m_k = (1 - b1^k) g and
+    # v_k = (1 - b2^k) g^2, so the bias-corrected moments are g and g^2 at
+    # every step k and each step moves by lr * sign(g): this pins the bias
+    # correction at steps 2, 3, ..., not only at the first
+    rng = np.random.default_rng(7)
+    n = 9
+    p0 = rng.standard_normal((2, n))
+    g = rng.standard_normal((2, n))
+    s = rng.random(n) + 0.5
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    for k in range(1, 8):
+        p, m, v = optim.adam(p, g, m, v, lr=0.03, step=k, eps=0.0, n_stride=n, lr_scale=s)
+        assert np.allclose(p, p0 - 0.03 * k * s[None, :] * np.sign(g), rtol=0, atol=1e-13)
+        assert np.allclose(m, (1 - 0.9 ** k) * g, rtol=0, atol=1e-15)
+        assert np.allclose(v, (1 - 0.999 ** k) * g * g, rtol=0, atol=1e-15)
+
+
+def test_adam_matches_torch_optim_adam_over_steps():
+    # library routine: torch.optim.Adam (CPU, float64, the same bias-corrected
+    # update p -= lr m_hat / (sqrt(v_hat) + eps)) over seven steps with
+    # changing gradients; the sparse form on a visible set equals it there
+    import torch
+    rng = np.random.default_rng(8)
+    n = 40
+    p0 = rng.standard_normal((3, n))
+    grads = [rng.standard_normal((3, n)) * (1 + k) for k in range(7)]
+    pt = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=0.01, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    vis = np.ones(n, np.int32)
+    for k, gk in enumerate(grads, start=1):
+        opt.zero_grad()
+        pt.grad = torch.tensor(gk)
+        opt.step()
+        p, m, v = optim.adam(p, gk, m, v, lr=0.01, step=k, eps=1e-8, visible=vis, n_stride=n)
+        assert np.allclose(p, pt.detach().numpy(), rtol=0, atol=1e-14)
+    st = opt.state[pt]
+    # torch forms the moments by lerp (m + (1 - b1)(g - m)): equal up to FP64 rounding
+    assert np.allclose(m, st["exp_avg"].numpy(), rtol=1e-12, atol=1e-15)
+    assert np.allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-12, atol=1e-15)

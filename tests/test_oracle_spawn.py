@@ -209,3 +209,72 @@ def test_features_layout():
     assert f[0, 147 + 24] == 0.0 and f[1, 147 + 24] == 0.0  # log(D / D_centre) at the centre
     # corner pixel: replicated border
     assert np.allclose(f[1, :3], img[:, 0, 0])
+
+
+def test_mlp_adam_constant_gradient_and_torch():
+    # the network's Adam: a constant gradient moves every weight by lr sign(g)
+    # per step from zero moments (bias correction at every step; eps = 0),
+    # and changing gradients follow torch.optim.Adam (float64) step by step
+    import torch
+    rng = np.random.default_rng(3)
+    th0 = rng.standard_normal(mlp.n_params())
+    g = rng.standard_normal(th0.size)
+    th, m, v = th0.copy(), np.zeros_like(th0), np.zeros_like(th0)
+    for k in range(1, 6):
+        th, m, v = mlp.adam(th, g, m, v, lr=1e-3, step=k, eps=0.0)
+        assert np.allclose(th, th0 - 1e-3 * k * np.sign(g), rtol=0, atol=1e-13)
+    pt = torch.tensor(th0, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=2e-3, betas=(0.9, 0.999), eps=1e-8)
+    th, m, v = th0.copy(), np.zeros_like(th0), np.zeros_like(th0)
+    for k in range(1, 6):
+        gk = rng.standard_normal(th0.size) * 10 ** (k - 3)
+        opt.zero_grad()
+        pt.grad = torch.tensor(gk)
+        opt.step()
+        th, m, v = mlp.adam(th, gk, m, v, lr=2e-3, step=k)
+        assert np.allclose(th, pt.detach().numpy(), rtol=0, atol=1e-14)
+
+
+def _exact_net(rng):
+    """A network whose every product, sum and activation is exact in
+    bfloat16 and float64: inputs in {0, 1} with input 0 always 1, first-layer
+    weights in {0, 16} with a 16 on input 0, then 0/1 weights with a 1 on the
+    first unit, zero biases.  Every pre-activation is then a multiple of 16 in
+    [16, 4096] (at most 8 significant bits), and GELU(z) = z exactly for
+    z >= 16 (1 - Phi(16) is far below half an ulp of 1)."""
+    X = rng.integers(0, 2, (5, 196)).astype(np.float64)
+    X[:, 0] = 1.0
+    W1 = rng.choice([0.0, 0.0, 16.0], (64, 196))
+    W1[:, 0] = 16.0
+    W2 = (rng.random((64, 64)) < 1.0 / 64).astype(np.float64)
+    W2[:, 0] = 1.0
+    W3 = (rng.random((7, 64)) < 0.05).astype(np.float64)
+    W3[:, 1] = 1.0
+    z = lambda k: np.zeros(k)
+    return (W1, W2, W3), X, lambda W1_: np.concatenate([W1_.ravel(), z(64), W2.ravel(), z(64), W3.ravel(), z(7)])
+
+
+def test_bf16_forward_exact_network_and_rounding_points():
+    # with bfloat16-exact inputs, weights and activations the BF16 forward
+    # equals the float64 definition exactly; a weight of 1 + 2^-9 (halfway
+    # between two bfloat16 values, ties to even -> 1) is rounded before the
+    # product, and a hidden activation that needs more than 8 significant
+    # bits is rounded before the next layer
+    rng = np.random.default_rng(11)
+    (W1, W2, W3), X, pack = _exact_net(rng)
+    Y64, cache = mlp.forward_f64(pack(W1), X)
+    assert (cache[1] >= 16).all()
+    assert np.array_equal(mlp.forward_bf16(pack(W1), X), Y64)
+    Wh = W1.copy()
+    Wh[:, 1] = 1.0 + 2.0 ** -9  # rounds to 1 in bfloat16
+    Wr = W1.copy()
+    Wr[:, 1] = 1.0
+    Xw = X.copy()
+    Xw[:, 1] = 15.0  # z1 = 16 k + 15 w: with w = 1, 31 + 16 (k - 1) needs up to 12 bits
+    Y_exact, _ = mlp.forward_f64(pack(Wh), Xw)
+    Y_round, _ = mlp.forward_f64(pack(Wr), Xw)
+    assert not np.array_equal(Y_exact, Y_round)
+    h1 = mlp.bf16_round(Xw @ Wr.T)  # GELU(z) = z here; then the activation is rounded
+    h2 = mlp.bf16_round(h1 @ W2.T)
+    assert not np.array_equal(h1, Xw @ Wr.T)
+    assert np.array_equal(mlp.forward_bf16(pack(Wh), Xw), h2 @ W3.T)
