@@ -62,6 +62,59 @@ PEAK_VALU_TOPS = 157.3 / 2
 FWD_PAIR, FWD_COMP, BWD_COMP = 11, 8, 66
 
 
+def step_roofline(n, views, pixels, per_view, iters, spawn_k, sh_deg, ms_step):
+    """Whole-step roofline: T_roof = sum over the step's kernels of
+    max(algorithmic bytes / HBM peak, algorithmic lane-ops / VALU peak), with
+    the per-unit figures of the hot path's scope (bytes per Gaussian, per
+    (Gaussian, tile) instance, per pixel; lane-ops per support and per
+    composited pair), and frac = T_roof / T_measured.  per_view: the pair
+    counts of one view (instances, support, composited, visible)."""
+    shf = 3 * (sh_deg + 1) ** 2
+    par = 3 + 3 + 4 + 1 + shf  # floats per Gaussian
+    pb = 4 * par  # parameter bytes per Gaussian (236 at degree 3)
+    M, sup, comp, vis = (per_view[k] for k in ("instances", "support", "composited", "visible"))
+    radix_passes = 6  # 64-bit (tile, depth) keys over 32 + ceil(log2 tiles) bits in 8-bit digits
+    kern = {}
+
+    def add(name, nbytes, ops=0.0, times=1):
+        t = max(nbytes / (PEAK_HBM_GBS * 1e9), ops / (PEAK_VALU_TOPS * 1e12)) * 1e3
+        k = kern.setdefault(name, dict(bytes=0.0, lane_ops=0.0, t_roof_ms=0.0))
+        k["bytes"] += nbytes * times
+        k["lane_ops"] += ops * times
+        k["t_roof_ms"] += t * times
+
+    # the joint iterations
+    add("zero_gradients", 4 * par * n, times=iters)
+    add("project", n * (pb + views * 48), times=iters)
+    add("bin_scan_duplicate", views * (8 * n + 12 * M), times=iters)
+    add("radix_sort", views * radix_passes * 24 * M, times=iters)
+    add("tile_ranges", views * 8 * M, times=iters)
+    # forward: 40 B staged per instance, 24 B written per pixel, the fused L1 loss reads the
+    # target and writes the image gradient (12 + 12 B per pixel)
+    add("render_fwd", 40 * M + 48 * pixels, sup * FWD_PAIR + comp * FWD_COMP, times=iters * views)
+    # adjoint: 40 B per instance, 20 B per pixel in, 40 B of 2D gradients per visible Gaussian out
+    add("render_bwd", 40 * M + 20 * pixels + 40 * vis, comp * BWD_COMP, times=iters * views)
+    add("mark_visible", views * 8 * n, times=iters)
+    # projection adjoint over the window: parameters, per view the 40 B 2D gradients, gradients
+    # read and written once
+    add("project_bwd", n * (pb + views * 40 + 2 * pb), times=iters)
+    add("adam", 28 * par * vis, times=iters)
+    add("lr_decay", 12 * n, times=iters)
+    # the spawn step of the new frame: project + bin + render it, LoG probability on two
+    # images (24 B per pixel each, 8 B out), selection (P_s, flags, prefix), the rule and the
+    # network (196 inputs gathered, 7 outputs, a new 236 B Gaussian) per spawned primitive
+    add("spawn_render", n * (pb + 48) + 8 * n + 12 * M + radix_passes * 24 * M + 8 * M + 40 * M + 24 * pixels)
+    add("spawn_probability_select", 2 * 24 * pixels + 8 * pixels + 16 * pixels)
+    add("spawn_init", spawn_k * (4 * 196 + 4 * 7 + pb))
+    total = sum(k["t_roof_ms"] for k in kern.values())
+    for k in kern.values():
+        k["t_roof_ms"] = round(k["t_roof_ms"], 4)
+    return {"t_roof_ms": round(total, 3), "t_measured_ms": round(ms_step, 3), "frac": round(total / ms_step, 4),
+            "per_kernel": kern,
+            "definition": "sum over the step's kernels of max(algorithmic bytes / 8 TB/s, algorithmic lane-ops / "
+                          "78.6 T lane-op/s), divided by the measured step time"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -450,6 +503,9 @@ def main():
         "kernel_rooflines": others,
         "kernels_ms_per_step": {k: round(v["ms_total"], 4) for k, v in breakdown.items()},
         "ms_per_joint_iteration": round(ms_step / args.iters, 3),
+        "step_roofline": step_roofline(n, N_VIEWS, W * H, {"instances": M, "support": support, "composited": comp,
+                                                             "visible": visible_per_view},
+                                       args.iters, SPAWN_K, SH_DEG, ms_step),
         "pairs_per_view": {"tile_list_to_stop": tile_pairs, "evaluated": evaluated, "support": support,
                            "composited": comp, "tile_list_walked_bwd": walked, "instances": M,
                            "visible_gaussians": visible_per_view},

@@ -222,6 +222,22 @@ gs_status gs_render_fwd_l1(const gs_camera *cam, const gs_raster_params *rp, con
                            float *final_t, int32_t *n_contrib, const float *target, float grad_scale,
                            float *dL_dimage, double *sums, void *ws, size_t ws_bytes, void *stream);
 
+/* gs_render_fwd_l1 without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and outputs as
+ * gs_render_fwd_l1 minus ws / ws_bytes; allocates nothing: the per-tile loss
+ * partials live in a fixed 1 MiB scratch array of the library, one per GPU,
+ * held until the process ends.  Images of more than 65,536 tiles (e.g.
+ * larger than 4096 x 4096) return GS_ERR_INVALID_ARG.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from several host threads) race on it and must be serialised
+ * by the caller.  Every tile writes its partials before they are read, so
+ * nothing carries over from an earlier call. */
+gs_status gs_render_fwd_l1_noalloc(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                                   const uint32_t *values, const uint32_t *ranges, float *image, float *depth,
+                                   float *alpha, float *final_t, int32_t *n_contrib, const float *target,
+                                   float grad_scale, float *dL_dimage, double *sums, void *stream);
+
 /* ---- gs_render_bwd ------------------------------------------------------
  * Adjoint of gs_project + gs_render_fwd for upstream gradients of image
  * [3][H][W], depth [H][W] and alpha [H][W] (dL_ddepth / dL_dalpha may be
@@ -556,6 +572,48 @@ gs_status gs_anchor_sizes(const float *means, const float *log_scales, int64_t n
                           float tau, int32_t *flags, unsigned long long *count, void *stream);
 gs_status gs_anchor_blend_weight(float d1, float d2, float overlap, float *w);
 gs_status gs_scale_opacity(const float *logits, int64_t n, float w, float *out, void *stream);
+
+/* ---- anchor merging (section 4.4, "Clustering and Primitive Merging") ---
+ * When an anchor is created, a random share 1/(k+1) of the primitives that
+ * look too fine (fine[i] != 0, e.g. the flags of gs_anchor_sizes) is
+ * selected and each selected primitive is merged with its k nearest
+ * neighbours among the other too-fine primitives (k = 3 in the paper); all
+ * other primitives are kept, in their order, as the new active set.
+ *
+ * gs_anchor_merge_plan (synchronises the stream twice for counts):
+ *   selection  cls[i] = 1 (selected) iff fine[i] and the top 24 bits of
+ *              SplitMix64(seed + i) < floor(2^24 / (k+1)); 2 for the other
+ *              fine primitives (candidates); 0 otherwise.
+ *   nbr [n][k] for a selected i its k nearest candidates by the binary64
+ *              squared distance (dx dx + dy dy) + dz dz of the binary32
+ *              means, ascending, ties to the lower index (exactly the
+ *              brute-force result), -1 where fewer exist; -1 rows elsewhere.
+ *   owner [n]  for a candidate, the selected primitive it joins -- of those
+ *              that list it, the one with the smallest (binary32 d2, index)
+ *              -- else -1.
+ *   new_index [n]  position in the new active set, -1 for an absorbed
+ *              candidate; keep_index [n]: the first *n_keep entries are the
+ *              ascending indices of the kept primitives.
+ *   k in [1, 8]; ws: gs_anchor_merge_workspace(n) bytes.  Errors:
+ *   GS_ERR_INVALID_ARG for NULL arrays (n > 0), k out of range, n >= 2^31
+ *   or a candidate mean that is not finite.
+ * gs_anchor_merge_apply: writes the new active set into out (out->n =
+ *   *n_keep, same SH degree): the kept primitives gathered, and every
+ *   selected primitive that received a neighbour replaced by the merge of
+ *   its group (FP64): weights w = opacity * s_x s_y s_z, the weighted mean,
+ *   the weighted second moment about it (member covariances plus spreads) as
+ *   the covariance (its eigenvectors -> rotation, half log-eigenvalues ->
+ *   log-scales), SH coefficients averaged with the same weights, opacity
+ *   min(0.99, W / sqrt(det Sigma)).  merged [out->n] (optional) is set to 1
+ *   at the merged entries, 0 elsewhere, so the caller can reset their
+ *   optimiser state (gs_gather_planes with keep_index carries the rest). */
+gs_status gs_anchor_merge_workspace(int64_t n, size_t *bytes);
+gs_status gs_anchor_merge_plan(const gs_gaussians *g, const int32_t *fine, int32_t k, uint64_t seed, int32_t *cls,
+                               int32_t *nbr, int32_t *owner, int32_t *new_index, int32_t *keep_index,
+                               int64_t *n_keep, void *ws, size_t ws_bytes, void *stream);
+gs_status gs_anchor_merge_apply(const gs_gaussians *g, const int32_t *cls, const int32_t *nbr, const int32_t *owner,
+                                const int32_t *new_index, const int32_t *keep_index, int32_t k, gs_gaussians *out,
+                                int32_t *merged, void *stream);
 
 /* ---- measurement probes --------------------------------------------------
  * The achievable rates on the device, reported beside the datasheet peaks

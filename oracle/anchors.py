@@ -93,8 +93,12 @@ def merge_classes(fine, k: int, seed: int):
 def sq_dist(means, i, js):
     """binary64 squared distances from Gaussian i to Gaussians js, in the
     order (dx dx + dy dy) + dz dz with each operation rounded once."""
-    m = np.asarray(means, np.float32).astype(np.float64)
-    d = m[:, js] - m[:, i:i + 1]
+    m = np.asarray(means, np.float32)
+    return _sq_dist64(m[:, js].astype(np.float64), m[:, i:i + 1].astype(np.float64))
+
+
+def _sq_dist64(a, b):
+    d = a - b
     return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
 
 
@@ -103,13 +107,19 @@ def knn(means, cls, k: int):
     (brute force over all candidates, ascending (d2, index)), -1 padded;
     rows of other Gaussians are -1."""
     cls = np.asarray(cls)
+    m64 = np.asarray(means, np.float32).astype(np.float64)
     cand = np.flatnonzero(cls == CLS_CAND)
+    cm = m64[:, cand]
     out = np.full((cls.size, k), -1, np.int32)
     for s in np.flatnonzero(cls == CLS_SEED):
         if cand.size == 0:
             continue
-        d2 = sq_dist(means, s, cand)
-        order = np.lexsort((cand, d2))[:k]
+        d2 = _sq_dist64(cm, m64[:, s:s + 1])
+        if cand.size > k:  # every candidate up to the k-th smallest distance (ties included)
+            sel = np.flatnonzero(d2 <= np.partition(d2, k - 1)[k - 1])
+        else:
+            sel = np.arange(cand.size)
+        order = sel[np.lexsort((cand[sel], d2[sel]))][:k]
         out[s, :order.size] = cand[order]
     return out
 

@@ -17,6 +17,8 @@
 // into block-local positions, adds the row-total prefix to the row scan to
 // get each digit's output base, reorders the block in LDS and writes each
 // digit's keys as one contiguous run -- stable, and with coalesced stores.
+#include <algorithm>
+
 #include "common.h"
 
 namespace gsmi {
@@ -514,6 +516,29 @@ gs_status radix_sort(uint32_t *k[2], uint32_t *v[2], uint32_t *v2[2], const uint
 }
 
 }  // namespace
+
+size_t sort_pairs_workspace(int64_t count) {
+  return 2 * align_up(sizeof(uint32_t) * (size_t)std::max<int64_t>(count, 1)) +
+         align_up(sizeof(uint32_t) * radix_hist_elems(std::max<int64_t>(count, 1))) + align_up(sizeof(uint32_t) * 256);
+}
+
+gs_status sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t count, int key_bits, void *ws, hipStream_t s) {
+  if (count <= 1 || key_bits <= 0) return GS_OK;
+  Carve cv(ws);
+  uint32_t *k_alt = cv.take<uint32_t>((size_t)count), *v_alt = cv.take<uint32_t>((size_t)count);
+  RadixWs rw{cv.take<uint32_t>(radix_hist_elems(count)), cv.take<uint32_t>(256)};
+  int shifts[8], widths[8];
+  const int np = plan_passes(key_bits, shifts, widths);
+  uint32_t *kk[2] = {keys, k_alt}, *vv[2] = {vals, v_alt};
+  int res = 0;
+  gs_status st = radix_sort(kk, vv, nullptr, nullptr, count, np, shifts, widths, rw, s, &res);
+  if (st != GS_OK) return st;
+  if (res == 1) {
+    GS_CHECK_HIP(hipMemcpyAsync(keys, k_alt, sizeof(uint32_t) * count, hipMemcpyDeviceToDevice, s), "sort copy");
+    GS_CHECK_HIP(hipMemcpyAsync(vals, v_alt, sizeof(uint32_t) * count, hipMemcpyDeviceToDevice, s), "sort copy");
+  }
+  return GS_OK;
+}
 
 size_t scan_workspace(int64_t count) {
   const int64_t nparts = (count + kScanTile - 1) / kScanTile;

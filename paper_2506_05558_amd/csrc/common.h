@@ -63,6 +63,20 @@ struct Carve {
   }
 };
 
+// Stable LSD radix sort of (key, value) pairs by the low key_bits bits of
+// the keys, in place (binning.hip); ws: sort_pairs_workspace(count) bytes.
+size_t sort_pairs_workspace(int64_t count);
+gs_status sort_pairs_u32(uint32_t *keys, uint32_t *vals, int64_t count, int key_bits, void *ws, hipStream_t s);
+
+// SplitMix64 (Steele, Lea and Flood 2014): the generator's output for state
+// x, the counter-based stream of the library's random draws.
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // Scan / radix sort building blocks (binning.hip).
 size_t scan_workspace(int64_t count);
 gs_status scan_exclusive(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total, void *ws,

@@ -9,9 +9,27 @@ namespace {
 
 constexpr int kChains = 8;  // independent dependency chains per lane (covers VALU latency)
 
-__global__ __launch_bounds__(256) void k_probe_copy(const float4 *__restrict__ src, float4 *__restrict__ dst,
+// Each lane moves kCopyUnroll 16-byte vectors per turn (a workgroup's turn
+// covers 4 x 4 KiB contiguous), all loads issued before the first store,
+// with non-temporal hints: a stream that no cache can hold.
+constexpr int kCopyUnroll = 4;
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_probe_copy(const v4f *__restrict__ src, v4f *__restrict__ dst,
                                                     int64_t n4) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+  const int64_t stride = (int64_t)gridDim.x * 256 * kCopyUnroll;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * kCopyUnroll + threadIdx.x; base < n4; base += stride) {
+    v4f v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * 256;
+      if (i < n4) v[u] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * 256;
+      if (i < n4) __builtin_nontemporal_store(v[u], dst + i);
+    }
+  }
 }
 
 // iters x kChains FMAs per lane, all v_fma_f32 (packed FP32 is disabled)
@@ -60,9 +78,10 @@ gs_status gs_probe_copy(const void *src, void *dst, size_t bytes, void *stream) 
   if (bytes == 0) return GS_OK;
   GS_REQUIRE(src && dst && src != dst, "gs_probe_copy: bad pointers");
   const int64_t n4 = (int64_t)(bytes / 16);
-  const int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 256 * 64);
-  GS_LAUNCH("probe_copy", k_probe_copy, (unsigned)blocks, 256, 0, (hipStream_t)stream, (const float4 *)src,
-            (float4 *)dst, n4);
+  // 8 workgroups per CU, grid-stride over the rest
+  const int64_t blocks = std::min<int64_t>((n4 + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll), 256 * 8);
+  GS_LAUNCH("probe_copy", k_probe_copy, (unsigned)blocks, 256, 0, (hipStream_t)stream, (const v4f *)src,
+            (v4f *)dst, n4);
   return GS_OK;
 }
 

@@ -22,6 +22,8 @@
 // costs seven vector operations and no v_exp_f32.  The forward and the
 // adjoint stage, cull and evaluate with the same code and explicit operation
 // order, so the adjoint retraces the forward's decisions exactly.
+#include <mutex>
+
 #include "common.h"
 
 namespace gsmi {
@@ -622,6 +624,36 @@ static RenderArgs render_args(const gs_camera *cam, const gs_raster_params *rp, 
 
 static int padded_grid(int ntiles) { return (ntiles + 7) / 8 * 8; }
 
+// ---------------------------------------------- fixed scratch (no allocation)
+// The per-tile loss partials of gs_render_fwd_l1_noalloc live in a
+// file-scope device array: each GPU the library runs on holds its own copy
+// (2 doubles per tile, 1 MiB) until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in symbol):
+// its device address is looked up once per device with hipGetSymbolAddress
+// and kept in g_scratch_ptr.
+constexpr int kNoAllocMaxTiles = 65536;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxTiles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device.
+static gs_status noalloc_scratch(double **out) {
+  int dev = -1;
+  GS_CHECK_HIP(hipGetDevice(&dev), "hipGetDevice");
+  GS_REQUIRE(dev >= 0 && dev < kMaxDevices, "gs_render_fwd_l1_noalloc: device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    GS_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    GS_REQUIRE(ptr != nullptr, "gs_render_fwd_l1_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (double *)g_scratch_ptr[dev];
+  return GS_OK;
+}
+
 }  // namespace gsmi
 
 using namespace gsmi;
@@ -673,6 +705,34 @@ gs_status gs_render_fwd_l1(const gs_camera *cam, const gs_raster_params *rp, con
   GS_LAUNCH("render_fwd", (k_render_fwd<false, true>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
   GS_LAUNCH("loss_final", k_tile_loss_sums, 1, kSumBlock, 0, (hipStream_t)stream, (const double *)ws, a.ntiles,
             sums);
+  return GS_OK;
+}
+
+gs_status gs_render_fwd_l1_noalloc(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
+                                   const uint32_t *values, const uint32_t *ranges, float *image, float *depth,
+                                   float *alpha, float *final_t, int32_t *n_contrib, const float *target,
+                                   float grad_scale, float *dL_dimage, double *sums, void *stream) {
+  gs_status st = validate_camera(cam, "gs_render_fwd_l1_noalloc");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(rp && proj && ranges && image && depth && alpha && final_t && n_contrib && target && dL_dimage && sums,
+             "gs_render_fwd_l1_noalloc: NULL argument");
+  GS_REQUIRE(rp->alpha_max > 0.f && rp->alpha_max < 1.f && rp->t_min > 0.f && rp->t_min < 1.f,
+             "gs_render_fwd_l1_noalloc: raster params out of range");
+  const int64_t ntiles = (int64_t)tiles_x_of(cam->width) * tiles_y_of(cam->height);
+  GS_REQUIRE(ntiles <= kNoAllocMaxTiles, "gs_render_fwd_l1_noalloc: %lld tiles exceed the fixed scratch of %d tiles",
+             (long long)ntiles, kNoAllocMaxTiles);
+  double *partials = nullptr;
+  if ((st = noalloc_scratch(&partials)) != GS_OK) return st;
+  RenderArgs a = render_args(cam, rp, proj, values, ranges);
+  FwdOut o{image, depth, alpha, final_t, n_contrib, nullptr, target, grad_scale, dL_dimage, partials};
+  // launched without the profiling bracket (its events are created on demand)
+  // every tile writes its own two partials: nothing in the scratch needs clearing
+  hipLaunchKernelGGL((k_render_fwd<false, true>), dim3(padded_grid(a.ntiles)), dim3(256), 0, (hipStream_t)stream, a,
+                     o);
+  GS_CHECK_HIP(hipGetLastError(), "render_fwd");
+  hipLaunchKernelGGL(k_tile_loss_sums, dim3(1), dim3(kSumBlock), 0, (hipStream_t)stream, (const double *)partials,
+                     a.ntiles, sums);
+  GS_CHECK_HIP(hipGetLastError(), "loss_final");
   return GS_OK;
 }
 

@@ -125,13 +125,6 @@ __global__ __launch_bounds__(256) void k_spawn_prob(const float *img, const floa
   }
 }
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 __device__ __forceinline__ uint64_t quantize(float ps) { return (uint64_t)floorf(ps * 16777216.0f); }
 
 __global__ void k_select_bernoulli(const float *ps, int64_t np, uint64_t seed, uint32_t *flag) {
@@ -349,10 +342,7 @@ gs_status gs_spawn_select(const gs_camera *cam, const float *p_s, const gs_spawn
     GS_LAUNCH("spawn_select", k_quantize, grid1(np), 256, 0, s, p_s, np, L.q);
     if ((st = scan_exclusive_u64(L.q, L.prefix, np, L.total, L.scan_ws, s)) != GS_OK) return st;
     // systematic offset: top 24 bits of SplitMix64 of the seed (host side, same function)
-    uint64_t z = sp->seed + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
+    const uint64_t z = splitmix64(sp->seed);
     GS_LAUNCH("spawn_select", k_select_fixed, grid1(np), 256, 0, s, L.q, L.prefix, L.total, np, sp->k,
               (uint32_t)(z >> 40), L.flag);
   }

@@ -83,6 +83,8 @@ _sig = {
     "gs_render_fwd_l1_workspace": (C.c_int, [_i32, _i32, _P(_sz)]),
     "gs_render_fwd_l1": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f,
                                    _vp, _vp, _vp, _sz, _vp]),
+    "gs_render_fwd_l1_noalloc": (C.c_int, [_P(_Camera), _P(_Params), _P(_Proj), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           _vp, _f, _vp, _vp, _vp]),
     "gs_render_bwd_workspace": (C.c_int, [_i64, _i64, _P(_sz)]),
     "gs_render_bwd": (C.c_int, [_P(_Camera), _P(_Params), _P(_Gauss), _P(_Proj), _vp, _vp, _vp, _vp, _i64, _vp,
                                 _vp, _vp, _vp, _vp, _vp, _vp, _P(_Gauss), _vp, _vp, _vp, _sz, _vp]),
@@ -127,6 +129,10 @@ _sig = {
     "gs_anchor_sizes": (C.c_int, [_vp, _vp, _i64, _P(C.c_float), _f, _f, _vp, _vp, _vp]),
     "gs_anchor_blend_weight": (C.c_int, [_f, _f, _f, _P(C.c_float)]),
     "gs_scale_opacity": (C.c_int, [_vp, _i64, _f, _vp, _vp]),
+    "gs_anchor_merge_workspace": (C.c_int, [_i64, _P(_sz)]),
+    "gs_anchor_merge_plan": (C.c_int, [_P(_Gauss), _vp, _i32, C.c_uint64, _vp, _vp, _vp, _vp, _vp, _P(_i64), _vp,
+                                       _sz, _vp]),
+    "gs_anchor_merge_apply": (C.c_int, [_P(_Gauss), _vp, _vp, _vp, _vp, _vp, _i32, _P(_Gauss), _vp, _vp]),
     "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
     "gs_probe_valu": (C.c_int, [_i32, _i32, _i32, _vp, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
@@ -419,6 +425,27 @@ def render_fwd_l1(cam: Camera, proj: Projected, binned: Binned, target: torch.Te
                                  out.alpha.data_ptr(), out.final_t.data_ptr(), out.n_contrib.data_ptr(),
                                  target.data_ptr(), grad_scale, dL_dimage.data_ptr(), sums.data_ptr(), ws.data_ptr(),
                                  ws.numel(), _stream()))
+    return out
+
+
+def render_fwd_l1_noalloc(cam: Camera, proj: Projected, binned: Binned, target: torch.Tensor, grad_scale: float,
+                          dL_dimage: torch.Tensor, sums: torch.Tensor, out: Frame, params: Params = Params()) -> Frame:
+    """gs_render_fwd_l1_noalloc: render_fwd_l1 with the library's fixed
+    scratch instead of a workspace; every output buffer is the caller's
+    (out, dL_dimage, sums), so the call allocates nothing."""
+    H, W = cam.height, cam.width
+    _require(target, torch.float32, (3, H, W), "target")
+    _require(dL_dimage, torch.float32, (3, H, W), "dL_dimage")
+    _require(sums, torch.float64, (2,), "sums")
+    _require(out.image, torch.float32, (3, H, W), "image")
+    for t, nm in ((out.depth, "depth"), (out.alpha, "alpha"), (out.final_t, "final_t")):
+        _require(t, torch.float32, (H, W), nm)
+    _require(out.n_contrib, torch.int32, (H, W), "n_contrib")
+    _check(_lib.gs_render_fwd_l1_noalloc(C.byref(cam.c()), C.byref(params.c()), C.byref(proj.c()),
+                                         binned.values.data_ptr(), binned.ranges.data_ptr(), out.image.data_ptr(),
+                                         out.depth.data_ptr(), out.alpha.data_ptr(), out.final_t.data_ptr(),
+                                         out.n_contrib.data_ptr(), target.data_ptr(), grad_scale,
+                                         dL_dimage.data_ptr(), sums.data_ptr(), _stream()))
     return out
 
 
@@ -868,6 +895,53 @@ def scale_opacity(logits: torch.Tensor, w: float, out: Optional[torch.Tensor] = 
         out = torch.empty_like(logits)
     _check(_lib.gs_scale_opacity(logits.data_ptr(), logits.numel(), w, out.data_ptr(), _stream()))
     return out
+
+
+@dataclass
+class MergePlan:
+    cls: torch.Tensor  # (n,) int32: 0 other, 1 selected, 2 candidate
+    nbr: torch.Tensor  # (n, k) int32
+    owner: torch.Tensor  # (n,) int32
+    new_index: torch.Tensor  # (n,) int32
+    keep_index: torch.Tensor  # (n_keep,) int32 view
+    k: int
+
+
+def anchor_merge_plan(g: Gaussians, fine: torch.Tensor, k: int = 3, seed: int = 0,
+                      ws: Optional[torch.Tensor] = None) -> MergePlan:
+    """gs_anchor_merge_plan: which too-fine primitives merge with which
+    (synchronises for the counts)."""
+    n = g.n
+    dev = g.means.device
+    _require(fine, torch.int32, (n,), "fine")
+    need = C.c_size_t()
+    _check(_lib.gs_anchor_merge_workspace(n, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=dev)
+    i32 = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
+    cls, nbr, owner, new_index, keep = i32(n), i32(n, k), i32(n), i32(n), i32(max(n, 1))
+    n_keep = C.c_int64()
+    _check(_lib.gs_anchor_merge_plan(C.byref(g.c()), fine.data_ptr(), k, seed & ((1 << 64) - 1), cls.data_ptr(),
+                                     nbr.data_ptr(), owner.data_ptr(), new_index.data_ptr(), keep.data_ptr(),
+                                     C.byref(n_keep), ws.data_ptr(), ws.numel(), _stream()))
+    return MergePlan(cls, nbr, owner, new_index, keep[:n_keep.value], k)
+
+
+def anchor_merge_apply(g: Gaussians, plan: MergePlan, out: Optional[Gaussians] = None,
+                       merged: Optional[torch.Tensor] = None):
+    """gs_anchor_merge_apply: the new active set (n_keep Gaussians) and the
+    int32 flags of its merged entries."""
+    m = plan.keep_index.numel()
+    dev = g.means.device
+    if out is None:
+        z = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+        out = Gaussians(z(3, m), z(3, m), z(4, m), z(m), z(g.sh.shape[0], 3, m))
+    if merged is None:
+        merged = torch.empty(m, dtype=torch.int32, device=dev)
+    _check(_lib.gs_anchor_merge_apply(C.byref(g.c()), plan.cls.data_ptr(), plan.nbr.data_ptr(),
+                                      plan.owner.data_ptr(), plan.new_index.data_ptr(), plan.keep_index.data_ptr(),
+                                      plan.k, C.byref(out.c()), merged.data_ptr(), _stream()))
+    return out, merged
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor):
