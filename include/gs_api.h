@@ -615,6 +615,25 @@ gs_status gs_anchor_merge_apply(const gs_gaussians *g, const int32_t *cls, const
                                 const int32_t *new_index, const int32_t *keep_index, int32_t k, gs_gaussians *out,
                                 int32_t *merged, void *stream);
 
+/* planes [n_planes][n]: planes[p][i] = value wherever mask[i] != 0 (e.g. the
+ * Adam moments of the merged entries of gs_anchor_merge_apply, reset to 0). */
+gs_status gs_masked_fill(float *planes, int64_t n, int32_t n_planes, const int32_t *mask, float value,
+                         void *stream);
+
+/* ---- anchor storage (section 4.4) ----------------------------------------
+ * An anchor stores the active Gaussians, their optimisation state and the
+ * keyframes they were optimised with in CPU RAM, off the GPU.
+ * gs_anchor_offload copies n_planes DEVICE arrays (src[p], bytes[p] bytes)
+ * into one HOST block, each at a 256-byte aligned offset
+ * (gs_anchor_host_bytes gives the block size); gs_anchor_reload copies them
+ * back into dst[p].  Both are asynchronous on `stream` (a side stream keeps
+ * them beside the optimisation); for the copies to be asynchronous the host
+ * block must be pinned (page-locked) memory the caller allocated.  The host
+ * block must not be read or freed before the stream has passed the call. */
+size_t gs_anchor_host_bytes(int32_t n_planes, const size_t *bytes);
+gs_status gs_anchor_offload(int32_t n_planes, const void *const *src, const size_t *bytes, void *host, void *stream);
+gs_status gs_anchor_reload(int32_t n_planes, void *const *dst, const size_t *bytes, const void *host, void *stream);
+
 /* ---- measurement probes --------------------------------------------------
  * The achievable rates on the device, reported beside the datasheet peaks
  * that the roofline fractions use.

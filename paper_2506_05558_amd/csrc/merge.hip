@@ -400,6 +400,12 @@ __global__ __launch_bounds__(128) void k_merge_apply(MergeArgs a) {
   if (a.merged) a.merged[p] = 1;
 }
 
+// planes[p][i] = value where mask[i] != 0 (plane p = blockIdx.y)
+__global__ void k_masked_fill(float *planes, int64_t n, const int32_t *mask, float value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && mask[i]) planes[(int64_t)blockIdx.y * n + i] = value;
+}
+
 template <class T>
 __global__ void k_fill_t(T *p, int64_t count, T v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -523,6 +529,50 @@ gs_status gs_anchor_merge_plan(const gs_gaussians *g, const int32_t *fine, int32
   GS_CHECK_HIP(hipStreamSynchronize(s), "merge keep count");
   *n_keep = kept;
   return GS_OK;
+}
+
+gs_status gs_masked_fill(float *planes, int64_t n, int32_t n_planes, const int32_t *mask, float value,
+                         void *stream) {
+  GS_REQUIRE(n >= 0 && n_planes >= 0, "gs_masked_fill: bad sizes");
+  if (n == 0 || n_planes == 0) return GS_OK;
+  GS_REQUIRE(planes && mask, "gs_masked_fill: NULL argument");
+  GS_LAUNCH("masked_fill", k_masked_fill, dim3(grid_of(n), (unsigned)n_planes), 256, 0, (hipStream_t)stream, planes,
+            n, mask, value);
+  return GS_OK;
+}
+
+gs_status gs_anchor_offload(int32_t n_planes, const void *const *src, const size_t *bytes, void *host, void *stream) {
+  GS_REQUIRE(n_planes >= 0 && (n_planes == 0 || (src && bytes && host)), "gs_anchor_offload: bad argument");
+  size_t off = 0;
+  for (int32_t p = 0; p < n_planes; ++p) {
+    if (bytes[p]) {
+      GS_REQUIRE(src[p], "gs_anchor_offload: plane %d is NULL", p);
+      GS_CHECK_HIP(hipMemcpyAsync((char *)host + off, src[p], bytes[p], hipMemcpyDeviceToHost, (hipStream_t)stream),
+                   "gs_anchor_offload copy");
+    }
+    off += align_up(bytes[p]);
+  }
+  return GS_OK;
+}
+
+gs_status gs_anchor_reload(int32_t n_planes, void *const *dst, const size_t *bytes, const void *host, void *stream) {
+  GS_REQUIRE(n_planes >= 0 && (n_planes == 0 || (dst && bytes && host)), "gs_anchor_reload: bad argument");
+  size_t off = 0;
+  for (int32_t p = 0; p < n_planes; ++p) {
+    if (bytes[p]) {
+      GS_REQUIRE(dst[p], "gs_anchor_reload: plane %d is NULL", p);
+      GS_CHECK_HIP(hipMemcpyAsync(dst[p], (const char *)host + off, bytes[p], hipMemcpyHostToDevice, (hipStream_t)stream),
+                   "gs_anchor_reload copy");
+    }
+    off += align_up(bytes[p]);
+  }
+  return GS_OK;
+}
+
+size_t gs_anchor_host_bytes(int32_t n_planes, const size_t *bytes) {
+  size_t off = 0;
+  for (int32_t p = 0; bytes && p < n_planes; ++p) off += align_up(bytes[p]);
+  return off;
 }
 
 gs_status gs_anchor_merge_apply(const gs_gaussians *g, const int32_t *cls, const int32_t *nbr, const int32_t *owner,

@@ -133,6 +133,10 @@ _sig = {
     "gs_anchor_merge_plan": (C.c_int, [_P(_Gauss), _vp, _i32, C.c_uint64, _vp, _vp, _vp, _vp, _vp, _P(_i64), _vp,
                                        _sz, _vp]),
     "gs_anchor_merge_apply": (C.c_int, [_P(_Gauss), _vp, _vp, _vp, _vp, _vp, _i32, _P(_Gauss), _vp, _vp]),
+    "gs_masked_fill": (C.c_int, [_vp, _i64, _i32, _vp, _f, _vp]),
+    "gs_anchor_host_bytes": (C.c_size_t, [_i32, _P(_sz)]),
+    "gs_anchor_offload": (C.c_int, [_i32, _P(_vp), _P(_sz), _vp, _vp]),
+    "gs_anchor_reload": (C.c_int, [_i32, _P(_vp), _P(_sz), _vp, _vp]),
     "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
     "gs_probe_valu": (C.c_int, [_i32, _i32, _i32, _vp, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
@@ -942,6 +946,50 @@ def anchor_merge_apply(g: Gaussians, plan: MergePlan, out: Optional[Gaussians] =
                                       plan.owner.data_ptr(), plan.new_index.data_ptr(), plan.keep_index.data_ptr(),
                                       plan.k, C.byref(out.c()), merged.data_ptr(), _stream()))
     return out, merged
+
+
+def masked_fill(planes: torch.Tensor, mask: torch.Tensor, value: float = 0.0):
+    """planes [..., n] float32: planes[..., i] = value where mask[i] != 0."""
+    n = mask.numel()
+    _require(mask, torch.int32, (n,), "mask")
+    if planes.shape[-1] != n or not planes.is_contiguous() or planes.dtype != torch.float32:
+        raise ValueError("planes: contiguous float32 [..., n]")
+    _check(_lib.gs_masked_fill(planes.data_ptr(), n, planes.numel() // max(n, 1), mask.data_ptr(), value, _stream()))
+
+
+def _plane_lists(tensors):
+    k = len(tensors)
+    ptrs = (_vp * max(k, 1))(*[t.data_ptr() for t in tensors])
+    sizes = (_sz * max(k, 1))(*[t.numel() * t.element_size() for t in tensors])
+    return k, ptrs, sizes
+
+
+def anchor_host_bytes(tensors) -> int:
+    k, _, sizes = _plane_lists(tensors)
+    return int(_lib.gs_anchor_host_bytes(k, sizes))
+
+
+def anchor_offload(tensors, host: torch.Tensor):
+    """gs_anchor_offload: the device tensors into one pinned uint8 host block
+    (asynchronous on the current stream)."""
+    for t in tensors:
+        if not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("anchor_offload: contiguous device tensors only")
+    if host.device.type != "cpu" or host.dtype != torch.uint8 or host.numel() < anchor_host_bytes(tensors):
+        raise ValueError("anchor_offload: host block too small or not a uint8 CPU tensor")
+    k, ptrs, sizes = _plane_lists(tensors)
+    _check(_lib.gs_anchor_offload(k, ptrs, sizes, host.data_ptr(), _stream()))
+
+
+def anchor_reload(tensors, host: torch.Tensor):
+    """gs_anchor_reload: the host block back into the device tensors."""
+    for t in tensors:
+        if not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("anchor_reload: contiguous device tensors only")
+    if host.device.type != "cpu" or host.dtype != torch.uint8 or host.numel() < anchor_host_bytes(tensors):
+        raise ValueError("anchor_reload: host block too small or not a uint8 CPU tensor")
+    k, ptrs, sizes = _plane_lists(tensors)
+    _check(_lib.gs_anchor_reload(k, ptrs, sizes, host.data_ptr(), _stream()))
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor):
