@@ -634,6 +634,53 @@ size_t gs_anchor_host_bytes(int32_t n_planes, const size_t *bytes);
 gs_status gs_anchor_offload(int32_t n_planes, const void *const *src, const size_t *bytes, void *host, void *stream);
 gs_status gs_anchor_reload(int32_t n_planes, void *const *dst, const size_t *bytes, const void *host, void *stream);
 
+/* ---- mini bundle adjustment (section 4.1, appendix "Initial Pose
+ * Estimation") ------------------------------------------------------------
+ * Levenberg-Marquardt as the appendix states it: damping lambda from 1e-5,
+ * divided by 2 after a step that lowers the cost (the step is kept),
+ * multiplied by 2 otherwise (the step is dropped); damped normal equations
+ * (J^T W J + lambda diag(J^T W J)) delta = -J^T W r (a variable none of whose
+ * observations is kept holds still).  Robustness: the Huber loss of each
+ * observation's reprojection error e (threshold huber_delta pixels) and the
+ * rejection of the observations with e > median + 4 MAD of the errors at
+ * the iterate.  Poses are world->camera [R | t] (row-major R, then t) in
+ * FP64, updated by left perturbations exp(xi^) T; the pinhole model is the
+ * rasterizer's.  Each call is a fixed-size problem that runs whole on the
+ * device (one launch per stage, all iterations inside).
+ *
+ * gs_pose_ransac: the pose of a new frame from K 3D-2D correspondences
+ *   (X [3][K] world points, uv [2][K] pixels, DEVICE float32; K <= 8192):
+ *   n_hyp hypotheses, each from the previous pose pose0 (HOST double[12])
+ *   run hyp_iters plain LM iterations on `sample` correspondences drawn by
+ *   the counter-based SplitMix64 stream (draw c of hypothesis h:
+ *   splitmix64(seed + h 2^32 + c) mod K, repeats skipped) and count the
+ *   correspondences in front of the camera with error < tau; the hypothesis
+ *   with most inliers (the first on ties) is refined by refine_iters robust
+ *   LM iterations on its inliers.  Out (DEVICE): inliers [K] (1 / 0 at the
+ *   winner, before refinement), n_inliers [1], pose_out double[12],
+ *   pose_out32 float[12], hyp_count [n_hyp] (optional).  ws:
+ *   gs_pose_ransac_workspace(n_hyp) bytes.
+ * gs_ba_bootstrap: focal length (fx = fy, principal point at the image
+ *   centre), the poses of views 1..V-1 (view 0 is the identity) and P points
+ *   seen in every view, from f = 0.7 width, identity poses and points at depth
+ *   1 along view 0's rays: uv [V][2][P] DEVICE float32 (2 <= V <= 8, V P <=
+ *   8192).  The points are eliminated per point (3 x 3 blocks) and the
+ *   reduced camera system is solved by Cholesky.  The rejection applies from
+ *   iteration mad_from on (< 0: iters / 2; the Huber loss throughout).  Out
+ *   (DEVICE, FP64): f_out [1], pose_out [V][12], X_out [3][P], trace
+ *   [iters][3] (cost, candidate cost, lambda per iteration; optional).  ws:
+ *   gs_ba_bootstrap_workspace(V, P) bytes. */
+gs_status gs_pose_ransac_workspace(int32_t n_hyp, size_t *bytes);
+gs_status gs_pose_ransac(const float *X, const float *uv, int64_t K, float fx, float fy, float cx, float cy,
+                         const double *pose0, int32_t n_hyp, int32_t sample, int32_t hyp_iters, float tau,
+                         int32_t refine_iters, float huber_delta, uint64_t seed, int32_t *inliers, int32_t *n_inliers,
+                         double *pose_out, float *pose_out32, int32_t *hyp_count, void *ws, size_t ws_bytes,
+                         void *stream);
+gs_status gs_ba_bootstrap_workspace(int32_t n_views, int32_t n_points, size_t *bytes);
+gs_status gs_ba_bootstrap(const float *uv, int32_t n_views, int32_t n_points, int32_t width, int32_t height,
+                          int32_t iters, int32_t mad_from, float huber_delta, double *f_out, double *pose_out,
+                          double *X_out, double *trace, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- measurement probes --------------------------------------------------
  * The achievable rates on the device, reported beside the datasheet peaks
  * that the roofline fractions use.

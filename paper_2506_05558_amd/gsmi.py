@@ -134,6 +134,11 @@ _sig = {
                                        _sz, _vp]),
     "gs_anchor_merge_apply": (C.c_int, [_P(_Gauss), _vp, _vp, _vp, _vp, _vp, _i32, _P(_Gauss), _vp, _vp]),
     "gs_masked_fill": (C.c_int, [_vp, _i64, _i32, _vp, _f, _vp]),
+    "gs_pose_ransac_workspace": (C.c_int, [_i32, _P(_sz)]),
+    "gs_pose_ransac": (C.c_int, [_vp, _vp, _i64, _f, _f, _f, _f, _P(C.c_double), _i32, _i32, _i32, _f, _i32, _f,
+                                 C.c_uint64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "gs_ba_bootstrap_workspace": (C.c_int, [_i32, _i32, _P(_sz)]),
+    "gs_ba_bootstrap": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _f, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "gs_anchor_host_bytes": (C.c_size_t, [_i32, _P(_sz)]),
     "gs_anchor_offload": (C.c_int, [_i32, _P(_vp), _P(_sz), _vp, _vp]),
     "gs_anchor_reload": (C.c_int, [_i32, _P(_vp), _P(_sz), _vp, _vp]),
@@ -990,6 +995,52 @@ def anchor_reload(tensors, host: torch.Tensor):
         raise ValueError("anchor_reload: host block too small or not a uint8 CPU tensor")
     k, ptrs, sizes = _plane_lists(tensors)
     _check(_lib.gs_anchor_reload(k, ptrs, sizes, host.data_ptr(), _stream()))
+
+
+# ------------------------------------------------------ mini bundle adjustment
+def pose_ransac(X: torch.Tensor, uv: torch.Tensor, fx: float, fy: float, cx: float, cy: float, pose0,
+                n_hyp: int = 128, sample: int = 6, hyp_iters: int = 10, tau: float = 2.0, refine_iters: int = 20,
+                huber_delta: float = 1.0, seed: int = 0, ws: Optional[torch.Tensor] = None):
+    """gs_pose_ransac: (pose float64 [12], pose float32 [12], inliers int32 [K],
+    n_inliers int32 [1], hypothesis counts int32 [n_hyp]) on the device."""
+    K = X.shape[1]
+    _require(X, torch.float32, (3, K), "X")
+    _require(uv, torch.float32, (2, K), "uv")
+    dev = X.device
+    need = C.c_size_t()
+    _check(_lib.gs_pose_ransac_workspace(n_hyp, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    p0 = (C.c_double * 12)(*[float(x) for x in np.asarray(pose0, np.float64).reshape(12)])
+    pose = torch.empty(12, dtype=torch.float64, device=dev)
+    pose32 = torch.empty(12, dtype=torch.float32, device=dev)
+    inl = torch.empty(K, dtype=torch.int32, device=dev)
+    n_inl = torch.empty(1, dtype=torch.int32, device=dev)
+    counts = torch.empty(n_hyp, dtype=torch.int32, device=dev)
+    _check(_lib.gs_pose_ransac(X.data_ptr(), uv.data_ptr(), K, fx, fy, cx, cy, p0, n_hyp, sample, hyp_iters, tau,
+                               refine_iters, huber_delta, seed & ((1 << 64) - 1), inl.data_ptr(), n_inl.data_ptr(),
+                               pose.data_ptr(), pose32.data_ptr(), counts.data_ptr(), ws.data_ptr(), ws.numel(),
+                               _stream()))
+    return pose, pose32, inl, n_inl, counts
+
+
+def ba_bootstrap(uv: torch.Tensor, width: int, height: int, iters: int = 200, mad_from: int = -1,
+                 huber_delta: float = 1.0, trace: bool = False, ws: Optional[torch.Tensor] = None):
+    """gs_ba_bootstrap on uv [V][2][P]: (f [1], poses [V][12], X [3][P],
+    trace [iters][3] or None), float64 on the device."""
+    V, _, P = uv.shape
+    _require(uv, torch.float32, (V, 2, P), "uv")
+    dev = uv.device
+    need = C.c_size_t()
+    _check(_lib.gs_ba_bootstrap_workspace(V, P, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    d = lambda *s: torch.empty(s, dtype=torch.float64, device=dev)
+    f, poses, X = d(1), d(V, 12), d(3, P)
+    tr = d(max(iters, 1), 3) if trace else None
+    _check(_lib.gs_ba_bootstrap(uv.data_ptr(), V, P, width, height, iters, mad_from, huber_delta, f.data_ptr(),
+                                poses.data_ptr(), X.data_ptr(), _ptr(tr), ws.data_ptr(), ws.numel(), _stream()))
+    return f, poses, X, tr
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor):
