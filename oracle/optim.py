@@ -27,6 +27,14 @@ def psnr(mse):
     return 10.0 * np.log10(1.0 / mse)
 
 
+def psnr_images(image, target, peak=1.0):
+    """(PSNR in dB, MSE) of an image against its target: 10 log10(peak^2 /
+    MSE), +inf for equal images (the novel-view metric of section 5)."""
+    d = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    mse = (d * d).sum() / d.size
+    return (10.0 * np.log10(peak * peak / mse) if mse > 0 else np.inf), mse
+
+
 def adam(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=None, lr_scale=None):
     """One Adam step; lr_scale [n_stride] multiplies the rate of element e
     by lr_scale[e % n_stride] (the per-Gaussian rate)."""

@@ -22,6 +22,14 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// Finite checks (checks.hip): on when GS_CHECK_FINITE is set to anything but
+// "0"; each returns GS_ERR_NONFINITE (with the count in gs_last_error) if
+// the array holds a NaN or an infinity, and synchronises the stream.
+bool finite_checks_on();
+gs_status check_finite(const float *x, int64_t count, const char *fn, const char *what, hipStream_t s);
+gs_status check_finite_d(const double *x, int64_t count, const char *fn, const char *what, hipStream_t s);
+gs_status check_finite_gaussians(const gs_gaussians *g, const char *fn, const char *what, hipStream_t s);
+
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Launch helper that checks the launch and returns a status.

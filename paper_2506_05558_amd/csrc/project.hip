@@ -261,7 +261,10 @@ __device__ __forceinline__ void project_one(const MultiArgs &m, const ViewArgs &
   Geo<double> f;
   float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0, r3 = r0;
   int rx = 0, ry = 0, tiles = 0;
-  bool ok = geometry<double, DEG>(m, v, P, f);
+  // a projection that is not finite (NaN or infinite parameters, or an
+  // inverse 2D covariance that overflows) is culled
+  bool ok = geometry<double, DEG>(m, v, P, f) && isfinite(f.p[0]) && isfinite(f.p[1]) && isfinite(f.p[2]) &&
+            isfinite(f.a) && isfinite(f.b) && isfinite(f.c) && isfinite(f.A) && isfinite(f.B) && isfinite(f.C);
   double mx = 0, my = 0, o = 0;
   if (ok) {
     mx = (double)v.fx * f.p[0] * f.iz + (double)v.cx;
@@ -274,7 +277,7 @@ __device__ __forceinline__ void project_one(const MultiArgs &m, const ViewArgs &
       double det0, det;
       o *= mip_rho<double>(f, (double)m.eps2d, det0, det);
     }
-    ok = o >= (double)m.alpha_min;
+    ok = o >= (double)m.alpha_min;  // false for a NaN opacity
   }
   if (ok) {
     // support: o exp(-q/2) >= alpha_min  <=>  q = d^T Sigma2^-1 d <= qmax;
@@ -819,6 +822,10 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
   GS_REQUIRE(out, "gs_project: output struct is NULL");
   if (g->n == 0) return GS_OK;
   GS_REQUIRE(out->rec && out->radius && out->tiles_touched, "gs_project: NULL output plane");
+  if (finite_checks_on()) {
+    if ((st = check_finite(cam->pose, 12, "gs_project", "pose", (hipStream_t)stream)) != GS_OK) return st;
+    if ((st = check_finite_gaussians(g, "gs_project", "gaussians", (hipStream_t)stream)) != GS_OK) return st;
+  }
   MultiArgs m = multi_args(rp, g);
   m.nv = 1;
   m.v[0] = view_args(cam, out);
@@ -838,6 +845,12 @@ gs_status gs_project_views(int32_t n_views, const gs_view *views, const gs_raste
                  "gs_project_views: view %d has a NULL output plane", v);
   }
   if (g->n == 0) return GS_OK;
+  if (finite_checks_on()) {
+    for (int v = 0; v < n_views; ++v)
+      if ((st = check_finite(views[v].cam.pose, 12, "gs_project_views", "pose", (hipStream_t)stream)) != GS_OK)
+        return st;
+    if ((st = check_finite_gaussians(g, "gs_project_views", "gaussians", (hipStream_t)stream)) != GS_OK) return st;
+  }
   for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
     MultiArgs m = multi_args(rp, g);
     m.nv = std::min(kMaxViews, n_views - v0);

@@ -17,6 +17,23 @@ def test_l1_known_values():
     assert abs(optim.psnr(0.01) - 20.0) < 1e-12
 
 
+def test_psnr_images_closed_forms():
+    rng = np.random.default_rng(7)
+    tgt = rng.random((3, 17, 23))
+    # a constant offset c gives MSE = c^2 and PSNR = 20 log10(peak / |c|)
+    for c, peak in ((0.1, 1.0), (-0.25, 1.0), (3.0, 255.0)):
+        p, mse = optim.psnr_images(tgt + c, tgt, peak)
+        assert abs(mse - c * c) <= 1e-12 * c * c
+        assert abs(p - 20.0 * math.log10(peak / abs(c))) <= 1e-9
+    # half the values off by 0.2, half exact: MSE = 0.02, PSNR = 10 log10(50)
+    img = tgt.copy().ravel()
+    img[::2] += 0.2
+    p, mse = optim.psnr_images(img.reshape(tgt.shape), tgt)
+    half = (tgt.size + 1) // 2
+    assert abs(mse - 0.04 * half / tgt.size) <= 1e-15
+    assert optim.psnr_images(tgt, tgt)[0] == np.inf
+
+
 def test_adam_first_step_closed_form():
     rng = np.random.default_rng(0)
     p = rng.standard_normal(50)
