@@ -31,6 +31,20 @@
  *     GS_ERR_INVALID_ARG.  A failed HIP call returns GS_ERR_HIP.
  *     gs_last_error() returns a thread-local text for the last non-OK status.
  *     No C++ exception crosses the ABI.
+ *   * Non-finite values.  A Gaussian whose projection is not finite (a NaN
+ *     or infinite mean, scale, rotation or opacity, or a 2D covariance
+ *     whose inverse overflows) is culled by the projection: it touches no
+ *     tile, composites nothing and receives zero gradient.  A NaN or
+ *     infinite SH coefficient of a visible Gaussian is not detected in
+ *     normal operation and reaches the image.  With GS_CHECK_FINITE set
+ *     (to anything but "0") in the environment, gs_project(_views) count
+ *     the non-finite values of the Gaussians and poses, gs_render_fwd(_l1)
+ *     those of the image and depth they write, and gs_render_bwd those of
+ *     the upstream gradients and of the gradients it accumulates; any
+ *     count above 0 returns GS_ERR_NONFINITE (gs_last_error names the
+ *     array and the count).  The checks synchronise the stream, share one
+ *     8-byte device counter per GPU held by the library, and are
+ *     serialised by a host lock.
  *   * Gradients accumulate (+=) into caller buffers, so several views can
  *     be summed; the caller zeroes them.
  *   * Camera.  World->camera pose [R | t] with R row-major; the camera looks
@@ -54,7 +68,9 @@ typedef enum {
   GS_ERR_INVALID_ARG = 1, /* bad pointer, size, degree, ...; nothing launched */
   GS_ERR_CAPACITY = 2,    /* an output is too small; the required size is returned */
   GS_ERR_HIP = 3,         /* a HIP runtime call failed */
-  GS_ERR_WORKSPACE = 4    /* the workspace is smaller than the query returned */
+  GS_ERR_WORKSPACE = 4,   /* the workspace is smaller than the query returned */
+  GS_ERR_NONFINITE = 5    /* debug mode only (GS_CHECK_FINITE=1): a NaN or an infinity
+                             in an input, or produced in an output; see below */
 } gs_status;
 
 /* Tile edge in pixels; the render kernels map one 16x16 tile to one
@@ -317,6 +333,22 @@ gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_r
 gs_status gs_loss_workspace(int64_t count, size_t *bytes);
 gs_status gs_loss_l1(const float *image, const float *target, int64_t count, float grad_scale, float *dL_dimage,
                      double *sums, void *ws, size_t ws_bytes, void *stream);
+
+/* gs_psnr: peak signal-to-noise ratio over count values (section 5
+ * evaluates novel views by it; the joint optimisation logs it):
+ * out[0] = 10 log10(peak^2 / MSE) in dB, +inf when the images are equal,
+ * out[1] = MSE = sum (image - target)^2 / count, both summed in binary64
+ * (DEVICE, double [2], overwritten).  count >= 1, peak > 0 (1 for [0, 1]
+ * images).  ws: gs_psnr_workspace(count) bytes. */
+gs_status gs_psnr_workspace(int64_t count, size_t *bytes);
+gs_status gs_psnr(const float *image, const float *target, int64_t count, float peak, double *out, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* Number of NaN and infinite values among count floats (host out *n_bad);
+ * synchronises the stream.  The counting behind GS_CHECK_FINITE, callable
+ * on its own; shares the library's one device counter per GPU (calls are
+ * serialised by a host lock). */
+gs_status gs_count_nonfinite(const float *x, int64_t count, int64_t *n_bad, void *stream);
 
 /* One Adam step (bias-corrected, step >= 1) on count floats:
  *   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
@@ -633,6 +665,63 @@ gs_status gs_masked_fill(float *planes, int64_t n, int32_t n_planes, const int32
 size_t gs_anchor_host_bytes(int32_t n_planes, const size_t *bytes);
 gs_status gs_anchor_offload(int32_t n_planes, const void *const *src, const size_t *bytes, void *host, void *stream);
 gs_status gs_anchor_reload(int32_t n_planes, void *const *dst, const size_t *bytes, const void *host, void *stream);
+
+/* ---- spatial cells of a large scene (section 4.4) --------------------------
+ * The scalable construction keeps on the device only what the current views
+ * need and parks the rest in CPU RAM.  For a scene too large to stay
+ * resident the Gaussians are grouped into spatial cells by Lloyd's k-means
+ * over their means; a cell is copied to the device when its bounding sphere
+ * meets a view's frustum.
+ *
+ * gs_cells_assign: labels[i] = the nearest of the k centroids (DEVICE
+ *   double [k][3]) to mean i, by (dx dx + dy dy) + dz dz in binary64 on the
+ *   binary32 means with every operation rounded on its own; ties go to the
+ *   lower centroid.  means [3][n] DEVICE; 1 <= k <= 1024.
+ * gs_cells_kmeans: `iters` Lloyd iterations (assign, then move each
+ *   centroid to the binary64 mean of its members; a centroid without
+ *   members stays), then a final assignment.  init != 0 starts from the
+ *   means at indices floor((j + 1/2) n / k), else from the caller's
+ *   centroids.  Outputs (DEVICE): centroids [k][3] (in/out), labels [n];
+ *   if not NULL, order [n] = the indices stably sorted by label and
+ *   offsets [k + 1] = each cell's first position in that order
+ *   (offsets[k] = n).  The sums are taken in a fixed order (per 4096-mean
+ *   chunk in index order, then over the chunks in order): the result does
+ *   not depend on scheduling.  1 <= k <= min(n, 1024), n < 2^31.
+ *   ws: gs_cells_kmeans_workspace(n, k) bytes.
+ * gs_cells_spheres: radius[j] = max over cell j's members of the distance
+ *   from centroid j to the mean, plus margin times the largest exp(log
+ *   scale) of its members (0 for an empty cell).  log_scales [3][n].
+ *   ws: gs_cells_spheres_workspace(n, k) bytes.
+ * gs_cells_visible: visible[j] = 1 iff sphere j (centre centroids[j],
+ *   radius[j]) reaches in front of the camera's near plane and meets the
+ *   four side planes of its image frustum widened by `guard` half-FOVs
+ *   (the projection's guard band), in binary64; else 0.
+ * Errors: GS_ERR_INVALID_ARG for NULL arrays, sizes out of range, a bad
+ * camera; GS_ERR_WORKSPACE for a short workspace. */
+gs_status gs_cells_assign(const float *means, int64_t n, const double *centroids, int32_t k, int32_t *labels,
+                          void *stream);
+gs_status gs_cells_kmeans_workspace(int64_t n, int32_t k, size_t *bytes);
+gs_status gs_cells_kmeans(const float *means, int64_t n, int32_t k, int32_t iters, int32_t init, double *centroids,
+                          int32_t *labels, int32_t *order, int64_t *offsets, void *ws, size_t ws_bytes,
+                          void *stream);
+gs_status gs_cells_spheres_workspace(int64_t n, int32_t k, size_t *bytes);
+gs_status gs_cells_spheres(const float *means, const float *log_scales, int64_t n, const int32_t *labels,
+                           const double *centroids, int32_t k, float margin, double *radius, void *ws,
+                           size_t ws_bytes, void *stream);
+gs_status gs_cells_visible(const double *centroids, const double *radius, int32_t k, const gs_camera *cam,
+                           float guard, int32_t *visible, void *stream);
+
+/* Residency of cells (the device holds the cells the current views need,
+ * the CPU RAM all of them).  gs_copy_rows: `height` rows of `width` bytes,
+ * row r from src + r spitch to dst + r dpitch, asynchronously on the stream
+ * (either side may be pinned host memory or device memory; a cell's
+ * parameter and optimiser rows move in one call).  gs_fill_f32: count floats
+ * of DEVICE memory set to value (e.g. an opacity logit that culls the
+ * unused columns of a page).  Errors: GS_ERR_INVALID_ARG for NULL pointers
+ * or a row wider than its pitch; GS_ERR_HIP if the copy fails. */
+gs_status gs_copy_rows(void *dst, size_t dpitch, const void *src, size_t spitch, size_t width, size_t height,
+                       void *stream);
+gs_status gs_fill_f32(float *dst, int64_t count, float value, void *stream);
 
 /* ---- mini bundle adjustment (section 4.1, appendix "Initial Pose
  * Estimation") ------------------------------------------------------------

@@ -26,7 +26,7 @@ if not os.path.exists(LIB_PATH):
                       "(python paper_2506_05558_amd/build.py); there is no fallback")
 _lib = C.CDLL(LIB_PATH)
 
-GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_WORKSPACE = range(5)
+GS_OK, GS_ERR_INVALID_ARG, GS_ERR_CAPACITY, GS_ERR_HIP, GS_ERR_WORKSPACE, GS_ERR_NONFINITE = range(6)
 TILE = 16
 REC_FLOATS = 16
 
@@ -95,6 +95,9 @@ _sig = {
     "gs_project_bwd_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
+    "gs_psnr_workspace": (C.c_int, [_i64, _P(_sz)]),
+    "gs_psnr": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _sz, _vp]),
+    "gs_count_nonfinite": (C.c_int, [_vp, _i64, _P(_i64), _vp]),
     "gs_adam_step": (C.c_int, [_vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, _i32, _vp, _vp, _i64, _vp]),
     "gs_lr_decay": (C.c_int, [_vp, _vp, _i64, _f, _vp]),
     "gs_downsample": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp]),
@@ -142,6 +145,14 @@ _sig = {
     "gs_anchor_host_bytes": (C.c_size_t, [_i32, _P(_sz)]),
     "gs_anchor_offload": (C.c_int, [_i32, _P(_vp), _P(_sz), _vp, _vp]),
     "gs_anchor_reload": (C.c_int, [_i32, _P(_vp), _P(_sz), _vp, _vp]),
+    "gs_cells_assign": (C.c_int, [_vp, _i64, _vp, _i32, _vp, _vp]),
+    "gs_cells_kmeans_workspace": (C.c_int, [_i64, _i32, _P(_sz)]),
+    "gs_cells_kmeans": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "gs_cells_spheres_workspace": (C.c_int, [_i64, _i32, _P(_sz)]),
+    "gs_cells_spheres": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _f, _vp, _vp, _sz, _vp]),
+    "gs_cells_visible": (C.c_int, [_vp, _vp, _i32, _P(_Camera), _f, _vp, _vp]),
+    "gs_copy_rows": (C.c_int, [_vp, _sz, _vp, _sz, _sz, _sz, _vp]),
+    "gs_fill_f32": (C.c_int, [_vp, _i64, _f, _vp]),
     "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
     "gs_probe_valu": (C.c_int, [_i32, _i32, _i32, _vp, _vp]),
     "gs_profile_enable": (None, [C.c_int]),
@@ -574,6 +585,30 @@ def loss_l1(image: torch.Tensor, target: torch.Tensor, grad_scale: Optional[floa
     _check(_lib.gs_loss_l1(image.data_ptr(), target.data_ptr(), count, grad_scale, _ptr(dL_dimage),
                            sums.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
     return sums
+
+
+def psnr(image: torch.Tensor, target: torch.Tensor, peak: float = 1.0, out: Optional[torch.Tensor] = None,
+         ws: Optional[torch.Tensor] = None):
+    """out[0] = PSNR in dB (+inf for equal images), out[1] = MSE (float64,
+    device, binary64 sums)."""
+    count = image.numel()
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=image.device)
+    need = C.c_size_t()
+    _check(_lib.gs_psnr_workspace(count, C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=image.device)
+    _check(_lib.gs_psnr(image.data_ptr(), target.data_ptr(), count, peak, out.data_ptr(), ws.data_ptr(),
+                        ws.numel(), _stream()))
+    return out
+
+
+def count_nonfinite(x: torch.Tensor) -> int:
+    """Number of NaN and infinite values in a float32 tensor (synchronises)."""
+    assert x.dtype == torch.float32 and x.is_contiguous()
+    n = C.c_int64()
+    _check(_lib.gs_count_nonfinite(x.data_ptr(), x.numel(), C.byref(n), _stream()))
+    return int(n.value)
 
 
 def adam_step(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None, n_stride=0,
@@ -1113,3 +1148,69 @@ def rasterize(g: Gaussians, cam: Camera, params: Params = Params(), sorter: Opti
     each call then keeps a copy of its own lists."""
     return _Rasterize.apply(g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, cam.pose, cam, params,
                             sorter or BinSorter(), sorter is not None)
+
+
+# ------------------------------------------------------------ spatial cells
+def _ws(query, *args, device="cuda"):
+    need = C.c_size_t()
+    _check(query(*args, C.byref(need)))
+    return torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=device)
+
+
+def cells_assign(means: torch.Tensor, centroids: torch.Tensor) -> torch.Tensor:
+    """gs_cells_assign: nearest centroid (float64 [k][3]) of every mean."""
+    n, k = means.shape[1], centroids.shape[0]
+    _require(means, torch.float32, (3, n), "means")
+    _require(centroids, torch.float64, (k, 3), "centroids")
+    labels = torch.empty(n, dtype=torch.int32, device=means.device)
+    _check(_lib.gs_cells_assign(means.data_ptr(), n, centroids.data_ptr(), k, labels.data_ptr(), _stream()))
+    return labels
+
+
+def cells_kmeans(means: torch.Tensor, k: int, iters: int, centroids: Optional[torch.Tensor] = None,
+                 with_order: bool = True):
+    """gs_cells_kmeans: (centroids [k][3] float64, labels, order, offsets);
+    starts from the spread initial centroids unless centroids are given."""
+    n = means.shape[1]
+    _require(means, torch.float32, (3, n), "means")
+    dev = means.device
+    init = centroids is None
+    cent = torch.empty((k, 3), dtype=torch.float64, device=dev) if init else centroids
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    order = torch.empty(n, dtype=torch.int32, device=dev) if with_order else None
+    offsets = torch.empty(k + 1, dtype=torch.int64, device=dev) if with_order else None
+    ws = _ws(_lib.gs_cells_kmeans_workspace, n, k, device=dev)
+    _check(_lib.gs_cells_kmeans(means.data_ptr(), n, k, iters, int(init), cent.data_ptr(), labels.data_ptr(),
+                                _ptr(order), _ptr(offsets), ws.data_ptr(), ws.numel(), _stream()))
+    return cent, labels, order, offsets
+
+
+def cells_spheres(means: torch.Tensor, log_scales: torch.Tensor, labels: torch.Tensor, centroids: torch.Tensor,
+                  margin: float = 3.0) -> torch.Tensor:
+    n, k = means.shape[1], centroids.shape[0]
+    radius = torch.empty(k, dtype=torch.float64, device=means.device)
+    ws = _ws(_lib.gs_cells_spheres_workspace, n, k, device=means.device)
+    _check(_lib.gs_cells_spheres(means.data_ptr(), log_scales.data_ptr(), n, labels.data_ptr(), centroids.data_ptr(),
+                                 k, margin, radius.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+    return radius
+
+
+def cells_visible(centroids: torch.Tensor, radius: torch.Tensor, cam: Camera, guard: float = 1.3,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    k = centroids.shape[0]
+    if out is None:
+        out = torch.empty(k, dtype=torch.int32, device=centroids.device)
+    _check(_lib.gs_cells_visible(centroids.data_ptr(), radius.data_ptr(), k, C.byref(cam.c()), guard,
+                                 out.data_ptr(), _stream()))
+    return out
+
+
+def copy_rows(dst_ptr: int, dpitch: int, src_ptr: int, spitch: int, width: int, height: int):
+    """gs_copy_rows on the current stream (raw addresses: device or pinned host)."""
+    _check(_lib.gs_copy_rows(dst_ptr, dpitch, src_ptr, spitch, width, height, _stream()))
+
+
+def fill_(t: torch.Tensor, value: float):
+    """gs_fill_f32 over a contiguous float32 device tensor."""
+    assert t.dtype == torch.float32 and t.is_contiguous()
+    _check(_lib.gs_fill_f32(t.data_ptr(), t.numel(), value, _stream()))
