@@ -59,9 +59,11 @@ _lib = None
 
 
 def lib():
+    """The oracle library (GS_ORACLE_LIB names another build of gs_oracle.c,
+    e.g. one with the address and undefined-behaviour sanitizers)."""
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(os.environ.get("GS_ORACLE_LIB") or build())
         _lib.orc_render.restype = C.c_int
         _lib.orc_render_bwd.restype = C.c_int
     return _lib

@@ -9,7 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gs_api.h")
-LIB = os.path.join(ROOT, "paper_2506_05558_amd", "libgsmi.so")
+# GSMI_LIB: another build of the same sources (e.g. the host code under AddressSanitizer)
+LIB = os.environ.get("GSMI_LIB") or os.path.join(ROOT, "paper_2506_05558_amd", "libgsmi.so")
 
 
 def declared():
