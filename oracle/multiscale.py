@@ -57,3 +57,67 @@ def prune_keep(opacity_logits, min_opacity: float):
 def gather_planes(src, index):
     """[P][n] planes -> [P][m]: column j is column index[j] of src."""
     return np.asarray(src)[:, np.asarray(index, np.int64)]
+
+
+# ------------------------------------------------ 3D smoothing filter
+# Mip-Splatting's 3D smoothing filter, which the paper's "proper filtering"
+# of multi-scale training cites: each Gaussian is convolved with an
+# isotropic 3D Gaussian low-pass of variance v = (s_f / nu)^2, nu the
+# highest sampling rate (pixels per world unit, f / depth) at which any
+# training camera sees it, s_f a constant (0.2 in Mip-Splatting).  The
+# convolution adds v to the covariance, i.e. to each axis variance in the
+# same rotation, and the opacity is scaled so that the Gaussian's integral
+# o sqrt(det Sigma) is unchanged:
+#   s'_k^2 = s_k^2 + v,   o' = o prod_k s_k / s'_k.
+
+
+def sampling_rate(means, R, t, fx, fy, cx, cy, width, height, near=0.2, guard=1.15):
+    """Per Gaussian: fx / z in the camera when its mean lies in front of the
+    near plane and inside the image widened by `guard` (Mip-Splatting's
+    1.15 screen margin), else 0 (FP64)."""
+    m = np.asarray(means, np.float32).astype(np.float64)
+    p = np.asarray(R, np.float64) @ m + np.asarray(t, np.float64)[:, None]
+    z = p[2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = fx * p[0] / z + cx
+        v = fy * p[1] / z + cy
+        inside = (z > near) & (u >= -(guard - 1) / 2 * width) & (u <= (guard + 1) / 2 * width) & \
+                 (v >= -(guard - 1) / 2 * height) & (v <= (guard + 1) / 2 * height)
+        return np.where(inside, fx / z, 0.0)
+
+
+def filter_variance(nu_max, s_f: float = 0.2):
+    """(s_f / nu)^2 where a camera saw the Gaussian, else 0."""
+    nu = np.asarray(nu_max, np.float64)
+    with np.errstate(divide="ignore"):
+        return np.where(nu > 0, (s_f / np.where(nu > 0, nu, 1.0)) ** 2, 0.0)
+
+
+def apply_filter3d(log_scales, opacity_logits, var):
+    """The filtered Gaussian as (log-scales', opacity logit') in FP64."""
+    ls = np.asarray(log_scales, np.float64)
+    a = np.asarray(opacity_logits, np.float64)
+    v = np.asarray(var, np.float64)
+    ls2 = 0.5 * np.log(np.exp(2.0 * ls) + v)
+    o = 1.0 / (1.0 + np.exp(-a))
+    o2 = o * np.exp((ls - ls2).sum(axis=0))
+    return ls2, np.log(o2) - np.log1p(-o2)
+
+
+def filter3d_vjp(log_scales, opacity_logits, var, g_ls2, g_logit2):
+    """Gradients with respect to (log-scales, logit) from those with respect
+    to the filtered (log-scales', logit'), by the chain rule of
+    apply_filter3d."""
+    ls = np.asarray(log_scales, np.float64)
+    a = np.asarray(opacity_logits, np.float64)
+    v = np.asarray(var, np.float64)
+    s2 = np.exp(2.0 * ls)
+    ls2 = 0.5 * np.log(s2 + v)
+    o = 1.0 / (1.0 + np.exp(-a))
+    f = np.exp((ls - ls2).sum(axis=0))
+    o2 = o * f
+    g_o2 = np.asarray(g_logit2, np.float64) / (o2 * (1.0 - o2))  # d logit' / d o' = 1 / (o'(1 - o'))
+    dls2 = s2 / (s2 + v)  # d ls'_k / d ls_k
+    g_ls = np.asarray(g_ls2, np.float64) * dls2 + g_o2 * o2 * (1.0 - dls2)
+    g_a = g_o2 * f * o * (1.0 - o)
+    return g_ls, g_a

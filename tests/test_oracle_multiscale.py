@@ -80,3 +80,67 @@ def test_gather_keeps_order_and_planes():
     src = np.arange(3 * 8, dtype=np.float32).reshape(3, 8)
     out = ms.gather_planes(src, [0, 2, 7])
     assert out.tolist() == [[0, 2, 7], [8, 10, 15], [16, 18, 23]]
+
+
+def test_filter3d_closed_forms_and_invariant():
+    rng = np.random.default_rng(31)
+    n = 50
+    ls = rng.normal(-3, 0.6, (3, n))
+    a = rng.normal(0, 1, n)
+    v = rng.uniform(0, 0.01, n)
+    ls2, a2 = ms.apply_filter3d(ls, a, v)
+    # each axis variance grows by v, the same rotation
+    assert np.allclose(np.exp(2 * ls2), np.exp(2 * ls) + v, rtol=1e-13)
+    # the integral o sqrt(det Sigma) = o prod s_k is unchanged
+    o = 1 / (1 + np.exp(-a))
+    o2 = 1 / (1 + np.exp(-a2))
+    assert np.allclose(o2 * np.exp(ls2.sum(0)), o * np.exp(ls.sum(0)), rtol=1e-12)
+    # an isotropic Gaussian of scale s: o' = o (s^2 / (s^2 + v))^(3/2)
+    s = 0.05
+    iso = np.full((3, 1), np.log(s))
+    _, ai = ms.apply_filter3d(iso, np.array([0.3]), np.array([0.0004]))
+    oi = 1 / (1 + np.exp(-ai[0]))
+    assert abs(oi - (1 / (1 + np.exp(-0.3))) * (s * s / (s * s + 0.0004)) ** 1.5) < 1e-14
+    # v = 0 is the identity
+    l0, a0 = ms.apply_filter3d(ls, a, np.zeros(n))
+    assert np.allclose(l0, ls, atol=1e-15) and np.allclose(a0, a, atol=1e-12)
+
+
+def test_filter3d_vjp_finite_differences():
+    rng = np.random.default_rng(32)
+    n = 20
+    ls = rng.normal(-3, 0.6, (3, n))
+    a = rng.normal(0, 1, n)
+    v = rng.uniform(1e-4, 4e-3, n)
+    w_ls = rng.standard_normal((3, n))
+    w_a = rng.standard_normal(n)
+    loss = lambda L, A: (w_ls * ms.apply_filter3d(L, A, v)[0]).sum() + \
+        (w_a * ms.apply_filter3d(L, A, v)[1]).sum()
+    g_ls, g_a = ms.filter3d_vjp(ls, a, v, w_ls, w_a)
+    h = 1e-6
+    for k in range(3):
+        for i in range(0, n, 3):
+            d = np.zeros_like(ls)
+            d[k, i] = h
+            fd = (loss(ls + d, a) - loss(ls - d, a)) / (2 * h)
+            assert abs(fd - g_ls[k, i]) <= 1e-6 * (1 + abs(fd))
+    for i in range(n):
+        d = np.zeros(n)
+        d[i] = h
+        fd = (loss(ls, a + d) - loss(ls, a - d)) / (2 * h)
+        assert abs(fd - g_a[i]) <= 1e-6 * (1 + abs(fd))
+
+
+def test_sampling_rate_brute_force():
+    rng = np.random.default_rng(33)
+    m = rng.uniform([-3, -2, -1], [3, 2, 8], (300, 3)).T.astype(np.float32)
+    R, t = np.eye(3), np.zeros(3)
+    W, H, f = 160, 120, 100.0
+    nu = ms.sampling_rate(m, R, t, f, f, W / 2, H / 2, W, H)
+    for i in range(m.shape[1]):
+        x, y, z = (float(c) for c in m[:, i].astype(np.float64))
+        u, vv = (f * x / z + W / 2, f * y / z + H / 2) if z > 0 else (0, 0)
+        inside = z > 0.2 and -0.075 * W <= u <= 1.075 * W and -0.075 * H <= vv <= 1.075 * H
+        assert nu[i] == (f / z if inside else 0.0)
+    var = ms.filter_variance(np.array([0.0, 100.0, 400.0]))
+    assert var[0] == 0.0 and abs(var[1] - 4e-6) < 1e-20 and abs(var[2] - 2.5e-7) < 1e-21
