@@ -62,6 +62,7 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
                                             Stage<NB> &S, uint32_t *gid_out) {
   const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
   const uint32_t j = base + t;
+  const float l2min = __builtin_amdgcn_logf(a.alpha_min);
   unsigned mask = 0;
   if (t < NB && j < end) {
     const uint32_t gid = a.values[j];
@@ -84,10 +85,45 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
       cx |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
       cy |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << c;
     }
+    unsigned box = 0;
 #pragma unroll
     for (int bl = 0; bl < kBlocks; ++bl) {
       const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
-      mask |= ((cx >> bx) & (cy >> by) & 1u) << bl;
+      box |= ((cx >> bx) & (cy >> by) & 1u) << bl;
+    }
+    // Of the sub-blocks the box meets, keep those the support ellipse meets:
+    // with q(d) = a dx^2 + b dx dy + c dy^2 = -(log2-domain exponent) the
+    // pixel test keeps d iff q(d) <= Q = log2 o - log2 alpha_min, so a block
+    // whose rectangle of pixel centres has min q > Q (plus a margin far above
+    // the FP32 rounding of the per-pixel evaluation) holds no kept pixel.  The
+    // minimum of the convex q over the rectangle is 0 if the mean lies inside,
+    // else it is on one of the four edges (a 1D quadratic, clamped).
+    const float qa = __fmul_rn(0.5f * kLog2e, r1.x), qb = __fmul_rn(kLog2e, r1.y),
+                qc = __fmul_rn(0.5f * kLog2e, r1.z);
+    const float Q = __fsub_rn(__builtin_amdgcn_logf(r1.w), l2min);
+    const float hy_x = 0.5f * qb / qc, hx_y = 0.5f * qb / qa;  // argmin offsets per unit of the fixed coordinate
+    while (box) {
+      const int bl = __builtin_ctz(box);
+      box &= box - 1;
+      const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
+      const float X0 = 4.0f * bx - mx, X1 = X0 + 3.0f, Y0 = 4.0f * by - my, Y1 = Y0 + 3.0f;
+      bool keep = X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f;
+      if (!keep) {
+        float qmin = INFINITY, mag = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool vert = e < 2;  // an edge of fixed x (else of fixed y)
+          const float F = vert ? (e == 0 ? X0 : X1) : (e == 2 ? Y0 : Y1);
+          const float v = vert ? fminf(fmaxf(-hy_x * F, Y0), Y1) : fminf(fmaxf(-hx_y * F, X0), X1);
+          const float dx = vert ? F : v, dy = vert ? v : F;
+          const float q = qa * dx * dx + qb * dx * dy + qc * dy * dy;
+          const float m = qa * dx * dx + fabsf(qb * dx * dy) + qc * dy * dy;
+          mag = q < qmin ? m : mag;
+          qmin = fminf(q, qmin);
+        }
+        keep = !(qmin - 1e-4f * mag - 1e-4f > Q);  // a NaN keeps the block
+      }
+      mask |= (unsigned)keep << bl;
     }
   }
   const uint64_t lt = lanemask_lt();
@@ -624,6 +660,16 @@ static RenderArgs render_args(const gs_camera *cam, const gs_raster_params *rp, 
 
 static int padded_grid(int ntiles) { return (ntiles + 7) / 8 * 8; }
 
+// GS_CHECK_FINITE: the image and depth a render wrote
+static gs_status check_frame(const gs_camera *cam, const float *image, const float *depth, const char *fn,
+                             hipStream_t s) {
+  if (!finite_checks_on()) return GS_OK;
+  const int64_t np = (int64_t)cam->width * cam->height;
+  gs_status st = check_finite(image, 3 * np, fn, "image", s);
+  if (st != GS_OK) return st;
+  return check_finite(depth, np, fn, "depth", s);
+}
+
 // ---------------------------------------------- fixed scratch (no allocation)
 // The per-tile loss partials of gs_render_fwd_l1_noalloc live in a
 // file-scope device array: each GPU the library runs on holds its own copy
@@ -675,7 +721,7 @@ gs_status gs_render_fwd(const gs_camera *cam, const gs_raster_params *rp, const 
     GS_LAUNCH("render_fwd", (k_render_fwd<true, false>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
   else
     GS_LAUNCH("render_fwd", (k_render_fwd<false, false>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
-  return GS_OK;
+  return check_frame(cam, image, depth, "gs_render_fwd", (hipStream_t)stream);
 }
 
 gs_status gs_render_fwd_l1_workspace(int32_t width, int32_t height, size_t *bytes) {
@@ -705,7 +751,7 @@ gs_status gs_render_fwd_l1(const gs_camera *cam, const gs_raster_params *rp, con
   GS_LAUNCH("render_fwd", (k_render_fwd<false, true>), padded_grid(a.ntiles), 256, 0, (hipStream_t)stream, a, o);
   GS_LAUNCH("loss_final", k_tile_loss_sums, 1, kSumBlock, 0, (hipStream_t)stream, (const double *)ws, a.ntiles,
             sums);
-  return GS_OK;
+  return check_frame(cam, image, depth, "gs_render_fwd_l1", (hipStream_t)stream);
 }
 
 gs_status gs_render_fwd_l1_noalloc(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
@@ -785,6 +831,14 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
     set_error("gs_render_bwd: workspace %zu bytes < %zu", ws_bytes, need);
     return GS_ERR_WORKSPACE;
   }
+  const bool checks = finite_checks_on();
+  const int64_t np = (int64_t)cam->width * cam->height;
+  hipStream_t hs = (hipStream_t)stream;
+  if (checks) {
+    if ((st = check_finite(dL_dimage, 3 * np, "gs_render_bwd", "dL_dimage", hs)) != GS_OK) return st;
+    if ((st = check_finite(dL_ddepth, np, "gs_render_bwd", "dL_ddepth", hs)) != GS_OK) return st;
+    if ((st = check_finite(dL_dalpha, np, "gs_render_bwd", "dL_dalpha", hs)) != GS_OK) return st;
+  }
   Carve cv(ws);
   float *pair_grad = cv.take<float>(12 * (size_t)n_instances);
   size_t pose_bytes = 0;
@@ -805,7 +859,13 @@ gs_status gs_render_bwd(const gs_camera *cam, const gs_raster_params *rp, const 
   view.first_slot = first_slot;
   view.dL_dpose = dL_dpose;
   view.dL_dtwist = dL_dtwist;
-  return gs_project_bwd_views(1, &view, rp, g, grads, pose_ws, pose_bytes, stream);
+  if ((st = gs_project_bwd_views(1, &view, rp, g, grads, pose_ws, pose_bytes, stream)) != GS_OK) return st;
+  if (checks) {
+    if ((st = check_finite_gaussians(grads, "gs_render_bwd", "grads", hs)) != GS_OK) return st;
+    if ((st = check_finite_d(dL_dpose, 12, "gs_render_bwd", "dL_dpose", hs)) != GS_OK) return st;
+    if ((st = check_finite_d(dL_dtwist, 6, "gs_render_bwd", "dL_dtwist", hs)) != GS_OK) return st;
+  }
+  return GS_OK;
 }
 
 }  // extern "C"
