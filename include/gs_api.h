@@ -121,6 +121,14 @@ typedef struct {
   float *quats;          /* [4][n] rotation (w, x, y, z), normalised inside */
   float *opacity_logits; /* [n]    opacity = sigmoid(logit) */
   float *sh;             /* [(deg+1)^2][3][n] SH coefficients per colour channel */
+  float *filter3d;       /* [n] or NULL: variance v of the 3D smoothing filter of
+                            multi-scale training (section 4.3, Mip-Splatting): the
+                            projection uses axis variances s^2 + v in the same
+                            rotation and opacity o prod s / sqrt(s^2 + v) (the
+                            Gaussian convolved with an isotropic low-pass, its
+                            integral kept); gradients flow to the log-scales and
+                            the logit, none to v.  Read by the projection and its
+                            adjoint only; ignored in gradient structs. */
 } gs_gaussians;          /* HOST struct of DEVICE pointers */
 
 typedef struct {
@@ -324,6 +332,14 @@ gs_status gs_render_bwd_pairs(const gs_camera *cam, const gs_raster_params *rp, 
 gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *bytes);
 gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream);
+/* The same adjoint, but grads receive the sum over the views by plain
+ * stores: every Gaussian's gradients are overwritten (0 for one no view
+ * saw), so the caller need not clear them first -- one pass over the
+ * gradient planes instead of a clearing pass plus a read-modify-write
+ * (the pose outputs still accumulate). */
+gs_status gs_project_bwd_views_store(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                                     const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
+                                     void *stream);
 
 /* ---- loss, metrics and optimiser (helpers of the joint optimisation) ----
  * gs_loss_l1: over count values, sums[0] = sum |image - target|,
@@ -385,6 +401,19 @@ gs_status gs_zero(void *ptr, size_t bytes, void *stream);
 /* mask[i] |= (tiles_touched[i] > 0) over n Gaussians: the set a step
  * processed, which the sparse Adam step of section 4.3 updates. */
 gs_status gs_mark_visible(const int32_t *tiles_touched, int64_t n, int32_t *mask, void *stream);
+
+/* gs_filter3d_update: the 3D smoothing filter's sampling rates (section 4.3's
+ * "proper filtering", Mip-Splatting): for each Gaussian, nu_max = max(nu_max,
+ * fx / z) over the cameras whose image, widened by `guard` times its size
+ * about its centre (1.15 in Mip-Splatting), holds the projected mean in front
+ * of the near plane (binary64 on the binary32 means; nu_max [n] DEVICE,
+ * in/out, 0 for a Gaussian no camera has seen); then, if filter3d is not
+ * NULL, filter3d = (s_f / nu_max)^2, 0 where nu_max = 0 (s_f = 0.2 in
+ * Mip-Splatting).  Call it with every new keyframe's camera.  cams: n_views
+ * host structs (poses on the device).  Errors: GS_ERR_INVALID_ARG for NULL
+ * arrays, guard < 1, s_f <= 0, a bad camera. */
+gs_status gs_filter3d_update(const float *means, int64_t n, int32_t n_views, const gs_camera *cams, float guard,
+                             float s_f, float *nu_max, float *filter3d, void *stream);
 
 /* ---- multi-scale training (section 4.3) ------------------------------
  * Coarse-to-fine: a newly added image first trains at 2^l downsampling

@@ -235,3 +235,87 @@ gs_status gs_gather_planes(const float *src, int64_t n_src, int32_t planes, cons
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- 3D smoothing filter
+// Mip-Splatting's 3D filter, which the paper's "proper filtering" of
+// multi-scale training cites: a Gaussian's highest sampling rate over the
+// training cameras, nu = max f_x / z over the cameras whose image (widened
+// by `guard` times its size about its centre) holds the projected mean in
+// front of the near plane, and the filter variance (s_f / nu)^2 (0 where no
+// camera has seen it).  Binary64 on the binary32 means.
+namespace gsmi {
+namespace {
+constexpr int kF3Views = 8;
+struct F3View {
+  const float *pose;
+  double fx, fy, cx, cy, umin, umax, vmin, vmax, near_plane;
+};
+struct F3Args {
+  const float *means;
+  int64_t n;
+  int nv;
+  F3View v[kF3Views];
+  float *nu_max, *filter3d;
+  double s_f;
+  int last;  // the last batch of views: write the filter variances
+};
+
+__global__ __launch_bounds__(256) void k_filter3d(F3Args a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  const double x = a.means[i], y = a.means[a.n + i], z = a.means[2 * a.n + i];
+  double nu = (double)a.nu_max[i];
+  for (int k = 0; k < a.nv; ++k) {
+    const F3View &v = a.v[k];
+    const float *P = v.pose;
+    const double px = (double)P[0] * x + (double)P[1] * y + (double)P[2] * z + (double)P[9];
+    const double py = (double)P[3] * x + (double)P[4] * y + (double)P[5] * z + (double)P[10];
+    const double pz = (double)P[6] * x + (double)P[7] * y + (double)P[8] * z + (double)P[11];
+    if (!(pz > v.near_plane)) continue;
+    const double u = v.fx * px / pz + v.cx, w = v.fy * py / pz + v.cy;
+    if (u >= v.umin && u <= v.umax && w >= v.vmin && w <= v.vmax) nu = fmax(nu, v.fx / pz);
+  }
+  a.nu_max[i] = (float)nu;
+  if (a.last && a.filter3d) {
+    const double r = a.s_f / nu;
+    a.filter3d[i] = nu > 0.0 ? (float)(r * r) : 0.0f;
+  }
+}
+}  // namespace
+}  // namespace gsmi
+
+extern "C" gs_status gs_filter3d_update(const float *means, int64_t n, int32_t n_views, const gs_camera *cams,
+                                        float guard, float s_f, float *nu_max, float *filter3d, void *stream) {
+  using namespace gsmi;
+  GS_REQUIRE(n >= 0 && n_views >= 0 && guard >= 1.0f && s_f > 0.0f, "gs_filter3d_update: bad sizes or constants");
+  if (n == 0) return GS_OK;
+  GS_REQUIRE(means && nu_max && (n_views == 0 || cams), "gs_filter3d_update: NULL argument");
+  for (int k = 0; k < n_views; ++k)
+    GS_REQUIRE(cams[k].pose && cams[k].width > 0 && cams[k].height > 0 && cams[k].fx > 0.f && cams[k].fy > 0.f,
+               "gs_filter3d_update: bad camera %d", k);
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  int v0 = 0;
+  do {
+    F3Args a;
+    a.means = means;
+    a.n = n;
+    a.nv = std::min(kF3Views, n_views - v0);
+    for (int k = 0; k < a.nv; ++k) {
+      const gs_camera &c = cams[v0 + k];
+      F3View &v = a.v[k];
+      v.pose = c.pose;
+      v.fx = c.fx, v.fy = c.fy, v.cx = c.cx, v.cy = c.cy;
+      const double g = 0.5 * ((double)guard - 1.0);
+      v.umin = -g * c.width, v.umax = (1.0 + g) * c.width;
+      v.vmin = -g * c.height, v.vmax = (1.0 + g) * c.height;
+      v.near_plane = c.near_plane;
+    }
+    a.nu_max = nu_max;
+    a.filter3d = filter3d;
+    a.s_f = s_f;
+    v0 += a.nv;
+    a.last = v0 >= n_views;
+    GS_LAUNCH("filter3d", k_filter3d, grid, 256, 0, (hipStream_t)stream, a);
+  } while (v0 < n_views);
+  return GS_OK;
+}

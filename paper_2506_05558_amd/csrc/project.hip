@@ -99,8 +99,10 @@ struct MultiArgs {
   int64_t n;
   int nv;
   float eps2d, alpha_min, guard;
-  int mip;  // eps2d is a screen-space filter whose opacity compensation applies
+  int mip;    // eps2d is a screen-space filter whose opacity compensation applies
+  int store;  // the adjoint stores (=) every Gaussian's gradients instead of adding them
   const float *means, *log_scales, *quats, *opac, *sh;
+  const float *f3;                 // [n] 3D smoothing-filter variance per Gaussian, or NULL
   float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
   double *partials;                // [nv][gridDim.x][12] pose partial sums
   float *gc;                       // [nv][3][n] clamped colour gradient per view (adjoint workspace)
@@ -111,8 +113,8 @@ struct MultiArgs {
 template <int DEG>
 struct GParams {
   static constexpr int NB = (DEG + 1) * (DEG + 1);
-  float mu[3], q[4], ls[3], logit;
-  float sh[NB * 3];  // [k][channel]
+  float mu[3], q[4], ls[3], logit, f3;  // f3: 3D smoothing-filter variance (0: none)
+  float sh[NB * 3];                     // [k][channel]
 };
 
 template <int DEG, bool SH = true>
@@ -125,6 +127,7 @@ __device__ __forceinline__ void load_params(const MultiArgs &m, int64_t i, GPara
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.ls[k] = m.log_scales[k * n + i];
   P.logit = m.opac[i];
+  P.f3 = m.f3 ? m.f3[i] : 0.0f;
   if (SH) {
 #pragma unroll
     for (int k = 0; k < GParams<DEG>::NB * 3; ++k) P.sh[k] = m.sh[(int64_t)k * n + i];
@@ -142,6 +145,7 @@ struct Geo {
   Real J00, J02, J11, J12;
   Real qn[4], qinv;
   Real Rq[9], s[3], M[9];
+  Real s0[3], ofac;  // unfiltered scales; opacity factor prod s0 / s of the 3D filter
   Real T[6], TM[6];
   Real a, b, c, A, B, C;
 };
@@ -152,6 +156,8 @@ __device__ __forceinline__ double real_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float real_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double real_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float real_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double real_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float real_sqrt(float x) { return __builtin_sqrtf(x); }
 
 // Camera-space point and the 2D covariance.  Returns false if culled by
 // the near plane or a non-positive determinant.
@@ -194,7 +200,18 @@ __device__ __forceinline__ bool geometry(const MultiArgs &m, const ViewArgs &v, 
   f.Rq[7] = 2 * (y * z + w * x);
   f.Rq[8] = 1 - 2 * (x * x + y * y);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) f.s[k] = real_exp((Real)P.ls[k]);
+  for (int k = 0; k < 3; ++k) f.s0[k] = f.s[k] = real_exp((Real)P.ls[k]);
+  // 3D smoothing filter: the Gaussian convolved with an isotropic low-pass of
+  // variance f3 has axis variances s^2 + f3 in the same rotation, and its
+  // opacity is scaled by prod s0 / s so that its integral is unchanged
+  f.ofac = (Real)1;
+  if (P.f3 > 0.0f) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      f.s[k] = real_sqrt(f.s0[k] * f.s0[k] + (Real)P.f3);
+      f.ofac *= f.s0[k] / f.s[k];
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -222,8 +239,6 @@ __device__ __forceinline__ bool geometry(const MultiArgs &m, const ViewArgs &v, 
   return true;
 }
 
-__device__ __forceinline__ double real_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float real_sqrt(float x) { return __builtin_sqrtf(x); }
 
 // Opacity compensation of the screen-space filter: rho = sqrt(det0 / det)
 // with det0 the determinant of the unfiltered 2D covariance TM TM^T and
@@ -272,7 +287,7 @@ __device__ __forceinline__ void project_one(const MultiArgs &m, const ViewArgs &
     ok = fabs(mx) < 8388608.0 && fabs(my) < 8388608.0;  // |mean| < 2^23 px
   }
   if (ok) {
-    o = 1.0 / (1.0 + exp(-(double)P.logit));
+    o = f.ofac / (1.0 + exp(-(double)P.logit));
     if (m.mip) {
       double det0, det;
       o *= mip_rho<double>(f, (double)m.eps2d, det0, det);
@@ -354,11 +369,18 @@ __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs
   gc[1] = rgbz.y > 0.f ? g1.w : 0.f;
   gc[2] = rgbz.z > 0.f ? g2.x : 0.f;
 
-  // opacity o = sigmoid(logit) rho (rho = 1 without the screen-space filter)
+  // opacity o = sigmoid(logit) ofac rho (ofac = 1 without the 3D filter, rho = 1
+  // without the screen-space filter)
   const float osig = real_rcp(1.0f + __expf(-P.logit));
   float rho = 1.0f, det0 = 0.f, detf = 1.f;
   if (m.mip) rho = mip_rho<float>(f, m.eps2d, det0, detf);
-  acc.go += g1.y * rho * osig * (1.0f - osig);
+  acc.go += g1.y * rho * f.ofac * osig * (1.0f - osig);
+  if (P.f3 > 0.0f) {
+    // ofac = prod s0 / s: d ln ofac / d ln s0_k = 1 - s0_k^2 / s_k^2
+    const float od = g1.y * rho * f.ofac * osig;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc.gl[k] += od * (1.0f - (f.s0[k] * f.s0[k]) / (f.s[k] * f.s[k]));
+  }
 
   // conic -> Sigma2: dL/dSigma2 = -Q G Q with G = [[gA, gB/2], [gB/2, gC]]
   const float gA = g0.z, hB = 0.5f * g0.w, gC = g1.x;
@@ -371,7 +393,7 @@ __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs
     // rho through the unfiltered covariance (a0, b, c0): d rho = rho / 2 d(ln det0 - ln det),
     // with d ln det0 = (c0, -2 b, a0) / det0 and d ln det = (c, -2 b, a) / det; the
     // off-diagonal b sits in two entries of the full-matrix gradient
-    const float k = 0.5f * g1.y * osig * rho, i0 = real_rcp(det0), i1 = real_rcp(detf);
+    const float k = 0.5f * g1.y * osig * f.ofac * rho, i0 = real_rcp(det0), i1 = real_rcp(detf);
     const float a0 = f.a - m.eps2d, c0 = f.c - m.eps2d;
     S00 += k * (c0 * i0 - f.c * i1);
     S11 += k * (a0 * i0 - f.a * i1);
@@ -404,7 +426,8 @@ __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs
       gRq[3 * r + c] = gM * f.s[c];
       gs += gM * f.Rq[3 * r + c];
     }
-    acc.gl[c] += gs * f.s[c];
+    // d s / d log s0 = s0^2 / s (= s without the 3D filter)
+    acc.gl[c] += gs * (P.f3 > 0.0f ? f.s0[c] * f.s0[c] / f.s[c] : f.s[c]);
   }
   {
     const float w = f.qn[0], x = f.qn[1], y = f.qn[2], z = f.qn[3];
@@ -575,8 +598,19 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
       part[t] = 0.0;
     }
   }
-  if (!any) return;
+  if (!valid || (!any && !m.store)) return;
   const int64_t n = m.n;
+  if (m.store) {  // zero where no view saw the Gaussian
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      m.gm[k * n + i] = acc.gm[k];
+      m.gl[k * n + i] = acc.gl[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m.gq[k * n + i] = acc.gq[k];
+    m.go[i] = acc.go;
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     m.gm[k * n + i] += acc.gm[k];
@@ -650,10 +684,15 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
       gm[2] += (gz - radial * d[2]) * dinv;
     }
   }
-  if (!any) return;
-  if (DEG > 0) {
+  if (!any && !m.store) return;
+  if (DEG > 0 && any) {  // after the geometry pass's store or sum
 #pragma unroll
     for (int k = 0; k < 3; ++k) m.gm[k * n + i] += gm[k];
+  }
+  if (m.store) {
+#pragma unroll
+    for (int k = 0; k < NB * 3; ++k) m.gsh[(int64_t)k * n + i] = gsh[k];
+    return;
   }
 #pragma unroll
   for (int k = 0; k < NB * 3; ++k) m.gsh[(int64_t)k * n + i] += gsh[k];
@@ -745,7 +784,9 @@ MultiArgs multi_args(const gs_raster_params *rp, const gs_gaussians *g) {
   m.alpha_min = rp->alpha_min;
   m.guard = rp->guard;
   m.mip = rp->mip_filter != 0;
+  m.store = 0;
   m.means = g->means; m.log_scales = g->log_scales; m.quats = g->quats; m.opac = g->opacity_logits; m.sh = g->sh;
+  m.f3 = g->filter3d;
   m.gm = m.gl = m.gq = m.go = m.gsh = nullptr;
   m.partials = nullptr;
   return m;
@@ -870,8 +911,26 @@ gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *byt
   return GS_OK;
 }
 
+static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                                   const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
+                                   void *stream, int store);
+
 gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream) {
+  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 0);
+}
+
+gs_status gs_project_bwd_views_store(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                                     const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
+                                     void *stream) {
+  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 1);
+}
+
+}  // extern "C"
+
+static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                                   const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
+                                   void *stream, int store) {
   GS_REQUIRE(n_views >= 0 && (n_views == 0 || views), "gs_project_bwd_views: bad view list");
   gs_status st = check_gaussians(g, "gs_project_bwd_views");
   if (st != GS_OK) return st;
@@ -891,7 +950,8 @@ gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_r
     return GS_ERR_WORKSPACE;
   }
   if (g->n == 0) return GS_OK;
-  for (int v0 = 0; v0 < n_views; v0 += kMaxViews) {
+  // (with no view the store form still runs once: every gradient becomes 0)
+  for (int v0 = 0; v0 < n_views || (store && v0 == 0); v0 += kMaxViews) {
     MultiArgs m = multi_args(rp, g);
     m.gm = grads->means; m.gl = grads->log_scales; m.gq = grads->quats; m.go = grads->opacity_logits;
     m.gsh = grads->sh;
@@ -899,6 +959,7 @@ gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_r
     m.gc = (float *)((char *)ws + align_up(sizeof(double) * 12 * (size_t)std::max(1, std::min(kMaxViews, (int)n_views)) *
                                            (size_t)proj_blocks(g->n)));
     m.nv = std::min(kMaxViews, n_views - v0);
+    m.store = store && v0 == 0;  // later batches of views add to the first batch's stores
     for (int k = 0; k < m.nv; ++k) {
       const gs_view &gv = views[v0 + k];
       m.v[k] = view_args(&gv.cam, &gv.proj);
@@ -911,6 +972,8 @@ gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_r
   }
   return GS_OK;
 }
+
+extern "C" {
 
 }  // extern "C"
 

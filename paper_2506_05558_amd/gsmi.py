@@ -50,7 +50,7 @@ class _Params(C.Structure):
 
 class _Gauss(C.Structure):
     _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int32), ("means", C.c_void_p), ("log_scales", C.c_void_p),
-                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("sh", C.c_void_p)]
+                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("sh", C.c_void_p), ("filter3d", C.c_void_p)]
 
 
 class _Proj(C.Structure):
@@ -93,6 +93,7 @@ _sig = {
                                       _vp, _vp, _vp, _vp, _vp]),
     "gs_project_bwd_views_workspace": (C.c_int, [_i64, _i32, _P(_sz)]),
     "gs_project_bwd_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
+    "gs_project_bwd_views_store": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
     "gs_psnr_workspace": (C.c_int, [_i64, _P(_sz)]),
@@ -151,6 +152,7 @@ _sig = {
     "gs_cells_spheres_workspace": (C.c_int, [_i64, _i32, _P(_sz)]),
     "gs_cells_spheres": (C.c_int, [_vp, _vp, _i64, _vp, _vp, _i32, _f, _vp, _vp, _sz, _vp]),
     "gs_cells_visible": (C.c_int, [_vp, _vp, _i32, _P(_Camera), _f, _vp, _vp]),
+    "gs_filter3d_update": (C.c_int, [_vp, _i64, _i32, _P(_Camera), _f, _f, _vp, _vp, _vp]),
     "gs_copy_rows": (C.c_int, [_vp, _sz, _vp, _sz, _sz, _sz, _vp]),
     "gs_fill_f32": (C.c_int, [_vp, _i64, _f, _vp]),
     "gs_probe_copy": (C.c_int, [_vp, _vp, _sz, _vp]),
@@ -237,6 +239,7 @@ class Gaussians:
     quats: torch.Tensor  # (4, N)
     opacity_logits: torch.Tensor  # (N,)
     sh: torch.Tensor  # ((d+1)^2, 3, N)
+    filter3d: Optional[torch.Tensor] = None  # (N,) 3D smoothing-filter variance, or None
 
     @property
     def n(self):
@@ -256,7 +259,9 @@ class Gaussians:
         _require(self.quats, torch.float32, (4, n), "quats")
         _require(self.opacity_logits, torch.float32, (n,), "opacity_logits")
         _require(self.sh, torch.float32, ((d + 1) ** 2, 3, n), "sh")
-        return _Gauss(n, d, *[t.data_ptr() for t in self.tensors()])
+        if self.filter3d is not None:
+            _require(self.filter3d, torch.float32, (n,), "filter3d")
+        return _Gauss(n, d, *[t.data_ptr() for t in self.tensors()], _ptr(self.filter3d))
 
     def zeros_like(self):
         return Gaussians(*[torch.zeros_like(t) for t in self.tensors()])
@@ -557,14 +562,16 @@ def project_bwd_views_workspace(n: int, n_views: int) -> int:
 
 
 def project_bwd_views(views, g: Gaussians, grads: Gaussians, params: Params = Params(),
-                      ws: Optional[torch.Tensor] = None):
+                      ws: Optional[torch.Tensor] = None, store: bool = False):
     """Chains every view's pair gradients to the parameters (summed over the
-    views into grads) and to each view's pose gradient."""
+    views into grads: added, or with store=True written, no clearing needed)
+    and to each view's pose gradient."""
     need = project_bwd_views_workspace(g.n, len(views))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.means.device)
-    _check(_lib.gs_project_bwd_views(len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()),
-                                     C.byref(grads.c()), ws.data_ptr(), ws.numel(), _stream()))
+    fn = _lib.gs_project_bwd_views_store if store else _lib.gs_project_bwd_views
+    _check(fn(len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()), C.byref(grads.c()), ws.data_ptr(),
+              ws.numel(), _stream()))
     return grads
 
 
@@ -1214,3 +1221,17 @@ def fill_(t: torch.Tensor, value: float):
     """gs_fill_f32 over a contiguous float32 device tensor."""
     assert t.dtype == torch.float32 and t.is_contiguous()
     _check(_lib.gs_fill_f32(t.data_ptr(), t.numel(), value, _stream()))
+
+
+def filter3d_update(means: torch.Tensor, cams, nu_max: torch.Tensor, filter3d: Optional[torch.Tensor] = None,
+                    guard: float = 1.15, s_f: float = 0.2):
+    """gs_filter3d_update: nu_max = max(nu_max, the cameras' sampling rates);
+    filter3d = (s_f / nu_max)^2 (0 where no camera has seen the Gaussian)."""
+    n = means.shape[1]
+    _require(nu_max, torch.float32, (n,), "nu_max")
+    arr = (_Camera * max(len(cams), 1))()
+    for k, c in enumerate(cams):
+        arr[k] = c.c()
+    _check(_lib.gs_filter3d_update(means.data_ptr(), n, len(cams), arr, guard, s_f, nu_max.data_ptr(),
+                                   _ptr(filter3d), _stream()))
+    return filter3d

@@ -641,6 +641,14 @@ def test_benchmark_configuration_window_sampled(mode):
         views[7] = synth.View(w, h, np.float32(fx), np.float32(fy), np.float32(cx), np.float32(cy), v.R, v.t)
     g = gc.gpu_gauss(scene)
     n = scene.n
+    og = orc.Gaussians.from_scene(scene)
+    if bench:  # the 3D smoothing filter from the window's keyframes and the new one, as the benchmark sets it
+        nu = torch.zeros(n, dtype=torch.float32, device="cuda")
+        g.filter3d = torch.empty(n, dtype=torch.float32, device="cuda")
+        gs.filter3d_update(g.means, [gc.gpu_camera(v) for v in synth.trajectory(seed, 9, 1920, 1080)], nu, g.filter3d)
+        f3 = g.filter3d.cpu().numpy().astype(np.float64)
+        ls2, a2 = oms.apply_filter3d(scene.log_scales, scene.opacity_logits, f3)
+        og = orc.Gaussians(scene.means, ls2, scene.quats, a2, scene.sh, scene.sh_degree)
     crops = [(200 + 190 * k, 120 + 100 * k, 40, 40) for k in range(7)] + [(200, 120, 40, 40)]
     keys = ("means", "log_scales", "quats", "opacity_logits", "sh")
     sorter = gs.BinSorter(0)
@@ -664,7 +672,6 @@ def test_benchmark_configuration_window_sampled(mode):
     for k, (v, vw) in enumerate(zip(views, vs)):
         full = (v.height, v.width)
         ocam = orc.Camera.from_view(v, eps2d=params.eps2d, mip_filter=params.mip_filter)
-        og = orc.Gaussians.from_scene(scene)
         op = orc.project(ocam, og)
         ref = orc.render(ocam, op, crop=crops[k], flag_rel=FLAG_REL)
         gi, gd, ga = gc.flagged_upstream(crops[k][2:][::-1], ref["flags"], 60 + k)
@@ -688,6 +695,9 @@ def test_benchmark_configuration_window_sampled(mode):
                 total[key] += rg[key]
         del rg, op
     assert flagged <= 2e-3 * 8 * 40 * 40, flagged
+    if bench:  # through the 3D filter to the log-scales and logits
+        total["log_scales"], total["opacity_logits"] = oms.filter3d_vjp(
+            scene.log_scales, scene.opacity_logits, f3, total["log_scales"], total["opacity_logits"])
     grads = g.zeros_like()
     gs.project_bwd_views(vs, g, grads, params)
     torch.cuda.synchronize()
