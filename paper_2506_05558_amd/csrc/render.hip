@@ -62,7 +62,6 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
                                             Stage<NB> &S, uint32_t *gid_out) {
   const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
   const uint32_t j = base + t;
-  const float l2min = __builtin_amdgcn_logf(a.alpha_min);
   unsigned mask = 0;
   if (t < NB && j < end) {
     const uint32_t gid = a.values[j];
@@ -85,45 +84,10 @@ __device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, 
       cx |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
       cy |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << c;
     }
-    unsigned box = 0;
 #pragma unroll
     for (int bl = 0; bl < kBlocks; ++bl) {
       const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
-      box |= ((cx >> bx) & (cy >> by) & 1u) << bl;
-    }
-    // Of the sub-blocks the box meets, keep those the support ellipse meets:
-    // with q(d) = a dx^2 + b dx dy + c dy^2 = -(log2-domain exponent) the
-    // pixel test keeps d iff q(d) <= Q = log2 o - log2 alpha_min, so a block
-    // whose rectangle of pixel centres has min q > Q (plus a margin far above
-    // the FP32 rounding of the per-pixel evaluation) holds no kept pixel.  The
-    // minimum of the convex q over the rectangle is 0 if the mean lies inside,
-    // else it is on one of the four edges (a 1D quadratic, clamped).
-    const float qa = __fmul_rn(0.5f * kLog2e, r1.x), qb = __fmul_rn(kLog2e, r1.y),
-                qc = __fmul_rn(0.5f * kLog2e, r1.z);
-    const float Q = __fsub_rn(__builtin_amdgcn_logf(r1.w), l2min);
-    const float hy_x = 0.5f * qb / qc, hx_y = 0.5f * qb / qa;  // argmin offsets per unit of the fixed coordinate
-    while (box) {
-      const int bl = __builtin_ctz(box);
-      box &= box - 1;
-      const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
-      const float X0 = 4.0f * bx - mx, X1 = X0 + 3.0f, Y0 = 4.0f * by - my, Y1 = Y0 + 3.0f;
-      bool keep = X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f;
-      if (!keep) {
-        float qmin = INFINITY, mag = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool vert = e < 2;  // an edge of fixed x (else of fixed y)
-          const float F = vert ? (e == 0 ? X0 : X1) : (e == 2 ? Y0 : Y1);
-          const float v = vert ? fminf(fmaxf(-hy_x * F, Y0), Y1) : fminf(fmaxf(-hx_y * F, X0), X1);
-          const float dx = vert ? F : v, dy = vert ? v : F;
-          const float q = qa * dx * dx + qb * dx * dy + qc * dy * dy;
-          const float m = qa * dx * dx + fabsf(qb * dx * dy) + qc * dy * dy;
-          mag = q < qmin ? m : mag;
-          qmin = fminf(q, qmin);
-        }
-        keep = !(qmin - 1e-4f * mag - 1e-4f > Q);  // a NaN keeps the block
-      }
-      mask |= (unsigned)keep << bl;
+      mask |= ((cx >> bx) & (cy >> by) & 1u) << bl;
     }
   }
   const uint64_t lt = lanemask_lt();
@@ -218,36 +182,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
     const int cnt = S.cnt[0][blk] + S.cnt[1][blk] + S.cnt[2][blk] + S.cnt[3][blk];
     if (ballot(fpx != kFar) == 0) continue;
     const int idx0 = (int)(base - s);
-    // returns true once every pixel of the wave has stopped
-    auto body = [&](int k, const float4 &B, float lg, bool take) -> bool {
-      const float alpha = clamp_alpha(exp2_fast(lg), a.alpha_max);
-      const float2 C = S.c[k];
-      const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
-      const bool stop = (take ? Tn : 1.0f) < a.t_min;
-      const bool comp = take && !stop;
-      const float wgt = comp ? __fmul_rn(alpha, T) : 0.0f;
-      c0 = __fmaf_rn(B.w, wgt, c0);
-      c1 = __fmaf_rn(C.x, wgt, c1);
-      c2 = __fmaf_rn(C.y, wgt, c2);
-      D = __fmaf_rn(B.z, wgt, D);
-      T = comp ? Tn : T;
-      last = comp ? idx0 + k + 1 : last;
-      if (STATS) {
-        nsup += take ? 1 : 0;
-        ncomp += comp ? 1 : 0;
-        ntile = stop ? idx0 + k + 1 : ntile;
-      }
-      if (ballot(stop) != 0) {
-        fpx = stop ? kFar : fpx;
-        if (ballot(fpx != kFar) == 0) return true;
-      }
-      return false;
-    };
     // the four sub-blocks of a wave walk their own lists side by side, four
-    // entries per turn (all exponents before the first body); a sub-block
-    // whose list is done or whose pixels have all stopped sits out
-    bool all_done = false;
-    for (int i = 0; !all_done; i += 4) {
+    // entries per turn: all exponents first, then the four compositing steps
+    // predicated per lane (a pixel that stops takes nothing more), and one
+    // ballot per turn for the stops; a sub-block whose list is done or whose
+    // pixels have all stopped sits out
+    for (int i = 0;; i += 4) {
       const bool act = i < cnt && fpx != kFar;
       if (ballot(act) == 0) break;
       const int qd = act ? *(const int *)&S.list[blk][i] : 0;
@@ -261,15 +201,34 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
         BB[j] = S.b[kk[j]];
         lg[j] = __fadd_rn(splat_s2(A.z, A.w, BB[j].x, __fsub_rn(fpx, A.x), __fsub_rn(fpy, A.y)), BB[j].y);
       }
+      bool stopped = false;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool live = act && i + j < cnt && fpx != kFar;  // a pixel that stopped earlier takes nothing more
+        const bool live = act && i + j < cnt && !stopped;
         if (STATS) nev += live ? 1 : 0;
-        const bool tk = live && lg[j] >= l2min;
-        if (ballot(tk) != 0 && body(kk[j], BB[j], lg[j], tk)) {
-          all_done = true;
-          break;
+        const bool take = live && lg[j] >= l2min;
+        const float alpha = clamp_alpha(exp2_fast(lg[j]), a.alpha_max);
+        const float2 C = S.c[kk[j]];
+        const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
+        const bool stop = take && Tn < a.t_min;
+        const bool comp = take && !stop;
+        const float wgt = comp ? __fmul_rn(alpha, T) : 0.0f;
+        c0 = __fmaf_rn(BB[j].w, wgt, c0);
+        c1 = __fmaf_rn(C.x, wgt, c1);
+        c2 = __fmaf_rn(C.y, wgt, c2);
+        D = __fmaf_rn(BB[j].z, wgt, D);
+        T = comp ? Tn : T;
+        last = comp ? idx0 + kk[j] + 1 : last;
+        if (STATS) {
+          nsup += take ? 1 : 0;
+          ncomp += comp ? 1 : 0;
+          ntile = stop ? idx0 + kk[j] + 1 : ntile;
         }
+        stopped = stopped || stop;
+      }
+      if (ballot(stopped) != 0) {
+        fpx = stopped ? kFar : fpx;
+        if (ballot(fpx != kFar) == 0) break;
       }
     }
   }
@@ -591,7 +550,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       for (int j = 0; j < 4; ++j) {
         const bool live = act && i + j < cnt;
         const bool tk = live && idx0 + kk[j] < ncon && lg[j] >= l2min;
-        if (ballot(tk) != 0) body(kk[j], BB[j], lg[j], tk, live);
+        body(kk[j], BB[j], lg[j], tk, live);  // every list entry takes a chunk slot
       }
     }
     if (nslots > 0) bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);

@@ -358,7 +358,6 @@ class LargeScene:
         self.step_count += 1
         k = self.step_count
         views = self.wviews[:len(win)]
-        gsmi.zero_(self.gflat)
         gsmi.zero_(self.d_pose)
         gsmi.zero_(self.dx6)
         gsmi.zero_(self.visible)
@@ -384,7 +383,7 @@ class LargeScene:
                                self.fwd_ws, self.params, out=self.frame)
             gsmi.render_bwd_pairs(vw.cam, vw.proj, b, self.frame, self.g_img, vw.pair_grad, params=self.params)
             gsmi.mark_visible(vw.proj, self.visible)
-        gsmi.project_bwd_views(views, pool.g, self.grads, self.params, ws=self.pbwd_ws)
+        gsmi.project_bwd_views(views, pool.g, self.grads, self.params, ws=self.pbwd_ws, store=True)
         torch.maximum(self.n_pairs_max[:len(win)], self.n_pairs[:len(win)], out=self.n_pairs_max[:len(win)])
         gsmi.pose_6d_bwd(self.x6, self.d_pose, self.dx6)
         g, m1, m2, gr = pool.g, pool.m1, pool.m2, self.grads
@@ -558,8 +557,11 @@ def run(cfg: Config = Config(), train_frames=None, eval_frames=None, conv_steps:
         mlp_steps: int = 3000, log=print):
     """The large-scene workload; returns its report."""
     from . import spawn_study
-    train_frames = list(range(20, cfg.frames // 2, 10)) if train_frames is None else train_frames
-    eval_frames = list(range(cfg.frames // 2 + 10, cfg.frames, 20)) if eval_frames is None else eval_frames
+    half = cfg.frames // 2
+    if train_frames is None:  # keyframes 20, 30, ..., 90 of 200
+        train_frames = list(range(min(20, cfg.frames // 4), half, max(1, cfg.frames // 20)))
+    if eval_frames is None:  # keyframes 110, 130, ..., 190 of 200
+        eval_frames = list(range(half + max(1, cfg.frames // 20), cfg.frames, max(1, cfg.frames // 10)))
     ls = LargeScene(cfg, log=log)
     W, H = cfg.width, cfg.height
     X, Y = [], []
@@ -569,7 +571,7 @@ def run(cfg: Config = Config(), train_frames=None, eval_frames=None, conv_steps:
     resident_max = 0
     arms = None
     for f in range(cfg.frames):
-        if f == cfg.frames // 2:
+        if f == half and X:
             # the spawn network from the pairs this run logged; learned spawn-init from here on
             Xc, Yc = torch.cat(X), torch.cat(Y)
             theta, tinfo = spawn_study.train(Xc, Yc, mlp_steps, 4096, 1e-3, log=log)

@@ -1,0 +1,62 @@
+"""The store form of the window's projection adjoint (gs_project_bwd_views_store)
+equals clearing the gradients and adding (gs_project_bwd_views) bit for bit:
+one batch of views, more than eight views (the second batch adds to the
+first's stores), stale values in the gradient planes beforehand, and no
+view at all (every gradient 0)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_05558_amd import synth
+from tests import gpu_common as gc
+
+pytestmark = pytest.mark.gpu
+
+
+def _window(gs, n_views, seed):
+    views = synth.trajectory(seed, n_views, 160, 120)
+    scene = synth.window_scene(seed, views, 1500, 2)
+    g = gc.gpu_gauss(scene)
+    params = gs.Params(eps2d=0.1, mip_filter=1)
+    vs = []
+    for k, v in enumerate(views):
+        cam = gc.gpu_camera(v)
+        vw = gs.View(cam, gs.alloc_projected(g.n), first_slot=torch.empty(g.n, dtype=torch.int32, device="cuda"),
+                     dL_dpose=torch.zeros(12, dtype=torch.float64, device="cuda"))
+        vs.append(vw)
+    gs.project_views(vs, g, params)
+    for k, vw in enumerate(vs):
+        b = gs.BinSorter(0)(vw.cam, vw.proj, first_slot=vw.first_slot)
+        fr = gs.render_fwd(vw.cam, vw.proj, b, params)
+        gi = torch.tensor(np.random.default_rng(seed + k).standard_normal((3, 120, 160)).astype(np.float32),
+                          device="cuda")
+        vw.pair_grad = torch.empty((max(b.n_instances, 1), 12), dtype=torch.float32, device="cuda")
+        gs.render_bwd_pairs(vw.cam, vw.proj, b, fr, gi, vw.pair_grad, params=params)
+    return g, vs, params
+
+
+@pytest.mark.parametrize("n_views", [3, 11])
+def test_store_equals_clear_and_add(n_views):
+    gs = gc.gpu()
+    g, vs, params = _window(gs, n_views, 70 + n_views)
+    add = g.zeros_like()
+    gs.project_bwd_views(vs, g, add, params)
+    poses_add = [vw.dL_dpose.clone() for vw in vs]
+    for vw in vs:
+        vw.dL_dpose.zero_()
+    st = gs.Gaussians(*[torch.full_like(t, 123.0) for t in g.tensors()])  # stale values
+    gs.project_bwd_views(vs, g, st, params, store=True)
+    torch.cuda.synchronize()
+    for a, b in zip(add.tensors(), st.tensors()):
+        assert torch.equal(a, b)
+    for vw, p in zip(vs, poses_add):
+        assert torch.equal(vw.dL_dpose, p)
+
+
+def test_store_with_no_view_clears():
+    gs = gc.gpu()
+    g, vs, params = _window(gs, 2, 90)
+    st = gs.Gaussians(*[torch.full_like(t, -5.0) for t in g.tensors()])
+    gs.project_bwd_views([], g, st, params, store=True)
+    torch.cuda.synchronize()
+    assert all(int(torch.count_nonzero(t)) == 0 for t in st.tensors())
