@@ -303,3 +303,15 @@ def bootstrap_ba(uv, W, H, iters=200, delta=1.0, lam0=LAMBDA0, nu=NU, mad_from=N
         else:
             lam = lam * nu
     return dict(f=f, R=Rs, t=ts, X=X, lam=lam)
+
+
+def bootstrap_cost(f, poses, X, uv, W, H, delta=1.0):
+    """The bootstrapping objective at a solution: the Huber cost of the
+    observations the median + 4 MAD rule keeps there.  poses [V][12] (R
+    row-major, t), X [3][P], uv [V][2][P]."""
+    poses = np.asarray(poses, np.float64)
+    Rs = [poses[v, :9].reshape(3, 3) for v in range(poses.shape[0])]
+    ts = [poses[v, 9:] for v in range(poses.shape[0])]
+    r, _ = ba_residuals(float(f), Rs, ts, np.asarray(X, np.float64), np.asarray(uv, np.float64), W / 2.0, H / 2.0)
+    e = np.sqrt((r * r).sum(1)).ravel()
+    return float((huber(e, delta) * mad_keep(e)).sum())

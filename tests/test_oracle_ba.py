@@ -167,3 +167,29 @@ def test_bootstrap_recovers_focal_poses_and_structure():
         ang = np.degrees(np.arccos(np.clip((np.trace(out["R"][v].T @ Rs[v]) - 1) / 2, -1, 1)))
         assert ang < 0.05 and np.allclose(out["t"][v] / s, ts[v], atol=2e-3)
     assert np.allclose(out["X"] / s, X, atol=5e-3)
+
+
+def test_bootstrap_cost_closed_forms():
+    """Zero at the exact solution; with residuals planted on a known set, the
+    Huber sum of those the median + 4 MAD rule keeps."""
+    rng = np.random.default_rng(41)
+    V, P, W, H, f = 3, 40, 320, 240, 300.0
+    Rs = [np.eye(3)] + [ba.so3_exp(rng.standard_normal(3) * 0.02) for _ in range(V - 1)]
+    ts = [np.zeros(3)] + [np.array([0.2 * v, 0.0, 0.0]) for v in range(1, V)]
+    X = np.stack([rng.uniform(-1, 1, P), rng.uniform(-1, 1, P), rng.uniform(3, 5, P)])
+    uv = np.stack([ba.project(Rs[v], ts[v], X, f, f, W / 2, H / 2)[0] for v in range(V)])
+    poses = np.stack([np.concatenate([Rs[v].reshape(9), ts[v]]) for v in range(V)])
+    assert ba.bootstrap_cost(f, poses, X, uv, W, H) < 1e-18
+    # planted errors along u (view-major order): 58 of 0.25 px, 59 of 0.75 px, 3 of 50 px; the median is
+    # 0.75, the MAD 0.5, so the rule keeps errors up to 2.75 and drops the three large ones
+    shift = np.array([0.25] * 58 + [0.75] * 59 + [50.0] * 3)
+    rng.shuffle(shift)
+    uv2 = uv.copy()
+    uv2[:, 0, :] -= shift.reshape(V, P)
+    c = ba.bootstrap_cost(f, poses, X, uv2, W, H)
+    assert abs(c - (58 * 0.5 * 0.25 ** 2 + 59 * 0.5 * 0.75 ** 2)) < 1e-9
+    # beyond delta = 1 the Huber cost is delta (e - delta / 2): all errors 3 px, all kept (MAD 0 up to rounding
+    # would reject some, so the errors are spread: 3 and 4 px alternately, median 3.5, MAD 0.5)
+    uv3 = uv.copy()
+    uv3[:, 0, :] -= np.where(np.arange(V * P) % 2 == 0, 3.0, 4.0).reshape(V, P)
+    assert abs(ba.bootstrap_cost(f, poses, X, uv3, W, H) - (V * P // 2) * (2.5 + 3.5)) < 1e-9
