@@ -83,9 +83,8 @@ def step_roofline(n, views, pixels, per_view, iters, spawn_k, sh_deg, ms_step):
         k["lane_ops"] += ops * times
         k["t_roof_ms"] += t * times
 
-    # the joint iterations
-    add("zero_gradients", 4 * par * n, times=iters)
-    add("project", n * (pb + views * 48), times=iters)
+    # the joint iterations (the projection adjoint stores every gradient: nothing is cleared first)
+    add("project", n * (pb + views * 76), times=iters)
     add("bin_scan_duplicate", views * (8 * n + 12 * M), times=iters)
     add("radix_sort", views * radix_passes * 24 * M, times=iters)
     add("tile_ranges", views * 8 * M, times=iters)
@@ -95,9 +94,9 @@ def step_roofline(n, views, pixels, per_view, iters, spawn_k, sh_deg, ms_step):
     # adjoint: 40 B per instance, 20 B per pixel in, 40 B of 2D gradients per visible Gaussian out
     add("render_bwd", 40 * M + 20 * pixels + 40 * vis, comp * BWD_COMP, times=iters * views)
     add("mark_visible", views * 8 * n, times=iters)
-    # projection adjoint over the window: parameters, per view the 40 B 2D gradients, gradients
-    # read and written once
-    add("project_bwd", n * (pb + views * 40 + 2 * pb), times=iters)
+    # projection adjoint over the window: parameters read, per view the 40 B 2D gradients, the
+    # gradients written once
+    add("project_bwd", n * (pb + views * 40 + pb), times=iters)
     add("adam", 28 * par * vis, times=iters)
     add("lr_decay", 12 * n, times=iters)
     # the spawn step of the new frame: project + bin + render it, LoG probability on two
@@ -529,11 +528,11 @@ def main():
                         traffic=None)
         # one launch of each covers the 8 views: parameters read once (236 B), per view a
         # 76 B record + half-widths + tile count written; the adjoint reads parameters and per
-        # view 24 B (tile count, first slot, colour record) + 48 B per pair, and updates the
+        # view 24 B (tile count, first slot, colour record) + 48 B per pair, and writes the
         # 236 B of gradients once
         per_launch_bytes = {
             "project": n * (236 + N_VIEWS * 76),
-            "project_bwd": n * (236 + 2 * 236 + N_VIEWS * 24) + N_VIEWS * M * 48,
+            "project_bwd": n * (236 + 236 + N_VIEWS * 24) + N_VIEWS * M * 48,
         }.get(name)
         if per_launch_bytes is None:
             return None
