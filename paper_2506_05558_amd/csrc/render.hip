@@ -51,62 +51,69 @@ struct Stage {
   float4 a[NB];               // mean x, y relative to the tile origin, ca, cb
   float4 b[NB];               // cc, log2 opacity, depth, colour r
   float2 c[NB];               // colour g, b
+  uint8_t box[NB];            // the 4-pixel columns (bits 0-3) and rows (bits 4-7) the support box meets
   uint8_t list[kBlocks][NB];  // per cull block: batch entries whose box meets it, in order
-  int cnt[4][kBlocks];        // [entry wave][cull block] entries
 };
 
-// Stages entries [base, end) of the tile list (at most NB) and builds the
-// per-block lists.  Called by all 256 lanes; contains two barriers.
+// The tile-list value (Gaussian index) lane t stages for the batch at base,
+// loaded one batch ahead so that its latency overlaps the walk.
 template <int NB>
-__device__ __forceinline__ void stage_batch(const RenderArgs &a, uint32_t base, uint32_t end, float ox, float oy,
-                                            Stage<NB> &S, uint32_t *gid_out) {
-  const int t = threadIdx.x, lane = t & 63, ew = t >> 6;
+__device__ __forceinline__ uint32_t batch_gid(const RenderArgs &a, uint32_t base, uint32_t end) {
+  const uint32_t j = base + threadIdx.x;
+  return threadIdx.x < NB && j < end ? a.values[j] : 0u;
+}
+
+// Stages entries [base, end) of the tile list (at most NB; lane t's value
+// gid from batch_gid), then each wave builds the lists of its own four
+// sub-blocks (read only by that wave).  Called by all 256 lanes; contains
+// one barrier.  Returns the length of the calling lane's sub-block list.
+template <int NB>
+__device__ __forceinline__ int stage_batch(const RenderArgs &a, uint32_t base, uint32_t end, float ox, float oy,
+                                           Stage<NB> &S, uint32_t gid) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4;
   const uint32_t j = base + t;
-  unsigned mask = 0;
-  if (t < NB && j < end) {
-    const uint32_t gid = a.values[j];
-    const float4 *r = (const float4 *)(a.rec + (size_t)gid * GS_REC_FLOATS);
-    const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-    // integer part minus tile origin is exact; one rounding adds the fraction
-    const float mx = __fadd_rn(__fsub_rn(r0.x, ox), r0.z);
-    const float my = __fadd_rn(__fsub_rn(r0.y, oy), r0.w);
-    S.a[t] = make_float4(mx, my, __fmul_rn(-0.5f * kLog2e, r1.x), __fmul_rn(-kLog2e, r1.y));
-    S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), __builtin_amdgcn_logf(r1.w), r2.w, r2.x);
-    S.c[t] = make_float2(r2.y, r2.z);
-    if (gid_out) gid_out[t] = gid;
-    // support box, widened so that FP32 rounding can never cull a pixel the
-    // per-pixel test would accept
-    const float hx = r3.x * (1.0f + 1e-4f) + 1e-3f, hy = r3.y * (1.0f + 1e-4f) + 1e-3f;
-    // columns / rows of 4 pixels met by the box, then their products
-    unsigned cx = 0, cy = 0;
+  if (t < NB) {
+    unsigned box = 0;  // an entry past the end meets nothing
+    if (j < end) {
+      const float4 *r = (const float4 *)(a.rec + (size_t)gid * GS_REC_FLOATS);
+      const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+      // integer part minus tile origin is exact; one rounding adds the fraction
+      const float mx = __fadd_rn(__fsub_rn(r0.x, ox), r0.z);
+      const float my = __fadd_rn(__fsub_rn(r0.y, oy), r0.w);
+      S.a[t] = make_float4(mx, my, __fmul_rn(-0.5f * kLog2e, r1.x), __fmul_rn(-kLog2e, r1.y));
+      S.b[t] = make_float4(__fmul_rn(-0.5f * kLog2e, r1.z), __builtin_amdgcn_logf(r1.w), r2.w, r2.x);
+      S.c[t] = make_float2(r2.y, r2.z);
+      // support box, widened so that FP32 rounding can never cull a pixel the
+      // per-pixel test would accept
+      const float hx = r3.x * (1.0f + 1e-4f) + 1e-3f, hy = r3.y * (1.0f + 1e-4f) + 1e-3f;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      cx |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
-      cy |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << c;
+      for (int c = 0; c < 4; ++c) {
+        box |= (unsigned)(mx - hx <= 4.0f * c + 3.0f && mx + hx >= 4.0f * c) << c;
+        box |= (unsigned)(my - hy <= 4.0f * c + 3.0f && my + hy >= 4.0f * c) << (4 + c);
+      }
     }
-#pragma unroll
-    for (int bl = 0; bl < kBlocks; ++bl) {
-      const int bx = 2 * ((bl >> 2) & 1) + (bl & 1), by = 2 * (bl >> 3) + ((bl >> 1) & 1);
-      mask |= ((cx >> bx) & (cy >> by) & 1u) << bl;
-    }
+    S.box[t] = (uint8_t)box;
   }
+  __syncthreads();
+  // wave w's sub-blocks g = 0..3 lie in the 4-pixel columns 2 (w & 1) + (g & 1)
+  // and rows 2 (w >> 1) + (g >> 1); entries in ascending order, 64 per round
+  const int sx = 2 * (w & 1), sy = 4 + 2 * (w >> 1);
   const uint64_t lt = lanemask_lt();
-  int rank[kBlocks];
+  int n[4] = {0, 0, 0, 0};  // wave-uniform list lengths
 #pragma unroll
-  for (int q = 0; q < kBlocks; ++q) {
-    const uint64_t bal = ballot((mask >> q) & 1u);
-    rank[q] = __popcll(bal & lt);
-    if (lane == 0) S.cnt[ew][q] = __popcll(bal);
-  }
-  __syncthreads();
+  for (int r = 0; r < (NB + 63) / 64; ++r) {
+    const int k = r * 64 + lane;
+    const unsigned bx = k < NB ? S.box[k] : 0u;
+    const unsigned cm = (bx >> sx) & 3u, rm = (bx >> sy) & 3u;
 #pragma unroll
-  for (int q = 0; q < kBlocks; ++q) {
-    if ((mask >> q) & 1u) {
-      const int off = rank[q] + (ew > 0 ? S.cnt[0][q] : 0) + (ew > 1 ? S.cnt[1][q] : 0) + (ew > 2 ? S.cnt[2][q] : 0);
-      S.list[q][off] = (uint8_t)t;
+    for (int q = 0; q < 4; ++q) {
+      const bool in = ((cm >> (q & 1)) & (rm >> (q >> 1)) & 1u) != 0;
+      const uint64_t bal = ballot(in);
+      if (in) S.list[4 * w + q][n[q] + __popcll(bal & lt)] = (uint8_t)k;
+      n[q] += __popcll(bal);
     }
   }
-  __syncthreads();
+  return g == 0 ? n[0] : g == 1 ? n[1] : g == 2 ? n[2] : n[3];
 }
 
 // log2-domain exponent of the 2D Gaussian at offset (dx, dy).
@@ -155,7 +162,7 @@ struct FwdOut {
 // LOSS: the L1 photometric loss is formed in the epilogue (the gradient
 // and the tile's partial sums) while the pixel's colour is in registers.
 template <bool STATS, bool LOSS>
-__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(STATS ? 1 : 8))) void k_render_fwd(RenderArgs a, FwdOut o) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;  // uniform over the workgroup
   const int w = threadIdx.x >> 6;
@@ -175,11 +182,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
   int ntile = (int)(e - s);  // tile-list entries up to and including the stop
   const int blk = w * 4 + (threadIdx.x & 63) / 16;  // this lane's 4x4 cull block
 
+  uint32_t gid = batch_gid<kBatch>(a, s, e);
   for (uint32_t base = s; base < e; base += kBatch) {
     if (__syncthreads_count(fpx == kFar) == kThreads) break;
-    stage_batch(a, base, e, ox, oy, S, nullptr);
     // the length of this lane's sub-block list (the same over its 16 lanes)
-    const int cnt = S.cnt[0][blk] + S.cnt[1][blk] + S.cnt[2][blk] + S.cnt[3][blk];
+    const int cnt = stage_batch(a, base, e, ox, oy, S, gid);
+    gid = batch_gid<kBatch>(a, base + kBatch, e);
     if (ballot(fpx != kFar) == 0) continue;
     const int idx0 = (int)(base - s);
     // the four sub-blocks of a wave walk their own lists side by side, four
@@ -187,31 +195,37 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
     // predicated per lane (a pixel that stops takes nothing more), and one
     // ballot per turn for the stops; a sub-block whose list is done or whose
     // pixels have all stopped sits out
+    // four list entries per 32-bit read, the next turn's read issued a turn ahead
+    int qn = cnt > 0 ? *(const int *)&S.list[blk][0] : 0;
     for (int i = 0;; i += 4) {
       const bool act = i < cnt && fpx != kFar;
       if (ballot(act) == 0) break;
-      const int qd = act ? *(const int *)&S.list[blk][i] : 0;
+      const int qd = qn;
+      qn = i + 4 < cnt ? *(const int *)&S.list[blk][i + 4] : 0;
       int kk[4];
       float4 BB[4];
+      float2 CC[4];
       float lg[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         kk[j] = i + j < cnt ? (qd >> (8 * j)) & 255 : (qd & 255);
         const float4 A = S.a[kk[j]];
         BB[j] = S.b[kk[j]];
+        CC[j] = S.c[kk[j]];
         lg[j] = __fadd_rn(splat_s2(A.z, A.w, BB[j].x, __fsub_rn(fpx, A.x), __fsub_rn(fpy, A.y)), BB[j].y);
       }
       bool stopped = false;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool live = act && i + j < cnt && !stopped;
+        // bitwise conditions: no branches inside a turn
+        const bool live = act & (i + j < cnt) & !stopped;
         if (STATS) nev += live ? 1 : 0;
-        const bool take = live && lg[j] >= l2min;
+        const bool take = live & (lg[j] >= l2min);
         const float alpha = clamp_alpha(exp2_fast(lg[j]), a.alpha_max);
-        const float2 C = S.c[kk[j]];
+        const float2 C = CC[j];
         const float Tn = __fmul_rn(T, __fsub_rn(1.0f, alpha));
-        const bool stop = take && Tn < a.t_min;
-        const bool comp = take && !stop;
+        const bool stop = take & (Tn < a.t_min);
+        const bool comp = take & !stop;
         const float wgt = comp ? __fmul_rn(alpha, T) : 0.0f;
         c0 = __fmaf_rn(BB[j].w, wgt, c0);
         c1 = __fmaf_rn(C.x, wgt, c1);
@@ -224,7 +238,7 @@ __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs a, FwdOut o) {
           ncomp += comp ? 1 : 0;
           ntile = stop ? idx0 + kk[j] + 1 : ntile;
         }
-        stopped = stopped || stop;
+        stopped = stopped | stop;
       }
       if (ballot(stopped) != 0) {
         fpx = stopped ? kFar : fpx;
@@ -341,12 +355,11 @@ __device__ __forceinline__ void wave_lds_fence() {
 // (lane = sub-block g, slot e, half h) reads [e][(16 g + 8 h + i) ^ e], one
 // lane per bank.
 struct BwdShared {
-  float gs[4][kChunk][64];     // per wave, chunk slot, lane ^ slot: d L / d s  (natural-log exponent)
-  float wt[4][kChunk][64];     // per wave, chunk slot, lane ^ slot: blending weight alpha T
-  uint8_t slot[4][kChunk][4];  // per wave, chunk slot, sub-block: its batch entry (kNoEntry: none)
+  float gs[4][kChunk][64];  // per wave, chunk slot, lane ^ slot: d L / d s  (natural-log exponent)
+  float wt[4][kChunk][64];  // per wave, chunk slot, lane ^ slot: blending weight alpha T
 };
 
-// Phase 2 of the adjoint for one wave.  A chunk slot holds one entry per
+// Phase 2 of the adjoint for one wave: the sums of a chunk.  A chunk slot holds one entry per
 // 4x4 sub-block (the four sub-blocks of a wave walk their own lists), so
 // the lanes are (sub-block g = lane / 16, slot e, half h = lane % 2); each
 // lane sums the 8 pixels of rows 2 h, 2 h + 1 of its sub-block, the two
@@ -356,24 +369,33 @@ struct BwdShared {
 //   opacity gradients are linear in these: d s / d mean = (A dx + B dy,
 //   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
 //   (the colour and depth gradients).
+// The lane's entry k and its mean (mx, my) were picked up in phase 1, when
+// its sub-block walked slot e (kNoEntry: the slot holds none).
 // Two sub-blocks of a wave may hold the same entry, so the four sub-blocks
-// add in turn (a read-modify-write per round, rounds kept in order); an
-// entry occurs at most once per sub-block list, so no two lanes of a round
-// share it, and no other wave writes this accumulator.
+// add in turn (bwd_commit: a read-modify-write per round, rounds kept in
+// order); an entry occurs at most once per sub-block list, so no two lanes of
+// a round share it, and no other wave writes this accumulator.
+// The values a lane adds in the five rounds of bwd_commit (round r: value
+// (r + g) mod 5 of the lane's five).
+struct Rot5 {
+  float r0, r1, r2, r3, r4;
+};
+
+__device__ __forceinline__ float pick4(int g, float a, float b, float c, float d) {
+  return g == 0 ? a : g == 1 ? b : g == 2 ? c : d;
+}
+
 template <bool DEPTH>
-__device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch> &S, BwdShared &B, int w, int nslots,
-                                           float (*acc)[kBwdBatch], const float (&Gr)[4][8]) {
+__device__ __forceinline__ Rot5 bwd_sums(BwdShared &B, int w, int k, float mx_, float my_, const float (&Gr)[4][8]) {
   constexpr int NQ = DEPTH ? 10 : 9;
   const int lane = threadIdx.x & 63, g = lane >> 4, e = (lane >> 1) & 7, h = lane & 1;
   float v[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) v[q] = 0.f;
-  const int k = e < nslots ? B.slot[w][e][g] : kNoEntry;
   if (k != kNoEntry) {
-    const float4 A = S.a[k];
     // pixel i of the lane sits at (x0 + ix, y0 + iy) from the mean, ix = i % 4, iy = i / 4
-    const float x0 = (float)((w & 1) * 8 + (g & 1) * 4) - A.x;
-    const float y0 = (float)((w >> 1) * 8 + (g >> 1) * 4 + 2 * h) - A.y;
+    const float x0 = (float)((w & 1) * 8 + (g & 1) * 4) - mx_;
+    const float y0 = (float)((w >> 1) * 8 + (g >> 1) * 4 + 2 * h) - my_;
     float m0 = 0.f, mx = 0.f, my = 0.f, mxx = 0.f, mxy = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f, sd = 0.f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -417,25 +439,68 @@ __device__ __forceinline__ void bwd_phase2(const Stage<kBwdBatch> &S, BwdShared 
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] += dpp_mov<0xb1, 0xf>(v[q]);  // quad_perm [1,0,3,2]
   // both lanes of a (sub-block, slot) hold the sums: lane h adds sums
-  // 5 h .. 5 h + 4
-  float u[5];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) u[j] = h ? (5 + j < NQ ? v[5 + j] : 0.f) : v[j];
-  float *row = &acc[5 * h][0];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (g == r && k != kNoEntry) {
-#pragma unroll
-      for (int j = 0; j < 5; ++j)
-        if (5 * h + j < NQ) row[j * kBwdBatch + k] += u[j];
-    }
-    wave_lds_fence();  // the rounds stay separate and in order
-  }
+  // 5 h .. 5 h + 4, in the order of the rounds
+  const float u0 = h ? v[5] : v[0], u1 = h ? v[6] : v[1], u2 = h ? v[7] : v[2], u3 = h ? v[8] : v[3];
+  const float u4 = h ? (NQ > 9 ? v[9] : 0.f) : v[4];
+  Rot5 o;
+  o.r0 = pick4(g, u0, u1, u2, u3);
+  o.r1 = pick4(g, u1, u2, u3, u4);
+  o.r2 = pick4(g, u2, u3, u4, u0);
+  o.r3 = pick4(g, u3, u4, u0, u1);
+  o.r4 = pick4(g, u4, u0, u1, u2);
+  return o;
 }
+
+// Adds a chunk's sums (bwd_sums: entry k, values u) to the wave's
+// accumulator in five rounds of one read-modify-write per lane: in round r
+// the lane of sub-block g adds its value (r + g) mod 5, so the four
+// sub-blocks of a round always write different rows and two lanes of a
+// round never share an address, even where sub-blocks hold the same entry.
+// The rounds are volatile accesses, kept in order (an address written in
+// one round may be read in a later one), and branch-free, so that they can
+// interleave with the arithmetic around them.  A lane with nothing to add in
+// a round reads and writes its own cell `dummy`, which no other lane touches
+// and which the caller overwrites before reading it.
+typedef __attribute__((address_space(3))) float lds_float;
+
+// One lane's part of adding a chunk's sums (bwd_sums: entry k, rotated
+// values) to the wave's accumulator, in five rounds of one read-modify-write:
+// in round r the lane of sub-block g adds its value (r + g) mod 5, so the
+// four sub-blocks of a round always write different rows and two lanes of a
+// round never share an address, even where sub-blocks hold the same entry.
+// The accesses are volatile, so the rounds stay in order (an address written
+// in one round may be read in a later one); the caller spreads them over a
+// turn's arithmetic to hide their latency.  A lane with nothing to add in a
+// round reads and writes its own cell `dummy` instead, which no other lane
+// touches and which the caller overwrites before it reads it.
+template <bool DEPTH>
+struct BwdCommit {
+  volatile lds_float *p[5];
+  float val[5];
+  __device__ __forceinline__ BwdCommit(float (*acc)[kBwdBatch], int k, const Rot5 &c, float *dummy) {
+    constexpr int NQ = DEPTH ? 10 : 9;
+    const int lane = threadIdx.x & 63, g = lane >> 4, h = lane & 1;
+    const bool has = k != kNoEntry;
+    lds_float *col = (lds_float *)&acc[5 * h][has ? k : 0];
+    lds_float *dum = (lds_float *)dummy;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+      const int q = r + g >= 5 ? r + g - 5 : r + g;
+      p[r] = has && 5 * h + q < NQ ? col + q * kBwdBatch : dum;
+    }
+    val[0] = c.r0;
+    val[1] = c.r1;
+    val[2] = c.r2;
+    val[3] = c.r3;
+    val[4] = c.r4;
+  }
+  __device__ __forceinline__ float read(int r) const { return *p[r]; }
+  __device__ __forceinline__ void write(int r, float old) const { *p[r] = old + val[r]; }
+};
 
 // DEPTH: a depth gradient is given (without one, the depth sums are skipped)
 template <bool DEPTH>
-__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEPTH ? 3 : 4))) void k_render_bwd(RenderArgs a, BwdIn bi) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= a.ntiles) return;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, g = lane >> 4, blk = w * 4 + g;
@@ -501,59 +566,97 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
   // No barrier opens a batch: lane t stages entry t and is also the lane that wrote out
   // entry t of the previous batch and cleared its accumulator column, so its own program
   // order covers those; the other lanes' accumulator writes come after the staging
-  // barriers, and the walk of the previous batch ended at the barrier before its write-out.
+  // barrier, and the walk of the previous batch (with its wave's list building) ended at
+  // the barrier before its write-out.
+  const int pe = (lane >> 1) & 7;  // this lane's phase 2 chunk slot
+  // the values and pair slots of the next batch are loaded during the walk of this one
+  uint32_t gid = batch_gid<kBwdBatch>(a, s, stop);
+  uint32_t slot = t < kBwdBatch && s + t < stop ? bi.slots[s + t] : 0u;
   for (uint32_t base = s; base < stop; base += kBwdBatch) {
-    stage_batch(a, base, stop, ox, oy, S, nullptr);
     // the length of this lane's sub-block list (the same over its 16 lanes)
-    const int cnt = S.cnt[0][blk] + S.cnt[1][blk] + S.cnt[2][blk] + S.cnt[3][blk];
+    const int cnt = stage_batch(a, base, stop, ox, oy, S, gid);
+    const uint32_t my_slot = slot;
+    gid = batch_gid<kBwdBatch>(a, base + kBwdBatch, stop);
+    slot = t < kBwdBatch && base + kBwdBatch + t < stop ? bi.slots[base + kBwdBatch + t] : 0u;
     const int idx0 = (int)(base - s);
-    int nslots = 0;
-    auto body = [&](int k, const float4 &Bv, float lg, bool take, bool live) {
-      const float raw = exp2_fast(lg);
-      const float alpha = clamp_alpha(raw, a.alpha_max);
-      const float2 C = S.c[k];
-      const float wgt = take ? __fmul_rn(alpha, T) : 0.0f;
-      const float gc = DEPTH ? G0 * Bv.w + G1 * C.x + G2 * C.y + GD * Bv.z : G0 * Bv.w + G1 * C.x + G2 * C.y;
-      GP = __fmaf_rn(wgt, gc, GP);
-      const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-      const float dalpha = T * gc + (GAT - GI + GP) * inv;
-      const bool livegrad = take && raw < a.alpha_max;  // the clamp passes no gradient
-      // row nslots, column lane ^ nslots: flat index lane ^ (65 nslots) (lane < 64, nslots < 8)
-      const int sw = lane ^ (nslots * 65);
-      (&B.gs[w][0][0])[sw] = livegrad ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
-      (&B.wt[w][0][0])[sw] = wgt;
-      if ((lane & 15) == 0) B.slot[w][nslots][g] = live ? (uint8_t)k : kNoEntry;
-      T = take ? __fmul_rn(T, __fsub_rn(1.0f, alpha)) : T;
-      if (++nslots == kChunk) {
-        bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);
-        nslots = 0;
-      }
-    };
-    // the four sub-blocks of a wave walk their own lists side by side, four
-    // entries per turn (all exponents before the first body); a sub-block
-    // whose list is done, or past the last contributor of its pixels, sits out
-    for (int i = 0;; i += 4) {
-      const int qd = i < cnt ? *(const int *)&S.list[blk][i] : 0;
+    const int nrel = ncon - idx0;  // batch entries below nrel come before this pixel's last contributor
+    // Every list entry takes a chunk slot, so a chunk is two turns.  The
+    // sums of a chunk are added to the accumulator at the start of the next
+    // (or after the walk), where the adds overlap that turn's arithmetic.
+    int ck = kNoEntry;  // the pending sums: entry and values
+    Rot5 cu = {0.f, 0.f, 0.f, 0.f, 0.f};
+    // one turn: entries i .. i + 3 of the sub-block list into slots e0 .. e0 + 3
+    // four list entries per 32-bit read, the next turn's read issued a turn ahead
+    int qn = cnt > 0 ? *(const int *)&S.list[blk][0] : 0;
+    auto turn = [&](int i, int e0, bool commit_first) -> bool {
+      const int qd = qn;
+      qn = i + 4 < cnt ? *(const int *)&S.list[blk][i + 4] : 0;
       const bool act = i < cnt && idx0 + (qd & 255) < gmax;  // lists ascend
-      if (ballot(act) == 0) break;
+      if (ballot(act) == 0) return false;
       int kk[4];
       float4 BB[4];
+      float2 CC[4];
       float lg[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         kk[j] = i + j < cnt ? (qd >> (8 * j)) & 255 : (qd & 255);
         const float4 A = S.a[kk[j]];
         BB[j] = S.b[kk[j]];
+        CC[j] = S.c[kk[j]];
         lg[j] = __fadd_rn(splat_s2(A.z, A.w, BB[j].x, __fsub_rn(fpx, A.x), __fsub_rn(fpy, A.y)), BB[j].y);
       }
+      // the pending sums: round j is read before body j and written after it, round 4 after
+      // body 3; a lane's dummy cell is the one its own body of slot 7 writes
+      const BwdCommit<DEPTH> cm(sAcc[w], commit_first ? ck : (int)kNoEntry, cu, &B.wt[w][7][lane ^ 7]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool live = act && i + j < cnt;
-        const bool tk = live && idx0 + kk[j] < ncon && lg[j] >= l2min;
-        body(kk[j], BB[j], lg[j], tk, live);  // every list entry takes a chunk slot
+        const float old = commit_first ? cm.read(j) : 0.f;
+        // bitwise conditions: no branches in a turn, so that its parts can interleave
+        const bool live = act & (i + j < cnt);
+        const bool take = live & (kk[j] < nrel) & (lg[j] >= l2min);
+        const float4 &Bv = BB[j];
+        const float raw = exp2_fast(lg[j]);
+        // alpha where the pixel takes the entry, else 0 (then the weight is 0 and T stays)
+        const float ae = take ? clamp_alpha(raw, a.alpha_max) : 0.0f;
+        const float2 C = CC[j];
+        const float wgt = __fmul_rn(ae, T);
+        const float om = __fsub_rn(1.0f, ae);
+        const float gc = DEPTH ? G0 * Bv.w + G1 * C.x + G2 * C.y + GD * Bv.z : G0 * Bv.w + G1 * C.x + G2 * C.y;
+        GP = __fmaf_rn(wgt, gc, GP);
+        const float inv = __builtin_amdgcn_rcpf(om);
+        const float dalpha = T * gc + (GAT - GI + GP) * inv;
+        const bool livegrad = take & (raw < a.alpha_max);  // the clamp passes no gradient
+        // row e0 + j, column lane ^ (e0 + j): flat index lane ^ (65 (e0 + j))
+        const int sw = lane ^ ((e0 + j) * 65);
+        (&B.gs[w][0][0])[sw] = livegrad ? dalpha * raw : 0.0f;  // d alpha / d s = alpha
+        (&B.wt[w][0][0])[sw] = wgt;
+        T = __fmul_rn(T, om);
+        if (commit_first) cm.write(j, old);
       }
+      if (commit_first) cm.write(4, cm.read(4));
+      return true;
+    };
+    for (int i = 0;; i += 8) {
+      // this lane's phase 2 entry: list position i + pe of its sub-block (every list entry
+      // takes a slot), read ahead of the two turns, and that entry's mean
+      const bool pin = i + pe < cnt;
+      const int pw = *(const int *)&S.list[blk][i + (pe & 4)];
+      const int pkk = pin ? (pw >> (8 * (pe & 3))) & 255 : 0;
+      const float2 pm = *(const float2 *)&S.a[pkk];
+      if (!turn(i, 0, true)) break;  // the previous chunk's sums are added here
+      const bool more = turn(i + 4, 4, false);
+      // a slot of a turn that did not run holds no entry; one that ran for the wave but not
+      // for this sub-block holds zeros
+      const int pk = pin && (pe < 4 || more) ? pkk : (int)kNoEntry;
+      cu = bwd_sums<DEPTH>(B, w, pk, pm.x, pm.y, Gr);
+      ck = pk;
+      if (!more) break;
     }
-    if (nslots > 0) bwd_phase2<DEPTH>(S, B, w, nslots, sAcc[w], Gr);
+    {
+      const BwdCommit<DEPTH> cm(sAcc[w], ck, cu, &B.wt[w][7][lane ^ 7]);
+#pragma unroll
+      for (int r = 0; r < 5; ++r) cm.write(r, cm.read(r));
+    }
     __syncthreads();
     // one plain store per (tile, entry): the pair's slot is owned by this tile.
     // From the sums (gs, gs dx, gs dy, gs dx^2, gs dx dy, gs dy^2, w G_c, w G_depth):
@@ -567,7 +670,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs a, BwdIn bi) {
       for (int q = 0; q < 10; ++q)
         v[q] = q < NQ ? (sAcc[0][q][t] + sAcc[1][q][t]) + (sAcc[2][q][t] + sAcc[3][q][t]) : 0.f;
       const float4 A = S.a[t], Bb = S.b[t];
-      float4 *dst = (float4 *)(bi.pair_grad + (size_t)bi.slots[base + t] * 12);
+      float4 *dst = (float4 *)(bi.pair_grad + (size_t)my_slot * 12);
       dst[0] = make_float4(-kLn2 * (2.0f * A.z * v[1] + A.w * v[2]), -kLn2 * (A.w * v[1] + 2.0f * Bb.x * v[2]),
                            -0.5f * v[3], -v[4]);
       dst[1] = make_float4(-0.5f * v[5], v[0] * exp2_fast(-Bb.y), v[6], v[7]);
