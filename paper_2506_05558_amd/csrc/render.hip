@@ -5,9 +5,10 @@
 // 16-lane groups the 4x4 sub-blocks of that quadrant.  The tile's
 // depth-ordered list is walked in batches (256 entries forward, 120 in the
 // adjoint).  Each lane gathers one 64-byte render record, converts it to
-// tile-relative form and stages it in LDS, and tests the entry's support box
-// against the 16 sub-blocks; ballots then build, per sub-block, the in-order
-// list of the batch entries whose box meets it.  The four groups of a wave
+// tile-relative form and stages it in LDS with one byte of support box (the
+// 4-pixel columns and rows it meets); after a barrier each wave builds, with
+// ballots over those bytes, the in-order lists of the batch entries whose box
+// meets each of its four sub-blocks.  The four groups of a wave
 // walk their own lists side by side (one entry per group per turn), so a
 // small Gaussian costs nothing in the sub-blocks it cannot reach.  The
 // workgroup leaves once all 256 pixels have stopped; a wave leaves its lists
