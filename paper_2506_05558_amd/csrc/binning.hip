@@ -66,13 +66,43 @@ __device__ __forceinline__ T block_excl_scan(T x, T *total) {
   return before + inc - x;
 }
 
+// The elements a scan reads: in[i] (ArrayLoad), or the binning's 64-bit
+// visibility record formed from a Gaussian's tile count (TilesLoad).
 template <class T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const T *in, int64_t count, T *partials) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+struct ArrayLoad {
+  const T *in;
+  __device__ __forceinline__ T operator()(int64_t i) const { return in[i]; }
+};
+
+// One 64-bit value per Gaussian whose exclusive prefix sum gives both its
+// position among the visible Gaussians (low word: visibility flag) and its
+// first slot (high word: tiles touched).  Neither total can carry into the
+// high word: n < 2^31 and the pair count < 2^32.
+__device__ __forceinline__ uint64_t visibility_record(int32_t t) {
+  return t > 0 ? (1ull | (uint64_t)(uint32_t)t << 32) : 0ull;
+}
+struct TilesLoad {
+  const int32_t *tiles;
+  __device__ __forceinline__ uint64_t operator()(int64_t i) const { return visibility_record(tiles[i]); }
+};
+
+// A workgroup's tile of kScanTile elements is read and written with
+// coalesced accesses (element k * kScanBlock + thread), and handed between
+// that order and the thread-contiguous order of the serial scan through LDS
+// padded by one element per 16, so that both orders are free of bank
+// conflicts.
+__device__ __forceinline__ int scan_pad(int e) { return e + (e >> 4); }
+constexpr int kScanLds = kScanTile + kScanTile / 16;
+
+template <class T, class L>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(L load, int64_t count, T *partials) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
   T sum = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < count) sum += in[base + k];
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanBlock;
+    if (i < count) sum += load(i);
+  }
   T total;
   block_excl_scan<T>(sum, &total);
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -82,10 +112,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const T *in, int64_t
 // totals before it, which every workgroup adds up itself from the (few,
 // cached) partials -- no separate spine launch.  The last workgroup also
 // writes the grand total.
-template <class T>
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, int64_t count, const T *partials,
+template <class T, class L>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(L load, T *out, int64_t count, const T *partials,
                                                            T *total) {
   __shared__ T s_off;
+  __shared__ T tile[kScanLds];
   {
     T part = 0;
     for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanBlock) part += partials[b];
@@ -95,21 +126,32 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *in, T *out, 
       s_off = all;
       if (total && blockIdx.x == gridDim.x - 1) *total = all + partials[blockIdx.x];
     }
-    __syncthreads();
   }
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int e = k * kScanBlock + threadIdx.x;
+    tile[scan_pad(e)] = base + e < count ? load(base + e) : (T)0;
+  }
+  __syncthreads();
   T v[kScanItems], sum = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    v[k] = (base + k < count) ? in[base + k] : (T)0;
+    v[k] = tile[scan_pad(threadIdx.x * kScanItems + k)];
     sum += v[k];
   }
   T tot;
   T run = s_off + block_excl_scan<T>(sum, &tot);
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < count) out[base + k] = run;
+    tile[scan_pad(threadIdx.x * kScanItems + k)] = run;
     run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int e = k * kScanBlock + threadIdx.x;
+    if (base + e < count) out[base + e] = tile[scan_pad(e)];
   }
 }
 
@@ -140,8 +182,8 @@ __device__ __forceinline__ T big_block_excl_scan(T x, T *total) {
   return before + inc - x;
 }
 
-template <class T>
-__global__ __launch_bounds__(kSmallBlock) void k_scan_small(const T *in, T *out, int64_t count, T *total) {
+template <class T, class L>
+__global__ __launch_bounds__(kSmallBlock) void k_scan_small(L load, T *out, int64_t count, T *total) {
   __shared__ T tot;
   T carry = 0;
   for (int64_t base = 0; base < count; base += (int64_t)kSmallBlock * kSmallItems) {
@@ -149,7 +191,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_scan_small(const T *in, T *out,
     T v[kSmallItems], sum = 0;
 #pragma unroll
     for (int k = 0; k < kSmallItems; ++k) {
-      v[k] = (i0 + k < count) ? in[i0 + k] : (T)0;
+      v[k] = (i0 + k < count) ? load(i0 + k) : (T)0;
       sum += v[k];
     }
     T run = carry + big_block_excl_scan<T>(sum, &tot);
@@ -336,18 +378,6 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(const uint32_t *k
 }
 
 // ------------------------------------------------------------ binning steps
-// One 64-bit value per Gaussian whose exclusive prefix sum gives both its
-// position among the visible Gaussians (low word: visibility flag) and its
-// first slot (high word: tiles touched).  Neither total can carry into the
-// high word: n < 2^31 and the pair count < 2^32.
-__global__ void k_visible_flags(const int32_t *tiles, int64_t n, uint64_t *flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const int32_t t = tiles[i];
-    flags[i] = t > 0 ? (1ull | (uint64_t)(uint32_t)t << 32) : 0ull;
-  }
-}
-
 constexpr uint32_t kNoSlot = 0xffffffffu;
 
 // Visible Gaussians in index order: depth key, index, a 16-byte record for
@@ -355,11 +385,11 @@ constexpr uint32_t kNoSlot = 0xffffffffu;
 // tx1 | ty1 << 16) and the first slot -- and the first slot itself.  A
 // Gaussian whose slots do not all fit (an asynchronous call short of
 // capacity) gets no first slot, so its adjoint reads no pair.
-__global__ void k_compact(const uint64_t *flags, const uint64_t *pos, const float *rec, const int32_t *radius,
+__global__ void k_compact(const int32_t *tiles, const uint64_t *pos, const float *rec, const int32_t *radius,
                           int64_t n, int W, int H, uint32_t capacity, uint32_t *keys, uint32_t *vals, uint4 *rect,
                           uint32_t *first_slot) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !flags[i]) return;
+  if (i >= n || tiles[i] <= 0) return;
   const uint64_t ps = pos[i];
   const uint32_t p = (uint32_t)ps;
   const float4 r0 = *(const float4 *)(rec + i * GS_REC_FLOATS);
@@ -545,31 +575,31 @@ size_t scan_workspace(int64_t count) {
   return align_up(sizeof(uint64_t) * (size_t)(nparts + 1));
 }
 
-template <class T>
-static gs_status scan_exclusive_t(const T *in, T *out, int64_t count, T *total, void *ws, hipStream_t s) {
+template <class T, class L>
+static gs_status scan_exclusive_t(L load, T *out, int64_t count, T *total, void *ws, hipStream_t s) {
   if (count <= 0) {
     if (total) GS_LAUNCH("fill", k_fill<T>, 1, 64, 0, s, total, 1, (T)0);
     return GS_OK;
   }
   if (count <= kSmallScan) {
-    GS_LAUNCH("scan", k_scan_small<T>, 1, kSmallBlock, 0, s, in, out, count, total);
+    GS_LAUNCH("scan", (k_scan_small<T, L>), 1, kSmallBlock, 0, s, load, out, count, total);
     return GS_OK;
   }
   const int64_t nparts = (count + kScanTile - 1) / kScanTile;
   T *partials = (T *)ws;
-  GS_LAUNCH("scan", k_scan_reduce<T>, nparts, kScanBlock, 0, s, in, count, partials);
-  GS_LAUNCH("scan", k_scan_apply<T>, nparts, kScanBlock, 0, s, in, out, count, (const T *)partials, total);
+  GS_LAUNCH("scan", (k_scan_reduce<T, L>), nparts, kScanBlock, 0, s, load, count, partials);
+  GS_LAUNCH("scan", (k_scan_apply<T, L>), nparts, kScanBlock, 0, s, load, out, count, (const T *)partials, total);
   return GS_OK;
 }
 
 // Exclusive scan; in may equal out.  total (device, may be NULL) receives the sum.
 gs_status scan_exclusive(const uint32_t *in, uint32_t *out, int64_t count, uint32_t *total, void *ws,
                          hipStream_t s) {
-  return scan_exclusive_t<uint32_t>(in, out, count, total, ws, s);
+  return scan_exclusive_t<uint32_t>(ArrayLoad<uint32_t>{in}, out, count, total, ws, s);
 }
 gs_status scan_exclusive_u64(const uint64_t *in, uint64_t *out, int64_t count, uint64_t *total, void *ws,
                              hipStream_t s) {
-  return scan_exclusive_t<uint64_t>(in, out, count, total, ws, s);
+  return scan_exclusive_t<uint64_t>(ArrayLoad<uint64_t>{in}, out, count, total, ws, s);
 }
 
 }  // namespace gsmi
@@ -581,7 +611,7 @@ namespace {
 struct BinLayout {
   uint32_t *kA, *vA, *kB, *vB, *block_pairs, *hist, *rowtot, *scalars, *ktmp, *vtmp, *stmp;
   uint64_t *total64;
-  uint64_t *flags64, *pos64;
+  uint64_t *pos64;
   uint4 *rect, *drec;
   void *scan_ws;
   size_t bytes;
@@ -592,7 +622,6 @@ BinLayout bin_layout(void *ws, int64_t n, int64_t capacity) {
   BinLayout L;
   const size_t nn = (size_t)(n > 0 ? n : 1);
   const size_t cc = (size_t)(capacity > 0 ? capacity : 1);
-  L.flags64 = cv.take<uint64_t>(nn);
   L.pos64 = cv.take<uint64_t>(nn);
   L.kA = cv.take<uint32_t>(nn);
   L.vA = cv.take<uint32_t>(nn);
@@ -664,9 +693,10 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
     // 1. compact the visible Gaussians with their depth keys
     //    (one 64-bit scan gives the visible positions and the index-order first slots;
     //    the visible count V is the low word of its total)
-    GS_LAUNCH("bin_flags", k_visible_flags, grid1(n), 256, 0, s, proj->tiles_touched, n, L.flags64);
-    if ((st = scan_exclusive_u64(L.flags64, L.pos64, n, L.total64, L.scan_ws, s)) != GS_OK) return st;
-    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, L.flags64, L.pos64, proj->rec, proj->radius, n, W, H,
+    if ((st = scan_exclusive_t<uint64_t>(TilesLoad{proj->tiles_touched}, L.pos64, n, L.total64, L.scan_ws, s)) !=
+        GS_OK)
+      return st;
+    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, proj->tiles_touched, L.pos64, proj->rec, proj->radius, n, W, H,
               (uint32_t)capacity, L.kA, L.vA, L.rect, first_slot);
     // 2. stable sort by depth (31 significant bits of a positive float)
     int shifts[8], widths[8];
