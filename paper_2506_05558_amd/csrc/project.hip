@@ -634,20 +634,6 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= m.n) return;
   const int64_t n = m.n;
-  // A Gaussian with a zero colour gradient in every view (no view saw it, or
-  // every channel was clamped) adds nothing: its parameters are not read, and
-  // in store mode its SH gradients are written as zeros.
-  bool seen = false;
-  for (int vi = 0; vi < m.nv && !seen; ++vi)
-    seen = m.gc[(int64_t)(vi * 3) * n + i] != 0.f || m.gc[(int64_t)(vi * 3 + 1) * n + i] != 0.f ||
-           m.gc[(int64_t)(vi * 3 + 2) * n + i] != 0.f;
-  if (!seen) {
-    if (m.store) {
-#pragma unroll
-      for (int k = 0; k < NB * 3; ++k) m.gsh[(int64_t)k * n + i] = 0.f;
-    }
-    return;
-  }
   float mu[3], sh[NB * 3], gsh[NB * 3], gm[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int k = 0; k < 3; ++k) mu[k] = m.means[k * n + i];
