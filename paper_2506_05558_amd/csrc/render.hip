@@ -370,13 +370,11 @@ struct BwdShared {
 //   opacity gradients are linear in these: d s / d mean = (A dx + B dy,
 //   B dx + C dy), d alpha / d o = alpha / o), sum w G_c and sum w G_depth
 //   (the colour and depth gradients).
-// The lane's entry k and its mean (mx, my) were picked up in phase 1, when
-// its sub-block walked slot e (kNoEntry: the slot holds none).
-// Two sub-blocks of a wave may hold the same entry, so the four sub-blocks
-// add in turn (bwd_commit: a read-modify-write per round, rounds kept in
-// order); an entry occurs at most once per sub-block list, so no two lanes of
-// a round share it, and no other wave writes this accumulator.
-// The values a lane adds in the five rounds of bwd_commit (round r: value
+// The lane's entry k (kNoEntry: the slot holds none) and its mean (mx, my)
+// come from the sub-block's list: slot e of a chunk is list position
+// 8 c + e, since every list entry takes a slot.  BwdCommit adds the sums to
+// the accumulator.
+// The values a lane adds in the five rounds of BwdCommit (round r: value
 // (r + g) mod 5 of the lane's five).
 struct Rot5 {
   float r0, r1, r2, r3, r4;
@@ -452,23 +450,14 @@ __device__ __forceinline__ Rot5 bwd_sums(BwdShared &B, int w, int k, float mx_, 
   return o;
 }
 
-// Adds a chunk's sums (bwd_sums: entry k, values u) to the wave's
-// accumulator in five rounds of one read-modify-write per lane: in round r
-// the lane of sub-block g adds its value (r + g) mod 5, so the four
-// sub-blocks of a round always write different rows and two lanes of a
-// round never share an address, even where sub-blocks hold the same entry.
-// The rounds are volatile accesses, kept in order (an address written in
-// one round may be read in a later one), and branch-free, so that they can
-// interleave with the arithmetic around them.  A lane with nothing to add in
-// a round reads and writes its own cell `dummy`, which no other lane touches
-// and which the caller overwrites before reading it.
 typedef __attribute__((address_space(3))) float lds_float;
 
 // One lane's part of adding a chunk's sums (bwd_sums: entry k, rotated
 // values) to the wave's accumulator, in five rounds of one read-modify-write:
 // in round r the lane of sub-block g adds its value (r + g) mod 5, so the
 // four sub-blocks of a round always write different rows and two lanes of a
-// round never share an address, even where sub-blocks hold the same entry.
+// round never share an address, even where sub-blocks hold the same entry;
+// no other wave writes this accumulator.
 // The accesses are volatile, so the rounds stay in order (an address written
 // in one round may be read in a later one); the caller spreads them over a
 // turn's arithmetic to hide their latency.  A lane with nothing to add in a
