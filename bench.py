@@ -93,10 +93,9 @@ def step_roofline(n, views, pixels, per_view, iters, spawn_k, sh_deg, ms_step):
     add("render_fwd", 40 * M + 48 * pixels, sup * FWD_PAIR + comp * FWD_COMP, times=iters * views)
     # adjoint: 40 B per instance, 20 B per pixel in, 40 B of 2D gradients per visible Gaussian out
     add("render_bwd", 40 * M + 20 * pixels + 40 * vis, comp * BWD_COMP, times=iters * views)
-    add("mark_visible", views * 8 * n, times=iters)
     # projection adjoint over the window: parameters read, per view the 40 B 2D gradients, the
-    # gradients written once
-    add("project_bwd", n * (pb + views * 40 + pb), times=iters)
+    # gradients and the 4 B visible flag (the sparse step's set) written once
+    add("project_bwd", n * (pb + views * 40 + pb + 4), times=iters)
     add("adam", 28 * par * vis, times=iters)
     add("lr_decay", 12 * n, times=iters)
     # the spawn step of the new frame: project + bin + render it, LoG probability on two
@@ -371,7 +370,6 @@ def main():
         k = state["step"]
         gsmi.zero_(d_pose)
         gsmi.zero_(dx6)
-        gsmi.zero_(visible)
         gsmi.pose_from_6d(x6, poses)
         gsmi.project_views(wviews, g, params)
         if use_async:  # no host synchronisation: the pair counts stay on the device
@@ -407,14 +405,14 @@ def main():
             if vw.pair_grad is None or vw.pair_grad.shape[0] < b.n_instances:
                 vw.pair_grad = torch.empty((int(b.n_instances * 1.25) + 1024, 12), dtype=torch.float32, device=dev)
             gsmi.render_bwd_pairs(cam, vw.proj, b, fr, gi, vw.pair_grad, params=params)
-            gsmi.mark_visible(vw.proj, visible)
             if count_pairs:
                 st = fr.stats.view(4, -1).to(torch.int64).sum(1).cpu().numpy()
                 pairs.append((int(st[0]), int(st[1]), int(st[2]), int(st[3]),
                               int(fr.n_contrib.to(torch.int64).sum()), b.n_instances,
                               int((vw.proj.tiles_touched > 0).sum())))
-        # the window's gradients are stored, not added: no clearing pass over the 2M x 59 planes
-        gsmi.project_bwd_views(wviews, g, grads, params, ws=pbwd_ws, store=True)
+        # the window's gradients are stored, not added: no clearing pass over the 2M x 59 planes;
+        # the same pass writes the set the sparse step updates
+        gsmi.project_bwd_views(wviews, g, grads, params, ws=pbwd_ws, store=True, visible=visible)
         if use_async:
             torch.maximum(n_pairs_max, n_pairs, out=n_pairs_max)
         gsmi.pose_6d_bwd(x6, d_pose, dx6)
@@ -532,7 +530,7 @@ def main():
         # 236 B of gradients once
         per_launch_bytes = {
             "project": n * (236 + N_VIEWS * 76),
-            "project_bwd": n * (236 + 236 + N_VIEWS * 24) + N_VIEWS * M * 48,
+            "project_bwd": n * (236 + 236 + 4 + N_VIEWS * 24) + N_VIEWS * M * 48,
         }.get(name)
         if per_launch_bytes is None:
             return None

@@ -336,10 +336,13 @@ gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_r
  * stores: every Gaussian's gradients are overwritten (0 for one no view
  * saw), so the caller need not clear them first -- one pass over the
  * gradient planes instead of a clearing pass plus a read-modify-write
- * (the pose outputs still accumulate). */
+ * (the pose outputs still accumulate).  visible: DEVICE int32 [n] or NULL;
+ * if given it is overwritten with 1 where some view's tiles_touched is
+ * positive and 0 elsewhere -- the set the sparse Adam step of section 4.3
+ * updates, as gs_mark_visible over the views would build it from zero. */
 gs_status gs_project_bwd_views_store(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                      const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
-                                     void *stream);
+                                     int32_t *visible, void *stream);
 
 /* ---- loss, metrics and optimiser (helpers of the joint optimisation) ----
  * gs_loss_l1: over count values, sums[0] = sum |image - target|,

@@ -106,6 +106,8 @@ struct MultiArgs {
   float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
   double *partials;                // [nv][gridDim.x][12] pose partial sums
   float *gc;                       // [nv][3][n] clamped colour gradient per view (adjoint workspace)
+  int32_t *visible;                // [n] or NULL: 1 where some view's tile count is positive
+  int visible_or;                  // OR into visible (later batches of views) instead of writing it
   ViewArgs v[kMaxViews];
 };
 
@@ -552,6 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   // colour record before the pair sums, so their latency overlaps work
   uint32_t fs_next = valid && m.nv > 0 ? m.v[0].first_slot[i] : 0xffffffffu;
   int t_next = valid && m.nv > 0 ? m.v[0].tiles[i] : 0;
+  bool seen = false;  // some view's tile count is positive (the sparse step's set)
   for (int vi = 0; vi < m.nv; ++vi) {
     const ViewArgs &v = m.v[vi];
     float term[12];
@@ -560,6 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
     // no first slot: the pairs did not fit the lists (see gs_bin_sort_async)
     const uint32_t fs = fs_next;
     const int nt = fs != 0xffffffffu ? t_next : 0;
+    seen = seen || t_next > 0;
     if (vi + 1 < m.nv) {
       fs_next = valid ? m.v[vi + 1].first_slot[i] : 0xffffffffu;
       t_next = valid ? m.v[vi + 1].tiles[i] : 0;
@@ -597,6 +601,10 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
     } else if (t < 12) {
       part[t] = 0.0;
     }
+  }
+  if (valid && m.visible) {
+    if (!m.visible_or) m.visible[i] = seen ? 1 : 0;
+    else if (seen) m.visible[i] = 1;
   }
   if (!valid || (!any && !m.store)) return;
   const int64_t n = m.n;
@@ -789,6 +797,9 @@ MultiArgs multi_args(const gs_raster_params *rp, const gs_gaussians *g) {
   m.f3 = g->filter3d;
   m.gm = m.gl = m.gq = m.go = m.gsh = nullptr;
   m.partials = nullptr;
+  m.gc = nullptr;
+  m.visible = nullptr;
+  m.visible_or = 0;
   return m;
 }
 
@@ -913,24 +924,24 @@ gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *byt
 
 static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                    const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
-                                   void *stream, int store);
+                                   void *stream, int store, int32_t *visible);
 
 gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream) {
-  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 0);
+  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 0, nullptr);
 }
 
 gs_status gs_project_bwd_views_store(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                      const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
-                                     void *stream) {
-  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 1);
+                                     int32_t *visible, void *stream) {
+  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 1, visible);
 }
 
 }  // extern "C"
 
 static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                    const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
-                                   void *stream, int store) {
+                                   void *stream, int store, int32_t *visible) {
   GS_REQUIRE(n_views >= 0 && (n_views == 0 || views), "gs_project_bwd_views: bad view list");
   gs_status st = check_gaussians(g, "gs_project_bwd_views");
   if (st != GS_OK) return st;
@@ -960,6 +971,8 @@ static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const 
                                            (size_t)proj_blocks(g->n)));
     m.nv = std::min(kMaxViews, n_views - v0);
     m.store = store && v0 == 0;  // later batches of views add to the first batch's stores
+    m.visible = visible;
+    m.visible_or = v0 > 0;
     for (int k = 0; k < m.nv; ++k) {
       const gs_view &gv = views[v0 + k];
       m.v[k] = view_args(&gv.cam, &gv.proj);

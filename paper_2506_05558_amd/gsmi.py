@@ -93,7 +93,8 @@ _sig = {
                                       _vp, _vp, _vp, _vp, _vp]),
     "gs_project_bwd_views_workspace": (C.c_int, [_i64, _i32, _P(_sz)]),
     "gs_project_bwd_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
-    "gs_project_bwd_views_store": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
+    "gs_project_bwd_views_store": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp,
+                                             _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
     "gs_psnr_workspace": (C.c_int, [_i64, _P(_sz)]),
@@ -562,16 +563,26 @@ def project_bwd_views_workspace(n: int, n_views: int) -> int:
 
 
 def project_bwd_views(views, g: Gaussians, grads: Gaussians, params: Params = Params(),
-                      ws: Optional[torch.Tensor] = None, store: bool = False):
+                      ws: Optional[torch.Tensor] = None, store: bool = False,
+                      visible: Optional[torch.Tensor] = None):
     """Chains every view's pair gradients to the parameters (summed over the
     views into grads: added, or with store=True written, no clearing needed)
-    and to each view's pose gradient."""
+    and to each view's pose gradient.  With store=True, visible (int32 [n])
+    is overwritten with the set the sparse step updates (some view's tile
+    count positive)."""
     need = project_bwd_views_workspace(g.n, len(views))
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.means.device)
-    fn = _lib.gs_project_bwd_views_store if store else _lib.gs_project_bwd_views
-    _check(fn(len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()), C.byref(grads.c()), ws.data_ptr(),
-              ws.numel(), _stream()))
+    args = (len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()), C.byref(grads.c()), ws.data_ptr(),
+            ws.numel())
+    if store:
+        if visible is not None:
+            _require(visible, torch.int32, (g.n,), "visible")
+        _check(_lib.gs_project_bwd_views_store(*args, _ptr(visible), _stream()))
+    else:
+        if visible is not None:
+            raise ValueError("project_bwd_views: the visible set is written by the store form only")
+        _check(_lib.gs_project_bwd_views(*args, _stream()))
     return grads
 
 

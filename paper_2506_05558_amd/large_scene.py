@@ -360,7 +360,6 @@ class LargeScene:
         views = self.wviews[:len(win)]
         gsmi.zero_(self.d_pose)
         gsmi.zero_(self.dx6)
-        gsmi.zero_(self.visible)
         gsmi.pose_from_6d(self.x6, self.poses)
         for i, fi in enumerate(win):
             views[i].cam = self.cams[fi]
@@ -382,8 +381,9 @@ class LargeScene:
             gsmi.render_fwd_l1(vw.cam, vw.proj, b, self.target(win[i]), scale, self.g_img, self.sums[i],
                                self.fwd_ws, self.params, out=self.frame)
             gsmi.render_bwd_pairs(vw.cam, vw.proj, b, self.frame, self.g_img, vw.pair_grad, params=self.params)
-            gsmi.mark_visible(vw.proj, self.visible)
-        gsmi.project_bwd_views(views, pool.g, self.grads, self.params, ws=self.pbwd_ws, store=True)
+        # stored gradients and the set the sparse step updates, in one pass
+        gsmi.project_bwd_views(views, pool.g, self.grads, self.params, ws=self.pbwd_ws, store=True,
+                               visible=self.visible)
         torch.maximum(self.n_pairs_max[:len(win)], self.n_pairs[:len(win)], out=self.n_pairs_max[:len(win)])
         gsmi.pose_6d_bwd(self.x6, self.d_pose, self.dx6)
         g, m1, m2, gr = pool.g, pool.m1, pool.m2, self.grads

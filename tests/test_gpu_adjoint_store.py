@@ -2,7 +2,8 @@
 equals clearing the gradients and adding (gs_project_bwd_views) bit for bit:
 one batch of views, more than eight views (the second batch adds to the
 first's stores), stale values in the gradient planes beforehand, and no
-view at all (every gradient 0)."""
+view at all (every gradient 0); the visible set it writes equals
+gs_mark_visible over the views from zero."""
 import numpy as np
 import pytest
 import torch
@@ -16,6 +17,7 @@ pytestmark = pytest.mark.gpu
 def _window(gs, n_views, seed):
     views = synth.trajectory(seed, n_views, 160, 120)
     scene = synth.window_scene(seed, views, 1500, 2)
+    scene.means[0, : scene.n // 10] += 1e4  # a tenth no view sees
     g = gc.gpu_gauss(scene)
     params = gs.Params(eps2d=0.1, mip_filter=1)
     vs = []
@@ -45,18 +47,25 @@ def test_store_equals_clear_and_add(n_views):
     for vw in vs:
         vw.dL_dpose.zero_()
     st = gs.Gaussians(*[torch.full_like(t, 123.0) for t in g.tensors()])  # stale values
-    gs.project_bwd_views(vs, g, st, params, store=True)
+    vis = torch.full((g.n,), 7, dtype=torch.int32, device="cuda")
+    gs.project_bwd_views(vs, g, st, params, store=True, visible=vis)
+    ref = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+    for vw in vs:
+        gs.mark_visible(vw.proj, ref)
     torch.cuda.synchronize()
     for a, b in zip(add.tensors(), st.tensors()):
         assert torch.equal(a, b)
     for vw, p in zip(vs, poses_add):
         assert torch.equal(vw.dL_dpose, p)
+    assert torch.equal(vis, ref) and 0 < int(ref.sum()) < g.n
 
 
 def test_store_with_no_view_clears():
     gs = gc.gpu()
     g, vs, params = _window(gs, 2, 90)
     st = gs.Gaussians(*[torch.full_like(t, -5.0) for t in g.tensors()])
-    gs.project_bwd_views([], g, st, params, store=True)
+    vis = torch.ones(g.n, dtype=torch.int32, device="cuda")
+    gs.project_bwd_views([], g, st, params, store=True, visible=vis)
     torch.cuda.synchronize()
     assert all(int(torch.count_nonzero(t)) == 0 for t in st.tensors())
+    assert int(torch.count_nonzero(vis)) == 0
