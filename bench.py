@@ -68,11 +68,12 @@ def step_roofline(n, views, pixels, per_view, iters, spawn_k, sh_deg, ms_step):
     the per-unit figures of the hot path's scope (bytes per Gaussian, per
     (Gaussian, tile) instance, per pixel; lane-ops per support and per
     composited pair), and frac = T_roof / T_measured.  per_view: the pair
-    counts of one view (instances, support, composited, visible)."""
+    counts of one view (instances, support, composited, visible) and the
+    size of the sparse step's set over the window (sparse)."""
     shf = 3 * (sh_deg + 1) ** 2
     par = 3 + 3 + 4 + 1 + shf  # floats per Gaussian
     pb = 4 * par  # parameter bytes per Gaussian (236 at degree 3)
-    M, sup, comp, vis = (per_view[k] for k in ("instances", "support", "composited", "visible"))
+    M, sup, comp, vis, sparse = (per_view[k] for k in ("instances", "support", "composited", "visible", "sparse"))
     radix_passes = 6  # 64-bit (tile, depth) keys over 32 + ceil(log2 tiles) bits in 8-bit digits
     kern = {}
 
@@ -94,10 +95,11 @@ def step_roofline(n, views, pixels, per_view, iters, spawn_k, sh_deg, ms_step):
     # adjoint: 40 B per instance, 20 B per pixel in, 40 B of 2D gradients per visible Gaussian out
     add("render_bwd", 40 * M + 20 * pixels + 40 * vis, comp * BWD_COMP, times=iters * views)
     # projection adjoint over the window: parameters read, per view the 40 B 2D gradients, the
-    # gradients and the 4 B visible flag (the sparse step's set) written once
-    add("project_bwd", n * (pb + views * 40 + pb + 4), times=iters)
-    add("adam", 28 * par * vis, times=iters)
-    add("lr_decay", 12 * n, times=iters)
+    # 4 B visible flag (the sparse step's set) written; the Adam step in its last pass reads
+    # both moments and writes parameters and moments (20 B per float) and reads and writes the
+    # rate (8 B) of each Gaussian of the set -- the gradients themselves never reach memory
+    add("project_bwd", n * (pb + views * 40 + 4), times=iters)
+    add("adam", (20 * par + 8) * sparse, times=iters)
     # the spawn step of the new frame: project + bin + render it, LoG probability on two
     # images (24 B per pixel each, 8 B out), selection (P_s, flags, prefix), the rule and the
     # network (196 inputs gathered, 7 outputs, a new 236 B Gaussian) per spawned primitive
@@ -318,6 +320,10 @@ def main():
     level = [0]
     lr = dict(means=1.6e-4 * 10, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh_dc=2.5e-3, sh_rest=1.25e-4,
               pose=1e-4)
+    # the sparse Adam step of every parameter group, applied by the projection adjoint's last pass
+    opt = gsmi.AdamGroups(lr_means=lr["means"], lr_log_scales=lr["log_scales"], lr_quats=lr["quats"],
+                          lr_opacity=lr["opacity_logits"], lr_sh_dc=lr["sh_dc"], lr_sh_rest=lr["sh_rest"], step=1,
+                          lr_decay=LR_DECAY)
     state = dict(step=0)
     pairs = []
     m_seen = [0] * N_VIEWS
@@ -410,20 +416,15 @@ def main():
                 pairs.append((int(st[0]), int(st[1]), int(st[2]), int(st[3]),
                               int(fr.n_contrib.to(torch.int64).sum()), b.n_instances,
                               int((vw.proj.tiles_touched > 0).sum())))
-        # the window's gradients are stored, not added: no clearing pass over the 2M x 59 planes;
-        # the same pass writes the set the sparse step updates
-        gsmi.project_bwd_views(wviews, g, grads, params, ws=pbwd_ws, store=True, visible=visible)
+        # the window's adjoint with the sparse Adam step and the rate decay in its last pass: the
+        # gradients of the 2M x 59 planes are never cleared, and the SH ones never stored; the
+        # geometry pass writes the set the sparse step updates
+        opt.step = k
+        gsmi.project_bwd_views_adam(wviews, g, grads, m1, m2, opt, visible, lr_scale=rates, params=params,
+                                    ws=pbwd_ws)
         if use_async:
             torch.maximum(n_pairs_max, n_pairs, out=n_pairs_max)
         gsmi.pose_6d_bwd(x6, d_pose, dx6)
-        for name in ["means", "log_scales", "quats", "opacity_logits"]:
-            gsmi.adam_step(getattr(g, name), getattr(grads, name), getattr(m1, name), getattr(m2, name), lr[name],
-                           k, visible=visible, n_stride=n, lr_scale=rates)
-        gsmi.adam_step(g.sh[0], grads.sh[0], m1.sh[0], m2.sh[0], lr["sh_dc"], k, visible=visible, n_stride=n,
-                       lr_scale=rates)
-        gsmi.adam_step(g.sh[1:], grads.sh[1:], m1.sh[1:], m2.sh[1:], lr["sh_rest"], k, visible=visible, n_stride=n,
-                       lr_scale=rates)
-        gsmi.lr_decay(rates, LR_DECAY, visible)
         gsmi.adam_step(x6[1:], dx6[1:], px_m[1:], px_v[1:], lr["pose"], k, eps=1e-12)
 
     for _ in range(args.warmup):
@@ -441,9 +442,9 @@ def main():
 
     names = ["project", "bin_compact", "radix_hist", "radix_scatter", "scan", "bin_counts",
              "bin_duplicate", "bin_ranges", "bin_fill", "render_fwd", "loss_l1", "loss_final", "render_bwd",
-             "project_bwd", "project_bwd_sh", "pose_reduce", "adam", "lr_decay", "zero", "mark_visible", "pose_6d",
-             "pose_6d_bwd", "downsample", "prune_flags", "prune_index", "gather_planes", "spawn_prob", "spawn_select",
-             "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
+             "project_bwd", "project_bwd_sh", "project_bwd_adam", "pose_reduce", "adam", "lr_decay", "zero",
+             "mark_visible", "pose_6d", "pose_6d_bwd", "downsample", "prune_flags", "prune_index", "gather_planes",
+             "spawn_prob", "spawn_select", "spawn_compact", "spawn_rule", "mlp_infer", "mlp_train"]
 
     def read_profile():
         out = {}
@@ -456,7 +457,7 @@ def main():
 
     # timed region: HIP events bracket only the kernels whose rooflines are reported
     gsmi.profile_reset()
-    gsmi.profile_select(["render_fwd", "render_bwd", "project", "project_bwd", "project_bwd_sh"])
+    gsmi.profile_select(["render_fwd", "render_bwd", "project", "project_bwd", "project_bwd_adam"])
     gsmi.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -500,6 +501,7 @@ def main():
     walked = sum(p[4] for p in pairs) / N_VIEWS
     M = sum(p[5] for p in pairs) / N_VIEWS
     visible_per_view = sum(p[6] for p in pairs) / N_VIEWS
+    n_sparse = int(visible.sum())  # the sparse step's set: Gaussians some window view sees
 
     ms_step = elapsed * 1e3 / args.steps
     multiscale = measure_multiscale(gsmi, keyframe_step, args.iters, targets, g, m1, m2, rates, ms_step)
@@ -511,9 +513,9 @@ def main():
     def roof(name, ks=kernels):
         k = ks[name]
         t = k["ms_per_launch"] * 1e-3
-        if name == "project_bwd" and "project_bwd_sh" in ks:
-            # the adjoint is two passes (geometry, then SH) per call
-            t = (k["ms_total"] + ks["project_bwd_sh"]["ms_total"]) / k["launches"] * 1e-3
+        if name == "project_bwd" and "project_bwd_adam" in ks:
+            # the adjoint is two passes per call: geometry, then SH with the Adam step
+            t = (k["ms_total"] + ks["project_bwd_adam"]["ms_total"]) / k["launches"] * 1e-3
         if name == "render_fwd":
             ops = support * FWD_PAIR + comp * FWD_COMP
             a = ops / t / 1e12
@@ -526,11 +528,12 @@ def main():
                         traffic=None)
         # one launch of each covers the 8 views: parameters read once (236 B), per view a
         # 76 B record + half-widths + tile count written; the adjoint reads parameters and per
-        # view 24 B (tile count, first slot, colour record) + 48 B per pair, and writes the
-        # 236 B of gradients once
+        # view 24 B (tile count, first slot, colour record) + 48 B per pair, writes the 4 B
+        # visible flag, and for each Gaussian of the sparse set reads both moments and writes
+        # parameters and moments (5 x 236 B) and its rate (4 + 4 B)
         per_launch_bytes = {
             "project": n * (236 + N_VIEWS * 76),
-            "project_bwd": n * (236 + 236 + 4 + N_VIEWS * 24) + N_VIEWS * M * 48,
+            "project_bwd": n * (236 + 4 + N_VIEWS * 24) + N_VIEWS * M * 48 + n_sparse * (5 * 236 + 8),
         }.get(name)
         if per_launch_bytes is None:
             return None
@@ -597,7 +600,7 @@ def main():
         "ms_per_joint_iteration": round(ms_step / args.iters, 3),
         "render_path": render_path,
         "step_roofline": step_roofline(n, N_VIEWS, W * H, {"instances": M, "support": support, "composited": comp,
-                                                             "visible": visible_per_view},
+                                                             "visible": visible_per_view, "sparse": n_sparse},
                                        args.iters, SPAWN_K, SH_DEG, ms_step),
         "pairs_per_view": {"tile_list_to_stop": tile_pairs, "evaluated": evaluated, "support": support,
                            "composited": comp, "tile_list_walked_bwd": walked, "instances": M,

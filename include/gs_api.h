@@ -344,6 +344,37 @@ gs_status gs_project_bwd_views_store(int32_t n_views, const gs_view *views, cons
                                      const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
                                      int32_t *visible, void *stream);
 
+/* Rates and constants of the sparse Adam step of the joint optimisation
+ * (section 4.3): one rate per parameter group -- means, log-scales,
+ * quaternions, opacity logits, the degree-0 SH coefficients (planes 0..2 of
+ * sh) and the higher-degree ones (planes 3..) -- Adam's beta1, beta2, eps
+ * and step (>= 1), and the per-Gaussian rate decay that follows the step,
+ * in (0, 1] (the joint-optimisation appendix). */
+typedef struct {
+  float lr_means, lr_log_scales, lr_quats, lr_opacity, lr_sh_dc, lr_sh_rest;
+  float beta1, beta2, eps;
+  int32_t step;
+  float lr_decay;
+} gs_adam_groups; /* HOST memory */
+
+/* The store-form adjoint of the window followed by the sparse Adam step and
+ * the rate decay, the step applied by the adjoint's last pass while each
+ * Gaussian's gradients are still in registers (the gradients of the SH
+ * coefficients never reach memory).  On return g, m1, m2 (the first and
+ * second moments, same shapes as g), lr_scale and visible hold exactly what
+ * gs_project_bwd_views_store (into grads, with visible), then
+ * gs_adam_step on each group (visible, lr_scale, n_stride = n) and
+ * gs_lr_decay (visible) would leave; each view's pose gradient is
+ * accumulated as there.  grads is scratch (its contents on return are
+ * unspecified); visible (DEVICE int32 [n]) is required and overwritten;
+ * lr_scale (DEVICE float [n]) may be NULL (rate lr, no decay).  ws: the
+ * gs_project_bwd_views_workspace(n, n_views) bytes.  g, m1, m2, lr_scale
+ * are updated in place. */
+gs_status gs_project_bwd_views_adam(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                                    gs_gaussians *g, gs_gaussians *m1, gs_gaussians *m2, float *lr_scale,
+                                    const gs_adam_groups *opt, gs_gaussians *grads, void *ws, size_t ws_bytes,
+                                    int32_t *visible, void *stream);
+
 /* ---- loss, metrics and optimiser (helpers of the joint optimisation) ----
  * gs_loss_l1: over count values, sums[0] = sum |image - target|,
  * sums[1] = sum (image - target)^2 (double, DEVICE, overwritten), and if

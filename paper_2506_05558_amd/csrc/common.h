@@ -142,6 +142,23 @@ __device__ __forceinline__ bool tile_rect(float mx, float my, int rx, int ry, in
   return true;
 }
 
+// One Adam update of one element (section 4.3; the formula of
+// gs_adam_step): c1 = 1 / (1 - b1^step), c2 = 1 / (1 - b2^step) from
+// adam_bias.  Shared by the optimiser kernels and the adjoint that applies
+// the step itself; the moment updates are written as explicit FMAs because
+// left to contraction the compiler fuses either product of b m + (1 - b) g
+// depending on the surrounding code, and the kernels would differ in the
+// last bit.
+__device__ __forceinline__ void adam_one(float gi, float &mi, float &vi, float &pi, float lr, float b1, float b2,
+                                         float eps, float c1, float c2) {
+  mi = __builtin_fmaf(b1, mi, (1.f - b1) * gi);
+  vi = __builtin_fmaf(b2, vi, (1.f - b2) * gi * gi);
+  pi -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+inline float adam_bias(float beta, int step) {
+  return (float)(1.0 / (1.0 - pow((double)beta, (double)step)));
+}
+
 // Map workgroup b of a grid of nb to a logical tile so that each of the 8
 // XCDs (workgroups are dealt round-robin) walks one contiguous band of tiles
 // and neighbouring tiles, which share Gaussians, hit the same L2.

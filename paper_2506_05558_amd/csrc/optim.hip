@@ -58,18 +58,6 @@ __global__ __launch_bounds__(64) void k_loss_final(const double *partials, int n
   }
 }
 
-// The same update, four consecutive elements of one plane per lane (16-byte
-// non-temporal loads and stores); used when the planes hold a multiple of four elements
-// and every array is 16-byte aligned.  A quad with no visible Gaussian is
-// not touched; in a partly visible quad the hidden elements are stored back
-// unchanged.
-__device__ __forceinline__ void adam_one(float gi, float &mi, float &vi, float &pi, float lr, float b1, float b2,
-                                         float eps, float c1, float c2) {
-  mi = b1 * mi + (1.f - b1) * gi;
-  vi = b2 * vi + (1.f - b2) * gi * gi;
-  pi -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
-}
-
 // Streaming 16-byte accesses that bypass cache retention: each element of
 // the optimiser state is touched once per step.
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -81,6 +69,11 @@ __device__ __forceinline__ void store_stream(float *q, const float4 &x) {
   __builtin_nontemporal_store((v4f){x.x, x.y, x.z, x.w}, (v4f *)q);
 }
 
+// The Adam update (adam_one), four consecutive elements of one plane per
+// lane (16-byte non-temporal loads and stores); used when the planes hold a
+// multiple of four elements and every array is 16-byte aligned.  A quad with
+// no visible Gaussian is not touched; in a partly visible quad the hidden
+// elements are stored back unchanged.
 // RATE: lr_scale[j] multiplies the rate of every element of Gaussian j.
 template <bool RATE>
 __global__ __launch_bounds__(256) void k_adam4(float *p, const float *g, float *m, float *v, float lr, float b1,
@@ -257,8 +250,7 @@ gs_status gs_adam_step(float *param, const float *grad, float *m, float *v, int6
   GS_REQUIRE(param && grad && m && v, "gs_adam_step: NULL argument");
   if (visible || lr_scale)
     GS_REQUIRE(n_stride > 0, "gs_adam_step: n_stride must be positive with a visibility mask or per-Gaussian rates");
-  const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
-  const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+  const float c1 = adam_bias(beta1, step), c2 = adam_bias(beta2, step);
   // without a mask or rates the whole array is one "plane"
   const int64_t stride = visible || lr_scale ? n_stride : count;
   const int64_t planes = (count + stride - 1) / stride;

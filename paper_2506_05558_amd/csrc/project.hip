@@ -95,12 +95,23 @@ struct ViewArgs {
 // views, which is what bounds both kernels (HBM traffic per Gaussian).
 constexpr int kMaxViews = 8;
 
+// The sparse Adam step that the last SH pass of the adjoint applies (section
+// 4.3): parameter planes and both moments updated in place, one rate per
+// group, the per-Gaussian rate (NULL: 1) and its decay after the step.
+struct AdamArgs {
+  float *p[5], *m1[5], *m2[5];  // means, log_scales, quats, opacity_logits, sh
+  float *rate;
+  float lr[6];  // means, log_scales, quats, opacity, sh degree 0, sh degree >= 1
+  float b1, b2, eps, c1, c2, decay;
+};
+
 struct MultiArgs {
   int64_t n;
   int nv;
   float eps2d, alpha_min, guard;
   int mip;    // eps2d is a screen-space filter whose opacity compensation applies
   int store;  // the adjoint stores (=) every Gaussian's gradients instead of adding them
+  int adam;   // the SH pass applies the sparse Adam step (opt) instead of storing
   const float *means, *log_scales, *quats, *opac, *sh;
   const float *f3;                 // [n] 3D smoothing-filter variance per Gaussian, or NULL
   float *gm, *gl, *gq, *go, *gsh;  // parameter gradients (accumulated)
@@ -108,6 +119,7 @@ struct MultiArgs {
   float *gc;                       // [nv][3][n] clamped colour gradient per view (adjoint workspace)
   int32_t *visible;                // [n] or NULL: 1 where some view's tile count is positive
   int visible_or;                  // OR into visible (later batches of views) instead of writing it
+  AdamArgs opt;                    // read by the SH pass's Adam form only
   ViewArgs v[kMaxViews];
 };
 
@@ -636,7 +648,63 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
 // view-direction part of the mean gradient (the view direction carries no
 // pose gradient, section 4.3).  Runs after k_project_bwd_views on the same
 // views.
+__device__ __forceinline__ void adam_elem(const AdamArgs &a, int plane, int64_t e, float g, float p, float lr) {
+  float m1 = __builtin_nontemporal_load(a.m1[plane] + e), m2 = __builtin_nontemporal_load(a.m2[plane] + e);
+  adam_one(g, m1, m2, p, lr, a.b1, a.b2, a.eps, a.c1, a.c2);
+  __builtin_nontemporal_store(m1, a.m1[plane] + e);
+  __builtin_nontemporal_store(m2, a.m2[plane] + e);
+  __builtin_nontemporal_store(p, a.p[plane] + e);
+}
+
+// Adam on Gaussian i (visible).  The gradient of each plane is the value the
+// store form leaves there: the geometry pass's stored sum, plus this pass's
+// view-direction part for the means; for the SH planes this pass's sum
+// (first batch of views) or the earlier batches' sum plus it.  The rate is
+// read before the step and decayed after it, as gs_lr_decay after
+// gs_adam_step.
 template <int DEG>
+__device__ __forceinline__ void adam_gaussian(const MultiArgs &m, int64_t i, const float mu[3], const float sh[],
+                                              const float gm[3], const float gsh[], bool any) {
+  constexpr int NB = GParams<DEG>::NB;
+  const AdamArgs &a = m.opt;
+  const int64_t n = m.n;
+  const float rate = a.rate ? a.rate[i] : 1.f;
+  const auto lr_of = [&](int group) { return a.rate ? a.lr[group] * rate : a.lr[group]; };
+  {
+    const float lr = lr_of(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float g = m.gm[k * n + i];
+      if (DEG > 0 && any) g += gm[k];
+      adam_elem(a, 0, k * n + i, g, mu[k], lr);
+    }
+  }
+  {
+    const float lr = lr_of(1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) adam_elem(a, 1, k * n + i, m.gl[k * n + i], m.log_scales[k * n + i], lr);
+  }
+  {
+    const float lr = lr_of(2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) adam_elem(a, 2, k * n + i, m.gq[k * n + i], m.quats[k * n + i], lr);
+  }
+  adam_elem(a, 3, i, m.go[i], m.opac[i], lr_of(3));
+  const float lr_dc = lr_of(4), lr_rest = lr_of(5);
+#pragma unroll
+  for (int k = 0; k < NB * 3; ++k) {
+    const int64_t e = (int64_t)k * n + i;
+    const float g = m.store ? gsh[k] : (any ? m.gsh[e] + gsh[k] : m.gsh[e]);
+    const float p = DEG > 0 ? sh[k] : m.sh[e];
+    adam_elem(a, 4, e, g, p, k < 3 ? lr_dc : lr_rest);
+  }
+  if (a.rate) a.rate[i] = rate * a.decay;
+}
+
+// ADAM: the last pass of a window whose step follows at once -- instead of
+// storing the gradients it applies the sparse Adam step (adam_gaussian) to
+// the Gaussians in visible, which this launch's geometry pass wrote.
+template <int DEG, bool ADAM>
 __global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
   constexpr int NB = GParams<DEG>::NB;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -691,6 +759,10 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
       gm[1] += (gy - radial * d[1]) * dinv;
       gm[2] += (gz - radial * d[2]) * dinv;
     }
+  }
+  if (ADAM) {
+    if (m.visible[i]) adam_gaussian<DEG>(m, i, mu, sh, gm, gsh, any);
+    return;
   }
   if (!any && !m.store) return;
   if (DEG > 0 && any) {  // after the geometry pass's store or sum
@@ -793,6 +865,7 @@ MultiArgs multi_args(const gs_raster_params *rp, const gs_gaussians *g) {
   m.guard = rp->guard;
   m.mip = rp->mip_filter != 0;
   m.store = 0;
+  m.adam = 0;
   m.means = g->means; m.log_scales = g->log_scales; m.quats = g->quats; m.opac = g->opacity_logits; m.sh = g->sh;
   m.f3 = g->filter3d;
   m.gm = m.gl = m.gq = m.go = m.gsh = nullptr;
@@ -840,11 +913,20 @@ gs_status launch_project_bwd(const MultiArgs &m, int deg, hipStream_t s) {
     case 2: GS_LAUNCH("project_bwd", k_project_bwd_views<2>, blocks, kBlock, 0, s, m); break;
     default: GS_LAUNCH("project_bwd", k_project_bwd_views<3>, blocks, kBlock, 0, s, m); break;
   }
-  switch (deg) {
-    case 0: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<0>, blocks, kBlock, 0, s, m); break;
-    case 1: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<1>, blocks, kBlock, 0, s, m); break;
-    case 2: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<2>, blocks, kBlock, 0, s, m); break;
-    default: GS_LAUNCH("project_bwd_sh", k_project_bwd_sh<3>, blocks, kBlock, 0, s, m); break;
+  if (m.adam) {
+    switch (deg) {
+      case 0: GS_LAUNCH("project_bwd_adam", (k_project_bwd_sh<0, true>), blocks, kBlock, 0, s, m); break;
+      case 1: GS_LAUNCH("project_bwd_adam", (k_project_bwd_sh<1, true>), blocks, kBlock, 0, s, m); break;
+      case 2: GS_LAUNCH("project_bwd_adam", (k_project_bwd_sh<2, true>), blocks, kBlock, 0, s, m); break;
+      default: GS_LAUNCH("project_bwd_adam", (k_project_bwd_sh<3, true>), blocks, kBlock, 0, s, m); break;
+    }
+  } else {
+    switch (deg) {
+      case 0: GS_LAUNCH("project_bwd_sh", (k_project_bwd_sh<0, false>), blocks, kBlock, 0, s, m); break;
+      case 1: GS_LAUNCH("project_bwd_sh", (k_project_bwd_sh<1, false>), blocks, kBlock, 0, s, m); break;
+      case 2: GS_LAUNCH("project_bwd_sh", (k_project_bwd_sh<2, false>), blocks, kBlock, 0, s, m); break;
+      default: GS_LAUNCH("project_bwd_sh", (k_project_bwd_sh<3, false>), blocks, kBlock, 0, s, m); break;
+    }
   }
   bool pose = false;
   PoseOuts outs;
@@ -924,7 +1006,7 @@ gs_status gs_project_bwd_views_workspace(int64_t n, int32_t n_views, size_t *byt
 
 static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                    const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
-                                   void *stream, int store, int32_t *visible);
+                                   void *stream, int store, int32_t *visible, const AdamArgs *adam = nullptr);
 
 gs_status gs_project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes, void *stream) {
@@ -937,11 +1019,46 @@ gs_status gs_project_bwd_views_store(int32_t n_views, const gs_view *views, cons
   return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 1, visible);
 }
 
+gs_status gs_project_bwd_views_adam(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
+                                    gs_gaussians *g, gs_gaussians *m1, gs_gaussians *m2, float *lr_scale,
+                                    const gs_adam_groups *opt, gs_gaussians *grads, void *ws, size_t ws_bytes,
+                                    int32_t *visible, void *stream) {
+  const char *fn = "gs_project_bwd_views_adam";
+  gs_status st = check_gaussians(g, fn);
+  if (st != GS_OK) return st;
+  if ((st = check_gaussians(m1, fn)) != GS_OK || (st = check_gaussians(m2, fn)) != GS_OK) return st;
+  GS_REQUIRE(m1->n == g->n && m2->n == g->n && m1->sh_degree == g->sh_degree && m2->sh_degree == g->sh_degree,
+             "%s: moment shapes differ from the Gaussians'", fn);
+  GS_REQUIRE(opt, "%s: NULL optimiser settings", fn);
+  GS_REQUIRE(opt->step >= 1, "%s: step must be >= 1", fn);
+  GS_REQUIRE(opt->beta1 >= 0.f && opt->beta1 < 1.f && opt->beta2 >= 0.f && opt->beta2 < 1.f && opt->eps >= 0.f,
+             "%s: bad betas or eps", fn);
+  GS_REQUIRE(opt->lr_decay > 0.f && opt->lr_decay <= 1.f, "%s: lr_decay must be in (0, 1]", fn);
+  if (g->n > 0) GS_REQUIRE(visible, "%s: visible is required", fn);
+  AdamArgs a;
+  float *const planes[3][5] = {{g->means, g->log_scales, g->quats, g->opacity_logits, g->sh},
+                               {m1->means, m1->log_scales, m1->quats, m1->opacity_logits, m1->sh},
+                               {m2->means, m2->log_scales, m2->quats, m2->opacity_logits, m2->sh}};
+  for (int k = 0; k < 5; ++k) {
+    a.p[k] = planes[0][k];
+    a.m1[k] = planes[1][k];
+    a.m2[k] = planes[2][k];
+  }
+  a.rate = lr_scale;
+  a.lr[0] = opt->lr_means; a.lr[1] = opt->lr_log_scales; a.lr[2] = opt->lr_quats; a.lr[3] = opt->lr_opacity;
+  a.lr[4] = opt->lr_sh_dc; a.lr[5] = opt->lr_sh_rest;
+  a.b1 = opt->beta1; a.b2 = opt->beta2; a.eps = opt->eps;
+  a.c1 = adam_bias(opt->beta1, opt->step);
+  a.c2 = adam_bias(opt->beta2, opt->step);
+  a.decay = opt->lr_decay;
+  return project_bwd_views(n_views, views, rp, g, grads, ws, ws_bytes, stream, 1, visible, &a);
+}
+
 }  // extern "C"
 
 static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const gs_raster_params *rp,
                                    const gs_gaussians *g, gs_gaussians *grads, void *ws, size_t ws_bytes,
-                                   void *stream, int store, int32_t *visible) {
+                                   void *stream, int store, int32_t *visible, const AdamArgs *adam) {
   GS_REQUIRE(n_views >= 0 && (n_views == 0 || views), "gs_project_bwd_views: bad view list");
   gs_status st = check_gaussians(g, "gs_project_bwd_views");
   if (st != GS_OK) return st;
@@ -973,6 +1090,10 @@ static gs_status project_bwd_views(int32_t n_views, const gs_view *views, const 
     m.store = store && v0 == 0;  // later batches of views add to the first batch's stores
     m.visible = visible;
     m.visible_or = v0 > 0;
+    if (adam && v0 + kMaxViews >= n_views) {  // the last batch applies the step
+      m.adam = 1;
+      m.opt = *adam;
+    }
     for (int k = 0; k < m.nv; ++k) {
       const gs_view &gv = views[v0 + k];
       m.v[k] = view_args(&gv.cam, &gv.proj);

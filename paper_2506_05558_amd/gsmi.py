@@ -67,6 +67,12 @@ class _SpawnParams(C.Structure):
                 ("opacity", C.c_float), ("min_prob", C.c_float)]
 
 
+class _AdamGroups(C.Structure):
+    _fields_ = [("lr_means", C.c_float), ("lr_log_scales", C.c_float), ("lr_quats", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_sh_dc", C.c_float), ("lr_sh_rest", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("step", C.c_int32), ("lr_decay", C.c_float)]
+
+
 _vp, _i64, _i32, _f, _sz = C.c_void_p, C.c_int64, C.c_int32, C.c_float, C.c_size_t
 _P = C.POINTER
 _sig = {
@@ -95,6 +101,8 @@ _sig = {
     "gs_project_bwd_views": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp]),
     "gs_project_bwd_views_store": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _vp, _sz, _vp,
                                              _vp]),
+    "gs_project_bwd_views_adam": (C.c_int, [_i32, _P(_View), _P(_Params), _P(_Gauss), _P(_Gauss), _P(_Gauss), _vp,
+                                            _P(_AdamGroups), _P(_Gauss), _vp, _sz, _vp, _vp]),
     "gs_loss_workspace": (C.c_int, [_i64, _P(_sz)]),
     "gs_loss_l1": (C.c_int, [_vp, _vp, _i64, _f, _vp, _vp, _vp, _sz, _vp]),
     "gs_psnr_workspace": (C.c_int, [_i64, _P(_sz)]),
@@ -584,6 +592,45 @@ def project_bwd_views(views, g: Gaussians, grads: Gaussians, params: Params = Pa
             raise ValueError("project_bwd_views: the visible set is written by the store form only")
         _check(_lib.gs_project_bwd_views(*args, _stream()))
     return grads
+
+
+@dataclass
+class AdamGroups:
+    """Rates per parameter group and Adam's constants for
+    project_bwd_views_adam (gs_adam_groups)."""
+    lr_means: float
+    lr_log_scales: float
+    lr_quats: float
+    lr_opacity: float
+    lr_sh_dc: float
+    lr_sh_rest: float
+    step: int
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+    lr_decay: float = 1.0
+
+    def c(self):
+        return _AdamGroups(self.lr_means, self.lr_log_scales, self.lr_quats, self.lr_opacity, self.lr_sh_dc,
+                           self.lr_sh_rest, self.beta1, self.beta2, self.eps, int(self.step), self.lr_decay)
+
+
+def project_bwd_views_adam(views, g: Gaussians, grads: Gaussians, m1: Gaussians, m2: Gaussians, opt: AdamGroups,
+                           visible: torch.Tensor, lr_scale: Optional[torch.Tensor] = None,
+                           params: Params = Params(), ws: Optional[torch.Tensor] = None):
+    """The store-form adjoint of the views followed by the sparse Adam step on
+    every parameter group and the rate decay (gs_project_bwd_views_adam): g,
+    m1, m2, lr_scale and visible are updated in place; grads is scratch."""
+    _require(visible, torch.int32, (g.n,), "visible")
+    if lr_scale is not None:
+        _require(lr_scale, torch.float32, (g.n,), "lr_scale")
+    need = project_bwd_views_workspace(g.n, len(views))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.means.device)
+    _check(_lib.gs_project_bwd_views_adam(len(views), _views_c(views), C.byref(params.c()), C.byref(g.c()),
+                                          C.byref(m1.c()), C.byref(m2.c()), _ptr(lr_scale), C.byref(opt.c()),
+                                          C.byref(grads.c()), ws.data_ptr(), ws.numel(), visible.data_ptr(),
+                                          _stream()))
 
 
 def loss_l1(image: torch.Tensor, target: torch.Tensor, grad_scale: Optional[float] = None,

@@ -354,7 +354,7 @@ class LargeScene:
                 vw.pair_grad = torch.empty((cap, 12), dtype=torch.float32, device="cuda")
 
     def joint_iteration(self, win):
-        cfg, pool, n = self.cfg, self.pool, self.pool.n
+        cfg, pool = self.cfg, self.pool
         self.step_count += 1
         k = self.step_count
         views = self.wviews[:len(win)]
@@ -381,20 +381,15 @@ class LargeScene:
             gsmi.render_fwd_l1(vw.cam, vw.proj, b, self.target(win[i]), scale, self.g_img, self.sums[i],
                                self.fwd_ws, self.params, out=self.frame)
             gsmi.render_bwd_pairs(vw.cam, vw.proj, b, self.frame, self.g_img, vw.pair_grad, params=self.params)
-        # stored gradients and the set the sparse step updates, in one pass
-        gsmi.project_bwd_views(views, pool.g, self.grads, self.params, ws=self.pbwd_ws, store=True,
-                               visible=self.visible)
+        # the window's adjoint with the sparse Adam step and the rate decay in its last pass (the
+        # geometry pass writes the set the step updates)
+        opt = gsmi.AdamGroups(lr_means=LR["means"], lr_log_scales=LR["log_scales"], lr_quats=LR["quats"],
+                              lr_opacity=LR["opacity_logits"], lr_sh_dc=LR["sh_dc"], lr_sh_rest=LR["sh_rest"],
+                              step=k, lr_decay=cfg.lr_decay)
+        gsmi.project_bwd_views_adam(views, pool.g, self.grads, pool.m1, pool.m2, opt, self.visible,
+                                    lr_scale=pool.rates, params=self.params, ws=self.pbwd_ws)
         torch.maximum(self.n_pairs_max[:len(win)], self.n_pairs[:len(win)], out=self.n_pairs_max[:len(win)])
         gsmi.pose_6d_bwd(self.x6, self.d_pose, self.dx6)
-        g, m1, m2, gr = pool.g, pool.m1, pool.m2, self.grads
-        for name in ["means", "log_scales", "quats", "opacity_logits"]:
-            gsmi.adam_step(getattr(g, name), getattr(gr, name), getattr(m1, name), getattr(m2, name), LR[name], k,
-                           visible=self.visible, n_stride=n, lr_scale=pool.rates)
-        gsmi.adam_step(g.sh[0], gr.sh[0], m1.sh[0], m2.sh[0], LR["sh_dc"], k, visible=self.visible, n_stride=n,
-                       lr_scale=pool.rates)
-        gsmi.adam_step(g.sh[1:], gr.sh[1:], m1.sh[1:], m2.sh[1:], LR["sh_rest"], k, visible=self.visible,
-                       n_stride=n, lr_scale=pool.rates)
-        gsmi.lr_decay(pool.rates, cfg.lr_decay, self.visible)
         # poses of the window except keyframe 0
         lo = max(win[0], 1)
         if lo <= win[-1]:
