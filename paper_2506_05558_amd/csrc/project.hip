@@ -641,6 +641,94 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   m.go[i] += acc.go;
 }
 
+// The Adam step on the SH planes of Gaussian i, six planes at a time with
+// every load of a batch issued before its first update (the moment stores of
+// one plane would otherwise hold back the next plane's loads: the compiler
+// cannot prove they do not alias).  STORE: the gradient is this pass's sum
+// (first batch of views); otherwise the earlier batches' stored sum plus it
+// (plus nothing if no view of this batch reached the colour).
+template <int DEG, bool STORE>
+__device__ __forceinline__ void adam_sh(const MultiArgs &m, int64_t i, const float sh[], const float gsh[], bool any,
+                                        float lr_dc, float lr_rest) {
+  constexpr int NSH = GParams<DEG>::NB * 3, kBatch = 6;
+  const AdamArgs &a = m.opt;
+  const int64_t n = m.n;
+#pragma unroll
+  for (int k0 = 0; k0 < NSH; k0 += kBatch) {
+    float g[kBatch], p[kBatch], m1[kBatch], m2[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = k0 + j;
+      if (k >= NSH) break;
+      const int64_t e = (int64_t)k * n + i;
+      m1[j] = __builtin_nontemporal_load(a.m1[4] + e);
+      m2[j] = __builtin_nontemporal_load(a.m2[4] + e);
+      if (STORE) {
+        g[j] = gsh[k];
+      } else {
+        const float prev = m.gsh[e];
+        g[j] = any ? prev + gsh[k] : prev;
+      }
+      p[j] = DEG > 0 ? sh[k] : m.sh[e];
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int k = k0 + j;
+      if (k >= NSH) break;
+      const int64_t e = (int64_t)k * n + i;
+      adam_one(g[j], m1[j], m2[j], p[j], k < 3 ? lr_dc : lr_rest, a.b1, a.b2, a.eps, a.c1, a.c2);
+      __builtin_nontemporal_store(m1[j], a.m1[4] + e);
+      __builtin_nontemporal_store(m2[j], a.m2[4] + e);
+      __builtin_nontemporal_store(p[j], a.p[4] + e);
+    }
+  }
+}
+
+// Adam on Gaussian i (visible): the SH planes while their values are still
+// in registers (adam_sh), then the eleven geometry planes, all their loads
+// issued together.  The gradient of each plane is the value the store form
+// leaves there: the geometry pass's stored sum, plus this pass's
+// view-direction part for the means.  The rate is read before the step and
+// decayed after it, as gs_lr_decay after gs_adam_step.
+template <int DEG>
+__device__ __forceinline__ void adam_gaussian(const MultiArgs &m, int64_t i, const float mu[3], const float sh[],
+                                              const float gm[3], const float gsh[], bool any) {
+  const AdamArgs &a = m.opt;
+  const int64_t n = m.n;
+  const float rate = a.rate ? a.rate[i] : 1.f;
+  const auto lr_of = [&](int group) { return a.rate ? a.lr[group] * rate : a.lr[group]; };
+  if (m.store) adam_sh<DEG, true>(m, i, sh, gsh, any, lr_of(4), lr_of(5));
+  else adam_sh<DEG, false>(m, i, sh, gsh, any, lr_of(4), lr_of(5));
+  // geometry planes: means 0..2, log-scales 3..5, quaternion 6..9, opacity 10
+  constexpr int kArr[11] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3};
+  constexpr int kRow[11] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 3, 0};
+  const float *const grad[4] = {m.gm, m.gl, m.gq, m.go};
+  const float *const par[4] = {m.means, m.log_scales, m.quats, m.opac};
+  float g[11], p[11], m1[11], m2[11];
+#pragma unroll
+  for (int j = 0; j < 11; ++j) {
+    const int64_t e = kRow[j] * n + i;
+    m1[j] = __builtin_nontemporal_load(a.m1[kArr[j]] + e);
+    m2[j] = __builtin_nontemporal_load(a.m2[kArr[j]] + e);
+    g[j] = grad[kArr[j]][e];
+    p[j] = j < 3 ? mu[j] : par[kArr[j]][e];
+  }
+  if (DEG > 0 && any) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] += gm[k];
+  }
+  const float lr[4] = {lr_of(0), lr_of(1), lr_of(2), lr_of(3)};
+#pragma unroll
+  for (int j = 0; j < 11; ++j) {
+    const int64_t e = kRow[j] * n + i;
+    adam_one(g[j], m1[j], m2[j], p[j], lr[kArr[j]], a.b1, a.b2, a.eps, a.c1, a.c2);
+    __builtin_nontemporal_store(m1[j], a.m1[kArr[j]] + e);
+    __builtin_nontemporal_store(m2[j], a.m2[kArr[j]] + e);
+    __builtin_nontemporal_store(p[j], a.p[kArr[j]] + e);
+  }
+  if (a.rate) a.rate[i] = rate * a.decay;
+}
+
 // The SH part of the projection adjoint, a pass of its own so that the SH
 // coefficients and their gradients (96 registers at degree 3) do not share
 // a lane with the geometry adjoint: per Gaussian and view, from the clamped
@@ -648,64 +736,12 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
 // view-direction part of the mean gradient (the view direction carries no
 // pose gradient, section 4.3).  Runs after k_project_bwd_views on the same
 // views.
-__device__ __forceinline__ void adam_elem(const AdamArgs &a, int plane, int64_t e, float g, float p, float lr) {
-  float m1 = __builtin_nontemporal_load(a.m1[plane] + e), m2 = __builtin_nontemporal_load(a.m2[plane] + e);
-  adam_one(g, m1, m2, p, lr, a.b1, a.b2, a.eps, a.c1, a.c2);
-  __builtin_nontemporal_store(m1, a.m1[plane] + e);
-  __builtin_nontemporal_store(m2, a.m2[plane] + e);
-  __builtin_nontemporal_store(p, a.p[plane] + e);
-}
-
-// Adam on Gaussian i (visible).  The gradient of each plane is the value the
-// store form leaves there: the geometry pass's stored sum, plus this pass's
-// view-direction part for the means; for the SH planes this pass's sum
-// (first batch of views) or the earlier batches' sum plus it.  The rate is
-// read before the step and decayed after it, as gs_lr_decay after
-// gs_adam_step.
-template <int DEG>
-__device__ __forceinline__ void adam_gaussian(const MultiArgs &m, int64_t i, const float mu[3], const float sh[],
-                                              const float gm[3], const float gsh[], bool any) {
-  constexpr int NB = GParams<DEG>::NB;
-  const AdamArgs &a = m.opt;
-  const int64_t n = m.n;
-  const float rate = a.rate ? a.rate[i] : 1.f;
-  const auto lr_of = [&](int group) { return a.rate ? a.lr[group] * rate : a.lr[group]; };
-  {
-    const float lr = lr_of(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float g = m.gm[k * n + i];
-      if (DEG > 0 && any) g += gm[k];
-      adam_elem(a, 0, k * n + i, g, mu[k], lr);
-    }
-  }
-  {
-    const float lr = lr_of(1);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) adam_elem(a, 1, k * n + i, m.gl[k * n + i], m.log_scales[k * n + i], lr);
-  }
-  {
-    const float lr = lr_of(2);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) adam_elem(a, 2, k * n + i, m.gq[k * n + i], m.quats[k * n + i], lr);
-  }
-  adam_elem(a, 3, i, m.go[i], m.opac[i], lr_of(3));
-  const float lr_dc = lr_of(4), lr_rest = lr_of(5);
-#pragma unroll
-  for (int k = 0; k < NB * 3; ++k) {
-    const int64_t e = (int64_t)k * n + i;
-    const float g = m.store ? gsh[k] : (any ? m.gsh[e] + gsh[k] : m.gsh[e]);
-    const float p = DEG > 0 ? sh[k] : m.sh[e];
-    adam_elem(a, 4, e, g, p, k < 3 ? lr_dc : lr_rest);
-  }
-  if (a.rate) a.rate[i] = rate * a.decay;
-}
-
+//
 // ADAM: the last pass of a window whose step follows at once -- instead of
 // storing the gradients it applies the sparse Adam step (adam_gaussian) to
 // the Gaussians in visible, which this launch's geometry pass wrote.
 template <int DEG, bool ADAM>
-__global__ __launch_bounds__(kBlock) void k_project_bwd_sh(MultiArgs m) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_project_bwd_sh(MultiArgs m) {
   constexpr int NB = GParams<DEG>::NB;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= m.n) return;
