@@ -314,7 +314,10 @@ gs_status gs_project_views(int32_t n_views, const gs_view *views, const gs_raste
 /* The compositing adjoint of one view only: writes, for every (Gaussian,
  * tile) pair of the view's lists, its 2D gradient record (dL/d mean x, y,
  * conic A, B, C, opacity, colour r, g, b, depth, 0, 0) into pair_grad
- * [n_instances][12] at the pair's emission slot; arguments as gs_render_bwd. */
+ * [n_instances][12] at the pair's emission slot; arguments as gs_render_bwd.
+ * The colour entries are taken through the clamp of the colour at 0 (the
+ * colour is max(SH value, 0)): 0 for a channel whose projected colour is
+ * not above 0, so the projection adjoint needs no colour record. */
 gs_status gs_render_bwd_pairs(const gs_camera *cam, const gs_raster_params *rp, const gs_projected *proj,
                               const uint32_t *values, const uint32_t *slots, const uint32_t *ranges,
                               int64_t n_instances, const float *image, const float *depth, const float *final_t,

@@ -362,26 +362,26 @@ struct GAcc {
 
 // Adjoint of Gaussian i in one view where it is visible, in FP32 (the
 // forward decided visibility; the adjoint only chains gradients), from the
-// summed 2D gradients g0..g2 and the view's colour record rgbz (its clamps).
+// summed 2D gradients g0..g2 (whose colour terms are already 0 for a channel
+// the projection clamped at 0).
 // Adds the geometry and opacity gradients to acc, writes this Gaussian's
 // pose terms into pose[12] (dL/dR row-major, dL/dt) and its clamped colour
 // gradient into gc[3], which the SH pass chains to the SH coefficients and
 // the view direction.
 template <int DEG>
 __device__ __forceinline__ void backward_view(const MultiArgs &m, const ViewArgs &v, int64_t i, const float4 &g0,
-                                              const float4 &g1, const float4 &g2, const float4 &rgbz,
-                                              const GParams<DEG> &P, GAcc &acc, float pose[12],
-                                              float gc[3]) {
+                                              const float4 &g1, const float4 &g2, const GParams<DEG> &P, GAcc &acc,
+                                              float pose[12], float gc[3]) {
   Geo<float> f;
   geometry<float, DEG>(m, v, P, f);
   const float mu[3] = {P.mu[0], P.mu[1], P.mu[2]};
   // g0 = (d mean x, d mean y, dA, dB), g1 = (dC, d opacity, d r, d g), g2 = (d b, d z, -, -):
   // the sums of the Gaussian's per-pair 2D gradients
 
-  // colour: a channel whose colour was clamped at 0 passes no gradient
-  gc[0] = rgbz.x > 0.f ? g1.z : 0.f;
-  gc[1] = rgbz.y > 0.f ? g1.w : 0.f;
-  gc[2] = rgbz.z > 0.f ? g2.x : 0.f;
+  // colour: the pair gradients carry 0 for a channel the projection clamped at 0
+  gc[0] = g1.z;
+  gc[1] = g1.w;
+  gc[2] = g2.x;
 
   // opacity o = sigmoid(logit) ofac rho (ofac = 1 without the 3D filter, rho = 1
   // without the screen-space filter)
@@ -562,8 +562,8 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
   __shared__ float4 stage[kBlock / 64][3][64];
   __shared__ float tb[12][kBlock];
   const int t = threadIdx.x, wv = t >> 6;
-  // each view's first slot and tile count are loaded one view ahead, and its
-  // colour record before the pair sums, so their latency overlaps work
+  // each view's first slot and tile count are loaded one view ahead, so their
+  // latency overlaps work
   uint32_t fs_next = valid && m.nv > 0 ? m.v[0].first_slot[i] : 0xffffffffu;
   int t_next = valid && m.nv > 0 ? m.v[0].tiles[i] : 0;
   bool seen = false;  // some view's tile count is positive (the sparse step's set)
@@ -580,12 +580,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
       fs_next = valid ? m.v[vi + 1].first_slot[i] : 0xffffffffu;
       t_next = valid ? m.v[vi + 1].tiles[i] : 0;
     }
-    const float4 rgbz = nt > 0 ? *(const float4 *)(v.rec + i * GS_REC_FLOATS + 8) : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 g0, g1, g2;
     pair_sums(v.pair_grad, fs, nt, stage[wv], g0, g1, g2);
     float gc[3] = {0.f, 0.f, 0.f};
     if (nt > 0) {
-      backward_view<DEG>(m, v, i, g0, g1, g2, rgbz, P, acc, term, gc);
+      backward_view<DEG>(m, v, i, g0, g1, g2, P, acc, term, gc);
       any = true;
     }
     if (valid) {

@@ -654,17 +654,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DEPTH ? 3 :
     //   d mean = -(A sum gs dx + B sum gs dy, B sum gs dx + C sum gs dy)
     //   d (A, B, C) = -(sum gs dx^2 / 2, sum gs dx dy, sum gs dy^2 / 2)
     //   d o = sum gs / o   (d alpha / d o = alpha / o)
+    //   d colour = sum w G_c for a channel above 0; 0 for one the projection clamped at 0
+    //   (the colour is max(SH value, 0): such a channel passes nothing to the SH terms)
     if (t < kBwdBatch && base + t < stop) {
       float v[10];
 #pragma unroll
       for (int q = 0; q < 10; ++q)
         v[q] = q < NQ ? (sAcc[0][q][t] + sAcc[1][q][t]) + (sAcc[2][q][t] + sAcc[3][q][t]) : 0.f;
       const float4 A = S.a[t], Bb = S.b[t];
+      const float2 Cc = S.c[t];
       float4 *dst = (float4 *)(bi.pair_grad + (size_t)my_slot * 12);
       dst[0] = make_float4(-kLn2 * (2.0f * A.z * v[1] + A.w * v[2]), -kLn2 * (A.w * v[1] + 2.0f * Bb.x * v[2]),
                            -0.5f * v[3], -v[4]);
-      dst[1] = make_float4(-0.5f * v[5], v[0] * exp2_fast(-Bb.y), v[6], v[7]);
-      dst[2] = make_float4(v[8], v[9], 0.f, 0.f);
+      dst[1] = make_float4(-0.5f * v[5], v[0] * exp2_fast(-Bb.y), Bb.w > 0.f ? v[6] : 0.f, Cc.x > 0.f ? v[7] : 0.f);
+      dst[2] = make_float4(Cc.y > 0.f ? v[8] : 0.f, v[9], 0.f, 0.f);
     }
     if (t < kBwdBatch) {  // clear column t of the four accumulators for the next batch
 #pragma unroll
