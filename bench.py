@@ -155,6 +155,7 @@ def run_large_scene(args):
     win = ls.window(cfg.frames - 1)
     W, H = cfg.width, cfg.height
     inst, sup, comp, vis = [], [], [], []
+    seen = torch.zeros(ls.pool.n, dtype=torch.bool, device="cuda")  # the sparse step's set over the window
     for i, fi in enumerate(win):
         cam = ls.cams[fi]
         pr = gsmi.project(cam, ls.pool.g, ls.params)
@@ -165,8 +166,9 @@ def run_large_scene(args):
         sup.append(int(st[2]))
         comp.append(int(st[3]))
         vis.append(int((pr.tiles_touched > 0).sum()))
+        seen |= pr.tiles_touched > 0
     per_view = {"instances": float(np.mean(inst)), "support": float(np.mean(sup)), "composited": float(np.mean(comp)),
-                "visible": float(np.mean(vis))}
+                "visible": float(np.mean(vis)), "sparse": int(seen.sum())}
     ms_iter = rep["total_s"] * 1e3 / (cfg.frames * cfg.iters)
     roof = step_roofline(ls.pool.n, len(win), W * H, per_view, cfg.iters, 0, cfg.sh_degree, ms_iter * cfg.iters)
     alg_bytes = sum(k["bytes"] for k in roof["per_kernel"].values()) / cfg.iters
