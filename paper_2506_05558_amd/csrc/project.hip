@@ -4,13 +4,16 @@
 // One lane per Gaussian and up to eight views per launch; parameters are
 // read once as SoA planes (every load of a wave is one contiguous 256-byte
 // segment per plane) and held in registers across the views, each view's
-// pose is a uniform 48-byte read.  Geometry runs in FP64: on gfx950 the FP64 vector rate
-// equals the unpacked FP32 rate, so the extra precision costs nothing in a
-// kernel bounded by HBM traffic (236 B in + 72 B out per SH-degree-3
-// Gaussian).  The adjoint runs in FP32 (hardware exp, rcp, rsqrt) with the
-// SH terms streamed one coefficient at a time, which keeps its register
-// footprint and with it occupancy up; the camera-pose sum over all Gaussians
-// is reduced in FP64.
+// pose is a uniform 48-byte read.  Geometry runs in FP64: the render record
+// needs a sub-1e-6-pixel mean and the support radii and tile counts must
+// agree with an FP64 reference exactly.  On gfx950 FP64 vector FMAs issue at
+// half the non-packed FP32 rate, and with the SH coefficients held as
+// doubles across the views (two waves per SIMD) the 8-view projection is
+// bound by FP64 issue and latency more than by its HBM traffic (236 B in
+// per SH-degree-3 Gaussian, 76 B out per view).  The adjoint runs in FP32
+// (hardware exp, rcp, rsqrt) with the SH terms streamed one coefficient at a
+// time, which keeps its register footprint and with it occupancy up; the
+// camera-pose sum over all Gaussians is reduced in FP64.
 #include "common.h"
 
 namespace gsmi {
