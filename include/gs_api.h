@@ -135,6 +135,14 @@ typedef struct {
   float *rec;             /* [n][GS_REC_FLOATS] render records (layout above) */
   int32_t *radius;        /* [2][n] integer half-widths (rx, ry) of the support rect, rx = 0: culled */
   int32_t *tiles_touched; /* [n] number of 16x16 tiles the support square meets */
+  uint32_t *bin;          /* [n][4] or NULL: the binning's inputs, written by the projection
+                             where tiles_touched > 0 (elsewhere left as they were): the bits
+                             of the depth rec[11], the tile rect as tx0 | ty0 << 16 and
+                             tx1 | ty1 << 16 (inclusive, the tiles counted in
+                             tiles_touched), 0.  gs_bin_sort(_async) read them when bin is
+                             not NULL instead of the records' lines (one 16-byte read per
+                             visible Gaussian instead of a 64-byte line and the radii);
+                             the lists are the same either way. */
 } gs_projected;           /* HOST struct of DEVICE pointers */
 
 /* Fills *p with the constants above (0.3, 0.99, 1/255, 1e-4, 1.3, 0). */

@@ -384,22 +384,35 @@ constexpr uint32_t kNoSlot = 0xffffffffu;
 // the pair emission -- the tile rect packed as (tx0 | ty0 << 16,
 // tx1 | ty1 << 16) and the first slot -- and the first slot itself.  A
 // Gaussian whose slots do not all fit (an asynchronous call short of
-// capacity) gets no first slot, so its adjoint reads no pair.
+// capacity) gets no first slot, so its adjoint reads no pair.  With bin
+// (the projection's binning inputs) the depth and the rect come from one
+// 16-byte read; otherwise from the record's line and the radii.
 __global__ void k_compact(const int32_t *tiles, const uint64_t *pos, const float *rec, const int32_t *radius,
-                          int64_t n, int W, int H, uint32_t capacity, uint32_t *keys, uint32_t *vals, uint4 *rect,
-                          uint32_t *first_slot) {
+                          const uint4 *bin, int64_t n, int W, int H, uint32_t capacity, uint32_t *keys,
+                          uint32_t *vals, uint4 *rect, uint32_t *first_slot) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || tiles[i] <= 0) return;
   const uint64_t ps = pos[i];
   const uint32_t p = (uint32_t)ps;
-  const float4 r0 = *(const float4 *)(rec + i * GS_REC_FLOATS);
-  keys[p] = __float_as_uint(rec[i * GS_REC_FLOATS + 11]);  // depth > 0: bits order like values
+  uint32_t key, rx, ry;
+  if (bin) {
+    const uint4 b = bin[i];
+    key = b.x;
+    rx = b.y;
+    ry = b.z;
+  } else {
+    const float4 r0 = *(const float4 *)(rec + i * GS_REC_FLOATS);
+    key = __float_as_uint(rec[i * GS_REC_FLOATS + 11]);
+    int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
+    tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[i], radius[n + i], W, H, tx0, ty0, tx1, ty1);
+    rx = (uint32_t)tx0 | (uint32_t)ty0 << 16;
+    ry = (uint32_t)tx1 | (uint32_t)ty1 << 16;
+  }
+  keys[p] = key;  // depth > 0: bits order like values
   vals[p] = (uint32_t)i;
-  int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1;
-  tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), radius[i], radius[n + i], W, H, tx0, ty0, tx1, ty1);
   const uint32_t s0 = (uint32_t)(ps >> 32);
-  rect[i] = make_uint4((uint32_t)tx0 | (uint32_t)ty0 << 16, (uint32_t)tx1 | (uint32_t)ty1 << 16, s0, 0u);
-  const uint32_t npairs = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  rect[i] = make_uint4(rx, ry, s0, 0u);
+  const uint32_t npairs = ((ry & 0xffffu) - (rx & 0xffffu) + 1u) * ((ry >> 16) - (rx >> 16) + 1u);
   first_slot[i] = (uint64_t)s0 + npairs <= capacity ? s0 : kNoSlot;
 }
 
@@ -672,6 +685,7 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
   GS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "%s: n out of range", fn);
   GS_REQUIRE(capacity >= 0 && capacity < (int64_t(1) << 32) - 1, "%s: capacity out of range", fn);
   if (n > 0) GS_REQUIRE(proj->rec && proj->radius && proj->tiles_touched, "%s: NULL projection plane", fn);
+  GS_REQUIRE(((uintptr_t)proj->bin & 15u) == 0, "%s: bin must be 16-byte aligned", fn);
   if (capacity > 0) GS_REQUIRE(tile_ids && values && slots, "%s: NULL list output", fn);
   if (n > 0) GS_REQUIRE(first_slot, "%s: NULL first_slot", fn);
   size_t need = 0;
@@ -696,8 +710,8 @@ static gs_status bin_sort_impl(const gs_camera *cam, const gs_projected *proj, i
     if ((st = scan_exclusive_t<uint64_t>(TilesLoad{proj->tiles_touched}, L.pos64, n, L.total64, L.scan_ws, s)) !=
         GS_OK)
       return st;
-    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, proj->tiles_touched, L.pos64, proj->rec, proj->radius, n, W, H,
-              (uint32_t)capacity, L.kA, L.vA, L.rect, first_slot);
+    GS_LAUNCH("bin_compact", k_compact, grid1(n), 256, 0, s, proj->tiles_touched, L.pos64, proj->rec, proj->radius,
+              (const uint4 *)proj->bin, n, W, H, (uint32_t)capacity, L.kA, L.vA, L.rect, first_slot);
     // 2. stable sort by depth (31 significant bits of a positive float)
     int shifts[8], widths[8];
     const int np = plan_passes(31, shifts, widths);

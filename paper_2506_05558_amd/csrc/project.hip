@@ -88,6 +88,7 @@ struct ViewArgs {
   int W, H;
   float *rec;
   int32_t *radius, *tiles;     // radius: [2][n] (rx, ry)
+  uint32_t *bin;               // [n][4] binning inputs of visible Gaussians, or NULL
   const float *pair_grad;      // [M][12] 2D gradients per (Gaussian, tile) pair (first 10 used)
   const uint32_t *first_slot;  // first pair slot of each visible Gaussian
   double *d_pose, *d_twist;    // pose-gradient outputs (accumulated), may be NULL
@@ -335,8 +336,12 @@ __device__ __forceinline__ void project_one(const MultiArgs &m, const ViewArgs &
     r2 = make_float4((float)fmax(val[0], 0.0), (float)fmax(val[1], 0.0), (float)fmax(val[2], 0.0), (float)f.p[2]);
     r3 = make_float4((float)hx, (float)hy, 0.f, 0.f);
     int tx0, ty0, tx1, ty1;
-    if (tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), rx, ry, v.W, v.H, tx0, ty0, tx1, ty1))
+    if (tile_rect(__fadd_rn(r0.x, r0.z), __fadd_rn(r0.y, r0.w), rx, ry, v.W, v.H, tx0, ty0, tx1, ty1)) {
       tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+      if (v.bin)
+        *(uint4 *)(v.bin + 4 * i) = make_uint4(__float_as_uint(r2.w), (uint32_t)tx0 | (uint32_t)ty0 << 16,
+                                               (uint32_t)tx1 | (uint32_t)ty1 << 16, 0u);
+    }
   }
   float4 *dst = (float4 *)(v.rec + i * GS_REC_FLOATS);
   dst[0] = r0;
@@ -924,6 +929,7 @@ ViewArgs view_args(const gs_camera *cam, const gs_projected *proj) {
   v.rec = proj ? proj->rec : nullptr;
   v.radius = proj ? proj->radius : nullptr;
   v.tiles = proj ? proj->tiles_touched : nullptr;
+  v.bin = proj ? proj->bin : nullptr;
   v.pair_grad = nullptr;
   v.first_slot = nullptr;
   v.d_pose = v.d_twist = nullptr;
@@ -994,6 +1000,7 @@ gs_status gs_project(const gs_camera *cam, const gs_raster_params *rp, const gs_
   GS_REQUIRE(out, "gs_project: output struct is NULL");
   if (g->n == 0) return GS_OK;
   GS_REQUIRE(out->rec && out->radius && out->tiles_touched, "gs_project: NULL output plane");
+  GS_REQUIRE(((uintptr_t)out->bin & 15u) == 0, "gs_project: bin must be 16-byte aligned");
   if (finite_checks_on()) {
     if ((st = check_finite(cam->pose, 12, "gs_project", "pose", (hipStream_t)stream)) != GS_OK) return st;
     if ((st = check_finite_gaussians(g, "gs_project", "gaussians", (hipStream_t)stream)) != GS_OK) return st;
@@ -1015,6 +1022,8 @@ gs_status gs_project_views(int32_t n_views, const gs_view *views, const gs_raste
     if (g->n > 0)
       GS_REQUIRE(views[v].proj.rec && views[v].proj.radius && views[v].proj.tiles_touched,
                  "gs_project_views: view %d has a NULL output plane", v);
+    GS_REQUIRE(((uintptr_t)views[v].proj.bin & 15u) == 0, "gs_project_views: view %d: bin must be 16-byte aligned",
+               v);
   }
   if (g->n == 0) return GS_OK;
   if (finite_checks_on()) {

@@ -54,7 +54,7 @@ class _Gauss(C.Structure):
 
 
 class _Proj(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles_touched", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles_touched", C.c_void_p), ("bin", C.c_void_p)]
 
 
 class _View(C.Structure):
@@ -286,9 +286,10 @@ class Projected:
     rec: torch.Tensor  # (N, 16) render records
     radius: torch.Tensor  # (2, N) int32 half-widths (rx, ry) of the support rect
     tiles_touched: torch.Tensor  # (N,) int32
+    bin: Optional[torch.Tensor] = None  # (N, 4) int32: the binning's inputs (depth bits, tile rect), or None
 
     def c(self):
-        return _Proj(self.rec.data_ptr(), self.radius.data_ptr(), self.tiles_touched.data_ptr())
+        return _Proj(self.rec.data_ptr(), self.radius.data_ptr(), self.tiles_touched.data_ptr(), _ptr(self.bin))
 
 
 def default_params() -> Params:
@@ -297,10 +298,13 @@ def default_params() -> Params:
     return Params(p.eps2d, p.alpha_max, p.alpha_min, p.t_min, p.guard, p.mip_filter)
 
 
-def alloc_projected(n: int, device="cuda") -> Projected:
+def alloc_projected(n: int, device="cuda", bin: bool = True) -> Projected:
+    """Output planes of a projection; with bin, also the binning's inputs
+    (16 B per Gaussian), which spare the binning a read of the records."""
     return Projected(torch.empty((n, REC_FLOATS), dtype=torch.float32, device=device),
                      torch.empty((2, n), dtype=torch.int32, device=device),
-                     torch.empty(n, dtype=torch.int32, device=device))
+                     torch.empty(n, dtype=torch.int32, device=device),
+                     torch.empty((n, 4), dtype=torch.int32, device=device) if bin else None)
 
 
 def project(cam: Camera, g: Gaussians, params: Params = Params(), out: Optional[Projected] = None) -> Projected:

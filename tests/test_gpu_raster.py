@@ -287,6 +287,51 @@ def test_capacity_growth_gives_same_lists():
     assert torch.equal(b1.values[:M], b2.values[:M]) and torch.equal(b1.ranges, b2.ranges)
 
 
+@pytest.mark.parametrize("asynchronous", [False, True])
+def test_binning_record_gives_same_lists(asynchronous):
+    """The projection's optional binning inputs (gs_projected.bin) leave its
+    other outputs as they are, hold the depth bits and the tile rect the
+    binning derives from the records, and give the same lists bit for bit;
+    a window view at 640x400 with a tenth of the Gaussians behind the
+    camera, synchronous and asynchronous sorts."""
+    gs = gc.gpu()
+    views = synth.trajectory(12, 1, 640, 400)
+    scene = synth.window_scene(12, views, 20_000, 3)
+    scene.means[2, : scene.n // 10] -= 1e3
+    g = gc.gpu_gauss(scene)
+    cam = gc.gpu_camera(views[0])
+    with_bin = gs.project(cam, g, out=gs.alloc_projected(g.n, bin=True))
+    without = gs.project(cam, g, out=gs.alloc_projected(g.n, bin=False))
+    for a, b in ((with_bin.rec, without.rec), (with_bin.radius, without.radius),
+                 (with_bin.tiles_touched, without.tiles_touched)):
+        assert torch.equal(a, b)
+    vis = with_bin.tiles_touched > 0
+    assert 0 < int(vis.sum()) < g.n
+    binrec = with_bin.bin[vis].cpu().numpy().view(np.uint32)
+    assert np.array_equal(binrec[:, 0], with_bin.rec[vis, 11].cpu().numpy().view(np.uint32))
+    tx0, ty0 = binrec[:, 1] & 0xFFFF, binrec[:, 1] >> 16
+    tx1, ty1 = binrec[:, 2] & 0xFFFF, binrec[:, 2] >> 16
+    counts = (tx1.astype(np.int64) - tx0 + 1) * (ty1.astype(np.int64) - ty0 + 1)
+    assert np.array_equal(counts, with_bin.tiles_touched[vis].cpu().numpy())
+    outs = []
+    for proj in (with_bin, without):
+        fs = torch.full((g.n,), -7, dtype=torch.int32, device="cuda")
+        if asynchronous:
+            cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+            b = gs.BinSorter(capacity=16 * g.n).sort_async(cam, proj, cnt, first_slot=fs)
+            torch.cuda.synchronize()
+            M = int(cnt[0])
+            assert M <= 16 * g.n
+        else:
+            b = gs.BinSorter(0)(cam, proj, first_slot=fs)
+            M = b.n_instances
+        outs.append((M, b.tile_ids[:M].clone(), b.values[:M].clone(), b.slots[:M].clone(), b.ranges.clone(),
+                     fs[vis].clone()))
+    assert outs[0][0] == outs[1][0] > 0
+    for a, b in zip(outs[0][1:], outs[1][1:]):
+        assert torch.equal(a, b)
+
+
 def _autograd_vs_oracle(name, view, scene, seed, crop=None, params=None, bg=(0.0, 0.0, 0.0), sorter=None):
     """gsmi.rasterize (the torch.autograd.Function) against the FP64 oracle:
     the loss is sum(W_img image) + sum(W_depth depth) + sum(W_alpha alpha)
