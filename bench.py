@@ -529,12 +529,12 @@ def main():
             return dict(bound="alu", achieved=a, peak=PEAK_VALU_TOPS, unit="Tlane-op/s", frac=a / PEAK_VALU_TOPS,
                         traffic=None)
         # one launch of each covers the 8 views: parameters read once (236 B), per view a
-        # 76 B record + half-widths + tile count written; the adjoint reads parameters and per
+        # 76 B record + half-widths + tile count and the 16 B binning inputs written; the adjoint reads parameters and per
         # view 8 B (tile count, first slot) + 48 B per pair, writes the 4 B
         # visible flag, and for each Gaussian of the sparse set reads both moments and writes
         # parameters and moments (5 x 236 B) and its rate (4 + 4 B)
         per_launch_bytes = {
-            "project": n * (236 + N_VIEWS * 76),
+            "project": n * (236 + N_VIEWS * (76 + 16)),
             "project_bwd": n * (236 + 4 + N_VIEWS * 8) + N_VIEWS * M * 48 + n_sparse * (5 * 236 + 8),
         }.get(name)
         if per_launch_bytes is None:
