@@ -232,3 +232,39 @@ def test_anchor_blend_weight_equals_the_oracle(lib):
     assert L.gs_anchor_blend_weight(1.0, 2.0, 0.5, C.byref(w)) == 1    # overlap not below 0.5
     assert L.gs_scale_opacity(1, 10, 1.5, 1, None) == 1                # w > 1
     assert L.gs_anchor_sizes(1, 1, 10, None, 1.0, 1.0, None, 1, None) == 1  # no pose
+
+
+def test_adjoint_adam_validation(lib):
+    """gs_project_bwd_views_adam rejects bad settings on the host, before
+    anything is launched, and the projection rejects a misaligned binning
+    plane (no GPU needed: every call below fails its checks)."""
+    from paper_2506_05558_amd import gsmi as g
+    L = g._lib
+    L.gs_last_error.restype = C.c_char_p
+    fake = [16 * (k + 1) for k in range(5)]  # non-NULL planes: validation fails before they are used
+    gau = g._Gauss(10, 0, *fake, None)
+    m1 = g._Gauss(10, 0, *fake, None)
+    m2 = g._Gauss(10, 0, *fake, None)
+    short = g._Gauss(9, 0, *fake, None)
+    prm = g._Params(0.3, 0.99, 1 / 255, 1e-4, 1.3, 0)
+    ok = dict(lr_means=1e-3, lr_log_scales=1e-3, lr_quats=1e-3, lr_opacity=1e-2, lr_sh_dc=1e-3, lr_sh_rest=1e-4,
+              beta1=0.9, beta2=0.999, eps=1e-15, step=1, lr_decay=0.99)
+
+    def call(opt, gm=gau, a=m1, b=m2, visible=64):
+        o = None if opt is None else C.byref(g._AdamGroups(**opt))
+        return L.gs_project_bwd_views_adam(0, None, C.byref(prm), C.byref(gm), C.byref(a), C.byref(b), None, o,
+                                           C.byref(gau), None, 0, visible, None)
+
+    assert call(None) == g.GS_ERR_INVALID_ARG and b"optimiser" in L.gs_last_error()
+    assert call(dict(ok, step=0)) == g.GS_ERR_INVALID_ARG and b"step" in L.gs_last_error()
+    assert call(dict(ok, beta1=1.0)) == g.GS_ERR_INVALID_ARG
+    assert call(dict(ok, eps=-1.0)) == g.GS_ERR_INVALID_ARG
+    assert call(dict(ok, lr_decay=0.0)) == g.GS_ERR_INVALID_ARG and b"lr_decay" in L.gs_last_error()
+    assert call(dict(ok, lr_decay=1.5)) == g.GS_ERR_INVALID_ARG
+    assert call(ok, a=short) == g.GS_ERR_INVALID_ARG and b"moment" in L.gs_last_error()
+    assert call(ok, visible=None) == g.GS_ERR_INVALID_ARG and b"visible" in L.gs_last_error()
+    # the binning plane of a projection must be 16-byte aligned
+    cam = g._Camera(10, 10, 1.0, 1.0, 0.0, 0.0, 0.2, (C.c_float * 3)(0, 0, 0), 16)
+    prj = g._Proj(16, 32, 48, 8)
+    assert L.gs_project(C.byref(cam), C.byref(prm), C.byref(gau), C.byref(prj), None) == g.GS_ERR_INVALID_ARG
+    assert b"16-byte" in L.gs_last_error()
