@@ -359,6 +359,25 @@ __global__ __launch_bounds__(kBlock) void k_project_views(MultiArgs m) {
   if (i >= m.n) return;
   GParams<DEG> P;
   load_params<DEG>(m, i, P);
+  // the filters only scale the opacity down (prod s0 / s <= 1, rho <= 1): a
+  // Gaussian whose sigmoid opacity is already below alpha_min is culled in
+  // every view, with the outputs the full test would give -- the per-view
+  // FP64 geometry is skipped (freed pool slots hold such logits)
+  if (1.0 / (1.0 + exp(-(double)P.logit)) < (double)m.alpha_min) {
+    for (int v = 0; v < m.nv; ++v) {
+      const ViewArgs &w = m.v[v];
+      float4 *dst = (float4 *)(w.rec + i * GS_REC_FLOATS);
+      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+      dst[0] = z;
+      dst[1] = z;
+      dst[2] = z;
+      dst[3] = z;
+      w.radius[i] = 0;
+      w.radius[m.n + i] = 0;
+      w.tiles[i] = 0;
+    }
+    return;
+  }
   for (int v = 0; v < m.nv; ++v) project_one<DEG>(m, m.v[v], i, P);
 }
 
@@ -752,6 +771,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   constexpr int NB = GParams<DEG>::NB;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= m.n) return;
+  // the step leaves a Gaussian outside the visible set as it is, and nothing
+  // else reads its gradients: skip it before its loads
+  if (ADAM && !m.visible[i]) return;
   const int64_t n = m.n;
   float mu[3], sh[NB * 3], gsh[NB * 3], gm[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -804,7 +826,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
   }
   if (ADAM) {
-    if (m.visible[i]) adam_gaussian<DEG>(m, i, mu, sh, gm, gsh, any);
+    adam_gaussian<DEG>(m, i, mu, sh, gm, gsh, any);
     return;
   }
   if (!any && !m.store) return;
