@@ -332,6 +332,27 @@ def test_binning_record_gives_same_lists(asynchronous):
         assert torch.equal(a, b)
 
 
+def test_binning_record_multi_view_equals_single_view():
+    """The binning inputs of a 3-view projection launch equal those of three
+    single-view projections bit for bit where tiles_touched > 0 (elsewhere
+    they are left as they were)."""
+    gs = gc.gpu()
+    views = synth.trajectory(14, 3, 320, 240)
+    scene = synth.window_scene(14, views, 6000, 3)
+    g = gc.gpu_gauss(scene)
+    params = gs.Params(eps2d=0.1, mip_filter=1)
+    vs = [gs.View(gc.gpu_camera(v), gs.alloc_projected(g.n)) for v in views]
+    for vw in vs:
+        vw.proj.bin.fill_(-1)
+    gs.project_views(vs, g, params)
+    for vw in vs:
+        single = gs.project(vw.cam, g, params)
+        vis = single.tiles_touched > 0
+        assert torch.equal(single.tiles_touched, vw.proj.tiles_touched) and int(vis.sum()) > 0
+        assert torch.equal(single.bin[vis], vw.proj.bin[vis])
+        assert bool((vw.proj.bin[~vis] == -1).all())
+
+
 def _autograd_vs_oracle(name, view, scene, seed, crop=None, params=None, bg=(0.0, 0.0, 0.0), sorter=None):
     """gsmi.rasterize (the torch.autograd.Function) against the FP64 oracle:
     the loss is sum(W_img image) + sum(W_depth depth) + sum(W_alpha alpha)
