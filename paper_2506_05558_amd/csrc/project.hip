@@ -645,6 +645,9 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd_views(MultiArgs m) {
     else if (seen) m.visible[i] = 1;
   }
   if (!valid || (!any && !m.store)) return;
+  // with the Adam step in this launch's last pass, a Gaussian no view saw is
+  // left as it is and nothing reads its gradients: no zeros are stored
+  if (m.adam && !seen) return;
   const int64_t n = m.n;
   if (m.store) {  // zero where no view saw the Gaussian
 #pragma unroll
